@@ -1,0 +1,230 @@
+/*
+ * otfs.h -- C ABI of libotfs: LMMSE equalisation of Zak-OTFS frames by conjugate gradient
+ * with the structured-sparse delay-Doppler channel applied on the fly, on one MI355X.
+ *
+ * The operation (paper Sec. III-B, Eq. eq_lin_sys and Eq. lmmse; Sec. IV-C, Algorithm 1):
+ * for every frame, given the received DD frame y (M*N complex values), the P dominant
+ * paths of the effective channel (Eq. heff_model) and the noise variance lam, compute
+ *     x_hat = (H^H H + lam I)^{-1} H^H y
+ * by conjugate gradient from x = 0, where H is the MN x MN DD channel matrix of Eq. Hdd.
+ * H is never formed: each iteration applies H and H^H through the structured-sparse
+ * gather of Eqs. sparse_mvm / sparse_herm_mvm, with the column map of Eq. map_chMatDD_col,
+ * the inverse map of Eq. herm_mapping and the twisted phase of Sec. IV-B ("Phase
+ * correction and coefficient synthesis").
+ *
+ * Conventions shared by every entry point:
+ *  - Frame layout: complex64 interleaved (re, im) -- the layout of torch.complex64 -- in
+ *    vector order q = l*M + k: delay bin k in [0, M) fastest, Doppler bin l in [0, N)
+ *    (Sec. IV-B indexes rows this way).  A batch is the concatenation of its frames in
+ *    descriptor order; total_elems = sum of M_f * N_f.
+ *  - Paths: signed bin shifts, |delay| < M, |doppler| < N, i.e. (k_p - K0, l_p - L0) with the
+ *    pilot reference already subtracted.  Paths of one frame may repeat a bin.
+ *  - Ownership: the caller owns every device buffer (inputs, outputs, workspace, server
+ *    pool).  The library never calls hipMalloc or hipFree.  All device work is enqueued
+ *    on the caller's stream (a hipStream_t passed as void*, NULL = default stream) and is
+ *    asynchronous; the caller keeps buffers alive until that stream completes.
+ *  - Errors: every function returns an otfs_status; no C++ exception crosses the ABI.
+ *    Argument errors are found on the host before anything is enqueued and return
+ *    OTFS_E_INVAL; otfs_last_error() then holds a readable message (per thread).
+ *    Numerical trouble in one frame never fails a batch: it is reported in that frame's
+ *    otfs_frame_stats.status.  A HIP runtime error returns OTFS_E_DEVICE.
+ *  - Thread safety: distinct plans / servers may be used from distinct threads.  One
+ *    plan must not be used by two threads at once.
+ */
+#ifndef OTFS_H_
+#define OTFS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OTFS_OK = 0,
+  OTFS_E_INVAL = 1,        /* bad argument (detected on the host, nothing enqueued)        */
+  OTFS_E_NOMEM = 2,        /* host allocation failed, or a caller buffer is too small       */
+  OTFS_E_DEVICE = 3,       /* HIP runtime error                                             */
+  OTFS_E_BUDGET = 4,       /* a single frame can never fit the server's memory budget       */
+  OTFS_E_AGAIN = 5,        /* otfs_poll: the frame is not finished yet                      */
+  OTFS_E_NOTFOUND = 6,     /* unknown ticket                                                */
+  OTFS_E_UNSUPPORTED = 7,  /* a valid request this build does not handle                    */
+  OTFS_E_STATE = 8         /* call out of order (e.g. plan used before otfs_plan_bind)     */
+} otfs_status;
+
+/* Text of the last non-OK status returned on the calling thread ("" if none). */
+const char* otfs_last_error(void);
+
+/* ------------------------------------------------------------------------------------ */
+/* Frames, options, statistics                                                           */
+/* ------------------------------------------------------------------------------------ */
+
+/* One frame: DD grid M x N and its dominant paths (Eq. heff_model; the threshold set of
+ * Eq. heff_thres with gains h_p = h_eff[k_p, l_p]).  Host pointers, read during the call
+ * that receives the descriptor and not kept. */
+typedef struct {
+  int32_t M, N;             /* delay bins >= 1, Doppler bins >= 1, M*N <= 2^28             */
+  int32_t P;                /* number of paths, 1 <= P <= 64                                */
+  const float* h;           /* 2*P floats: complex gain h_p as (re, im)                      */
+  const int32_t* delay;     /* P signed delay shifts tau_p,   |tau_p| < M                   */
+  const int32_t* doppler;   /* P signed Doppler shifts nu_p,  |nu_p|  < N                   */
+  float noise_var;          /* lam = sigma^2 >= 0: R_n = lam I (Sec. IV-C, Algorithm 1)      */
+  int32_t qam;              /* square QAM size for hard decisions (4,16,64,256) or 0 = none  */
+} otfs_frame_desc;
+
+/* Option flags. */
+enum {
+  OTFS_D_STORED_BF16 = 1u << 0,  /* store D_{p,q} (Eq. D_definition) as bf16 (re, im) pairs
+                                    in the workspace (the SS table of Eq. ds_repr) instead of
+                                    synthesising it on the fly                               */
+  OTFS_Y_BF16 = 1u << 1,         /* y_dev holds 2*total_elems bf16 values (re, im) instead of
+                                    complex64                                                */
+  OTFS_USE_GRAPH = 1u << 2,      /* otfs_lmmse_cg replays a captured hipGraph of its launch
+                                    sequence (re-captured when buffers or stream change);
+                                    needs a created stream, not the NULL stream             */
+  OTFS_TIME_KERNEL = 1u << 3     /* bracket the fused CG kernel with hipEvents on the caller's
+                                    stream; read with otfs_plan_kernel_ms                    */
+};
+
+/* CG options (Algorithm 1 with a per-frame stop test added in front of the direction
+ * update: stop when sqrt(||c_xi||^2 / ||c_0||^2) <= rel_tol, or when xi = max_iters). */
+typedef struct {
+  int32_t max_iters;        /* >= 1; Algorithm 1 fixes 10                                   */
+  float rel_tol;            /* >= 0; 0 runs exactly max_iters iterations                    */
+  int32_t refresh_every;    /* k >= 0: every k iterations replace the recursive residual by
+                               c = H^H (y - H x) - lam x computed in FP64; 0 = never         */
+  uint32_t flags;           /* OTFS_* flags above                                           */
+} otfs_cg_opts;
+
+enum {
+  OTFS_FRAME_RUNNING = 0,
+  OTFS_FRAME_CONVERGED = 1,   /* relative residual <= rel_tol (or H^H y = 0)                */
+  OTFS_FRAME_CAPPED = 2,      /* max_iters reached                                          */
+  OTFS_FRAME_NONFINITE = 3,   /* a NaN/Inf appeared; x_hat holds the last finite iterate    */
+  OTFS_FRAME_BREAKDOWN = 4,   /* Re(p^H a_p) <= 0; x_hat holds the last iterate             */
+  OTFS_FRAME_TIMEOUT = 5      /* an in-kernel wait exceeded its limit (should not happen)    */
+};
+
+/* Per-frame result, written to device memory by the solver (16 bytes). */
+typedef struct {
+  int32_t iters;            /* number of x updates performed                                */
+  float rel_res;            /* sqrt(||c||^2 / ||c_0||^2) at the last iteration              */
+  int32_t status;           /* OTFS_FRAME_*                                                  */
+  int32_t tiles;            /* workgroups that cooperated on the frame                      */
+} otfs_frame_stats;
+
+/* ------------------------------------------------------------------------------------ */
+/* Batch plan                                                                            */
+/* ------------------------------------------------------------------------------------ */
+typedef struct otfs_plan otfs_plan_t;
+
+/* Validate a batch of frames and precompute, on the host, everything the kernels need:
+ * ragged offsets, per-path delay phase ramps R_p[k] = h_p e^{j 2 pi nu_p (k - tau_p)/(MN)}
+ * and the wrap factors e^{j 2 pi l / N} (the twisted phase of Sec. IV-B reduced exactly,
+ * in integer arithmetic, before one FP64 sincos and a rounding to FP32), and the tiling
+ * of frames into workgroups.  No device work.  nframes >= 0; frames may be NULL when
+ * nframes == 0.  opts may be NULL (max_iters 50, rel_tol 1e-6, no refresh, no flags).
+ * On success *out owns a new plan (free with otfs_plan_free). */
+otfs_status otfs_plan(const otfs_frame_desc* frames, int32_t nframes, const otfs_cg_opts* opts,
+                      otfs_plan_t** out);
+
+/* Device workspace the plan needs (bytes, 256-byte aligned start required) and the batch
+ * length in complex elements.  Either output pointer may be NULL. */
+otfs_status otfs_plan_workspace_bytes(const otfs_plan_t* plan, size_t* bytes,
+                                      int64_t* total_elems);
+
+/* Attach caller-owned device memory of at least otfs_plan_workspace_bytes() bytes and
+ * upload the plan's tables with copies enqueued on `stream` (and, with
+ * OTFS_D_STORED_BF16, build D on the device).  Selects the device that is current on
+ * the calling thread.  May be called again with another workspace. */
+otfs_status otfs_plan_bind(otfs_plan_t* plan, void* workspace_dev, size_t workspace_bytes,
+                           void* stream);
+
+otfs_status otfs_plan_free(otfs_plan_t* plan);
+
+/* Frames, elements and the launch shape chosen for the fused kernel. */
+typedef struct {
+  int32_t nframes;
+  int64_t total_elems;
+  int32_t grid;             /* workgroups of the fused CG launch                            */
+  int32_t block;            /* threads per workgroup                                        */
+  int32_t max_paths;        /* largest P in the batch                                       */
+  int32_t tile_elems;       /* target elements per workgroup tile                           */
+} otfs_plan_info_t;
+otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
+
+/* Change the tiling (target elements per workgroup tile, >= 1, or 0 for the built-in
+ * rule) and the workgroup cap of the fused kernel (0 = occupancy limit).  Takes effect at
+ * the next otfs_plan_bind.  Used by the autotuner. */
+otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elems, int32_t max_grid);
+
+/* ------------------------------------------------------------------------------------ */
+/* Operator applications (Eq. sparse_mvm and Eq. sparse_herm_mvm), every frame of the   */
+/* bound batch in one launch.  x_dev / y_dev: total_elems complex64 each, distinct.       */
+/* ------------------------------------------------------------------------------------ */
+otfs_status otfs_apply_H(const otfs_plan_t* plan, const void* x_dev, void* y_dev, void* stream);
+otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y_dev, void* x_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* LMMSE by conjugate gradient (Algorithm 1), all frames of the bound batch.              */
+/* ------------------------------------------------------------------------------------ */
+/* Fused form: one persistent launch runs every frame's whole iteration loop; frames are
+ * split into row tiles, the workgroups of one frame meet at per-frame barriers, and each
+ * frame stops on its own.  y_dev: total_elems complex64 (bf16 pairs with OTFS_Y_BF16);
+ * xhat_dev: total_elems complex64 output; sym_dev: total_elems uint8 hard decisions
+ * i_I * sqrt(Q) + i_Q (Eq. demod; nullable; frames with qam = 0 are left untouched);
+ * stats_dev: nframes otfs_frame_stats (nullable). */
+otfs_status otfs_lmmse_cg(otfs_plan_t* plan, const void* y_dev, void* xhat_dev, uint8_t* sym_dev,
+                          otfs_frame_stats* stats_dev, void* stream);
+
+/* Plain form of the same computation: one frame at a time, five unfused kernel launches
+ * per iteration (H, H^H + lam + dot, update + norm, direction), scalars kept on the
+ * device, the same stop rule.  The baseline the fused form is measured against. */
+otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y_dev, void* xhat_dev,
+                                uint8_t* sym_dev, otfs_frame_stats* stats_dev, void* stream);
+
+/* Duration in milliseconds of the fused CG kernel of the last otfs_lmmse_cg call that ran
+ * with OTFS_TIME_KERNEL (waits for its end event). */
+otfs_status otfs_plan_kernel_ms(otfs_plan_t* plan, float* ms);
+
+/* ------------------------------------------------------------------------------------ */
+/* Serving: continuous batching of frames that arrive over time.                          */
+/* ------------------------------------------------------------------------------------ */
+typedef struct otfs_server otfs_server_t;
+
+/* Start a server on `device`.  pool_dev / pool_bytes: caller-owned device memory that
+ * bounds the CG state of admitted frames (the HBM admission budget).  A scheduler thread
+ * admits queued frames while their state fits the pool, runs steps of `step_iters` CG
+ * iterations over all admitted frames in one fused launch, and retires frames as they
+ * finish; frames that arrive meanwhile join at the next step.  opts as for otfs_plan
+ * (NULL = defaults). */
+otfs_status otfs_server_create(int device, void* pool_dev, size_t pool_bytes,
+                               const otfs_cg_opts* opts, int32_t step_iters,
+                               otfs_server_t** out);
+
+/* Queue one frame; y_host (M*N complex64, host memory) is copied before returning. */
+otfs_status otfs_submit(otfs_server_t* srv, const otfs_frame_desc* frame, const void* y_host,
+                        uint64_t* ticket);
+
+/* OTFS_E_AGAIN until the frame is done; then copies x_hat (M*N complex64), decisions
+ * (M*N uint8, nullable) and stats (nullable) to host memory, returns the latency from
+ * submit to completion in nanoseconds (nullable) and forgets the ticket. */
+otfs_status otfs_poll(otfs_server_t* srv, uint64_t ticket, void* xhat_host, uint8_t* sym_host,
+                      otfs_frame_stats* stats, uint64_t* latency_ns);
+
+typedef struct {
+  uint64_t submitted, completed, steps;
+  uint64_t queued, active;          /* frames waiting for admission / holding pool memory */
+  uint64_t pool_bytes_in_use, pool_bytes_peak;
+} otfs_server_stats_t;
+otfs_status otfs_server_stats(otfs_server_t* srv, otfs_server_stats_t* out);
+
+/* Stop the scheduler (frames still queued or running are dropped) and free host state. */
+otfs_status otfs_server_free(otfs_server_t* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OTFS_H_ */

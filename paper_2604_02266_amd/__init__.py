@@ -1,0 +1,316 @@
+"""Python binding of libotfs: LMMSE-CG equalisation of Zak-OTFS frames on MI355X.
+
+Argument marshalling only.  Every step of the computation runs in the HIP kernels of
+libotfs.so (built in-tree for gfx950); PyTorch provides device memory and the stream.  If
+the library is missing, every entry point raises: there is no CPU fallback.
+
+Layout: a batch is one complex64 vector holding the frames back to back, each in the
+order q = l*M + k (delay fastest).  Frames are described by objects with the attributes
+M, N, tau, nu, h, lam and qam (workloads.FrameSpec is one).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libotfs.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "otfs.h")
+
+# status codes and flags (include/otfs.h)
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_BUDGET, E_AGAIN, E_NOTFOUND, E_UNSUPPORTED, E_STATE = range(9)
+D_STORED_BF16 = 1 << 0
+Y_BF16 = 1 << 1
+USE_GRAPH = 1 << 2
+TIME_KERNEL = 1 << 3
+FRAME_RUNNING, FRAME_CONVERGED, FRAME_CAPPED, FRAME_NONFINITE, FRAME_BREAKDOWN, FRAME_TIMEOUT = range(6)
+
+
+class OtfsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libotfs status {status}: {msg}")
+        self.status = status
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("h", ctypes.POINTER(ctypes.c_float)),
+                ("delay", ctypes.POINTER(ctypes.c_int32)),
+                ("doppler", ctypes.POINTER(ctypes.c_int32)),
+                ("noise_var", ctypes.c_float), ("qam", ctypes.c_int32)]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("rel_tol", ctypes.c_float),
+                ("refresh_every", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class FrameStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("rel_res", ctypes.c_float),
+                ("status", ctypes.c_int32), ("tiles", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nframes", ctypes.c_int32), ("total_elems", ctypes.c_int64),
+                ("grid", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("max_paths", ctypes.c_int32), ("tile_elems", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("active", ctypes.c_uint64), ("pool_bytes_in_use", ctypes.c_uint64),
+                ("pool_bytes_peak", ctypes.c_uint64)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def header_functions() -> List[str]:
+    """Names of the functions include/otfs.h declares."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(otfs_[A-Za-z_0-9]+)\s*\(", txt)))
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first "
+                           "(there is no fallback implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    sig = {
+        "otfs_last_error": (ctypes.c_char_p, []),
+        "otfs_plan": (st, [ctypes.POINTER(FrameDesc), ctypes.c_int32, ctypes.POINTER(CgOpts),
+                           ctypes.POINTER(_vp)]),
+        "otfs_plan_workspace_bytes": (st, [_vp, ctypes.POINTER(ctypes.c_size_t),
+                                           ctypes.POINTER(ctypes.c_int64)]),
+        "otfs_plan_bind": (st, [_vp, _vp, ctypes.c_size_t, _vp]),
+        "otfs_plan_free": (st, [_vp]),
+        "otfs_plan_info": (st, [_vp, ctypes.POINTER(PlanInfo)]),
+        "otfs_plan_set_tiling": (st, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "otfs_apply_H": (st, [_vp, _vp, _vp, _vp]),
+        "otfs_apply_HH": (st, [_vp, _vp, _vp, _vp]),
+        "otfs_lmmse_cg": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "otfs_lmmse_cg_plain": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "otfs_plan_kernel_ms": (st, [_vp, ctypes.POINTER(ctypes.c_float)]),
+        "otfs_server_create": (st, [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(CgOpts),
+                                    ctypes.c_int32, ctypes.POINTER(_vp)]),
+        "otfs_submit": (st, [_vp, ctypes.POINTER(FrameDesc), _vp,
+                             ctypes.POINTER(ctypes.c_uint64)]),
+        "otfs_poll": (st, [_vp, ctypes.c_uint64, _vp, _vp, ctypes.POINTER(FrameStats),
+                           ctypes.POINTER(ctypes.c_uint64)]),
+        "otfs_server_stats": (st, [_vp, ctypes.POINTER(ServerStats)]),
+        "otfs_server_free": (st, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().otfs_last_error().decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise OtfsError(status, last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+class _Descs:
+    """ctypes frame descriptors plus the numpy arrays they point into."""
+
+    def __init__(self, frames: Sequence):
+        self.keep = []
+        self.arr = (FrameDesc * max(len(frames), 1))()
+        for i, f in enumerate(frames):
+            h = np.ascontiguousarray(np.stack([np.real(f.h), np.imag(f.h)], axis=1)
+                                     .astype(np.float32).reshape(-1))
+            tau = np.ascontiguousarray(np.asarray(f.tau, dtype=np.int32))
+            nu = np.ascontiguousarray(np.asarray(f.nu, dtype=np.int32))
+            self.keep += [h, tau, nu]
+            d = self.arr[i]
+            d.M, d.N, d.P = int(f.M), int(f.N), int(tau.shape[0])
+            d.h = h.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            d.delay = tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.doppler = nu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.noise_var = float(f.lam)
+            d.qam = int(getattr(f, "qam", 0) or 0)
+
+
+def make_opts(max_iters=50, rel_tol=1e-6, refresh_every=0, flags=0) -> CgOpts:
+    return CgOpts(int(max_iters), float(rel_tol), int(refresh_every), int(flags))
+
+
+class Plan:
+    """A bound batch of frames: otfs_plan + a torch-owned workspace + otfs_plan_bind."""
+
+    def __init__(self, frames: Sequence, max_iters: int = 50, rel_tol: float = 1e-6,
+                 refresh_every: int = 0, flags: int = 0, tile_elems: int = 0,
+                 max_grid: int = 0, bind: bool = True):
+        self._lib = lib()
+        self.frames = list(frames)
+        self.opts = make_opts(max_iters, rel_tol, refresh_every, flags)
+        descs = _Descs(self.frames)
+        h = _vp()
+        _check(self._lib.otfs_plan(descs.arr, len(self.frames), ctypes.byref(self.opts),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.ws = None
+        if tile_elems or max_grid:
+            _check(self._lib.otfs_plan_set_tiling(self._h, int(tile_elems), int(max_grid)))
+        if bind:
+            self.bind()
+
+    # ---- lifetime ----
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.otfs_plan_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- plan queries ----
+    def workspace_bytes(self):
+        nb = ctypes.c_size_t()
+        ne = ctypes.c_int64()
+        _check(self._lib.otfs_plan_workspace_bytes(self._h, ctypes.byref(nb), ctypes.byref(ne)))
+        return int(nb.value), int(ne.value)
+
+    @property
+    def total_elems(self) -> int:
+        return self.workspace_bytes()[1]
+
+    @property
+    def nframes(self) -> int:
+        return len(self.frames)
+
+    def info(self) -> PlanInfo:
+        inf = PlanInfo()
+        _check(self._lib.otfs_plan_info(self._h, ctypes.byref(inf)))
+        return inf
+
+    def set_tiling(self, tile_elems: int = 0, max_grid: int = 0, rebind: bool = True):
+        _check(self._lib.otfs_plan_set_tiling(self._h, int(tile_elems), int(max_grid)))
+        if rebind:
+            self.bind()
+
+    def bind(self, stream=None):
+        torch = _torch()
+        nbytes, _ = self.workspace_bytes()
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = raw.data_ptr()
+        pad = (-base) % 256
+        self.ws = raw
+        _check(self._lib.otfs_plan_bind(self._h, _vp(base + pad), nbytes,
+                                        _vp(_stream_ptr(stream))))
+
+    # ---- buffers ----
+    def _vec(self, t, name, dtype=None):
+        torch = _torch()
+        dtype = dtype or torch.complex64
+        n = self.total_elems
+        if t is None:
+            return torch.empty(n, dtype=dtype, device="cuda")
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: need a contiguous cuda {dtype} tensor of {n} elements")
+        return t
+
+    def _y(self, y):
+        torch = _torch()
+        if self.opts.flags & Y_BF16:
+            if (y.dtype != torch.bfloat16 or not y.is_cuda or not y.is_contiguous()
+                    or y.numel() != 2 * self.total_elems):
+                raise ValueError("y: with Y_BF16 need a contiguous cuda bfloat16 tensor of "
+                                 "2 * total_elems values (re, im)")
+            return y
+        return self._vec(y, "y")
+
+    def new_stats(self):
+        torch = _torch()
+        return torch.zeros((max(self.nframes, 1), 4), dtype=torch.int32, device="cuda")
+
+    # ---- operator ----
+    def apply_H(self, x, y=None, stream=None):
+        x = self._vec(x, "x")
+        y = self._vec(y, "y")
+        _check(self._lib.otfs_apply_H(self._h, _vp(_ptr(x)), _vp(_ptr(y)), _vp(_stream_ptr(stream))))
+        return y
+
+    def apply_HH(self, y, x=None, stream=None):
+        y = self._vec(y, "y")
+        x = self._vec(x, "x")
+        _check(self._lib.otfs_apply_HH(self._h, _vp(_ptr(y)), _vp(_ptr(x)), _vp(_stream_ptr(stream))))
+        return x
+
+    # ---- solver ----
+    def _solve(self, fn, y, xhat, sym, stats, stream):
+        torch = _torch()
+        y = self._y(y)
+        xhat = self._vec(xhat, "xhat")
+        if sym is not None:
+            sym = self._vec(sym, "sym", torch.uint8)
+        if stats is not None and (stats.dtype != torch.int32 or stats.numel() < 4 * self.nframes
+                                  or not stats.is_contiguous() or not stats.is_cuda):
+            raise ValueError("stats: need a contiguous cuda int32 tensor of shape (nframes, 4)")
+        _check(fn(self._h, _vp(_ptr(y)), _vp(_ptr(xhat)), _vp(_ptr(sym)), _vp(_ptr(stats)),
+                  _vp(_stream_ptr(stream))))
+        return xhat
+
+    def lmmse_cg(self, y, xhat=None, sym=None, stats=None, stream=None):
+        return self._solve(self._lib.otfs_lmmse_cg, y, xhat, sym, stats, stream)
+
+    def lmmse_cg_plain(self, y, xhat=None, sym=None, stats=None, stream=None):
+        return self._solve(self._lib.otfs_lmmse_cg_plain, y, xhat, sym, stats, stream)
+
+    def kernel_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(self._lib.otfs_plan_kernel_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
+
+
+def stats_numpy(stats) -> np.ndarray:
+    """(nframes, 4) int32 device tensor -> structured array (iters, rel_res, status, tiles)."""
+    a = stats.detach().cpu().numpy().astype(np.int32)
+    out = np.zeros(a.shape[0], dtype=[("iters", np.int32), ("rel_res", np.float32),
+                                      ("status", np.int32), ("tiles", np.int32)])
+    out["iters"] = a[:, 0]
+    out["rel_res"] = a[:, 1].view(np.float32)
+    out["status"] = a[:, 2]
+    out["tiles"] = a[:, 3]
+    return out
+
+
+def frame_offsets(frames: Sequence) -> np.ndarray:
+    sizes = np.array([int(f.M) * int(f.N) for f in frames], dtype=np.int64)
+    return np.concatenate([[0], np.cumsum(sizes)])

@@ -1,0 +1,114 @@
+// Internal declarations shared by the device code (kernels.hip) and the host library
+// (plan.cpp, server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "otfs.h"
+
+namespace otfs {
+
+constexpr int kBlock = 256;          // threads per workgroup of every kernel
+constexpr int kWaves = kBlock / 64;  // wave64
+
+// Per-frame CG scalars that persist between launches of the fused kernel (a serving step
+// ends in the middle of a frame's iteration loop and the next step resumes it).
+struct FrameState {
+  int32_t iter;      // iterations completed
+  int32_t status;    // OTFS_FRAME_*
+  int32_t pbuf;      // which direction buffer (p0 / p1) holds the current p
+  int32_t pending;   // 1: x += alpha p and p = c + beta p still to be applied
+  float cn;          // ||c||^2 of the current residual
+  float cn0;         // ||c_0||^2 = ||H^H y||^2
+  float alpha;       // step of the last iteration (pending x update)
+  float beta;        // cn_new / cn_old of the last iteration (pending direction update)
+  float rel;         // sqrt(cn / cn0)
+  int32_t init;      // 1 once b = H^H y has been formed
+  float cn_hist[2];  // plain form: ||c||^2 by iteration parity
+};
+
+// Everything a kernel needs to know about one frame.  Built on the host, uploaded once
+// per bind.  Vector pointers address device memory (the plan workspace or a server slot).
+struct FrameDev {
+  const void* y;          // received frame (complex64, or bf16 pairs with OTFS_Y_BF16)
+  float2* x;              // estimate
+  uint8_t* sym;           // hard decisions (nullable)
+  otfs_frame_stats* stats;// per-frame stats (nullable)
+  float2* c;              // residual
+  float2* p0;             // direction, double-buffered
+  float2* p1;
+  float2* t;              // H p
+  float2* a;              // H^H H p + lam p
+  double2* u;             // FP64 scratch of the residual refresh (nullable)
+  const float2* rtab;     // P x M: R_p[k] = h_p e^{j 2 pi nu_p (k - tau_p) / (MN)}
+  const float2* wtab;     // N: W[l] = e^{j 2 pi l / N}
+  const double2* rtab64;  // FP64 copies of the two tables for the refresh (nullable)
+  const double2* wtab64;
+  const int2* paths;      // P x (tau_p, nu_p)
+  const uint32_t* dtab;   // stored D_{p,q} as bf16 pairs, P x E (nullable)
+  float* part_pa;         // T partial sums of Re(p^H a)
+  float* part_cc;         // T partial sums of ||c||^2
+  double* part_d;         // T FP64 partial sums (refresh)
+  unsigned* bar;          // arrival counter of the per-frame barrier
+  FrameState* st;
+  int64_t off;            // element offset of the frame inside batch-wide buffers
+  int32_t M, N, P, T;     // grid, paths, workgroup tiles
+  float lam;
+  float qscale;           // sqrt(2 (Q - 1) / 3) rounded to FP32
+  int32_t qside;          // sqrt(Q), 0 = no decisions
+  int32_t flags;
+  int32_t max_iters;
+  float tol;
+  int32_t refresh_every;
+  int32_t index;          // frame index in its batch (stats slot)
+};
+
+// One workgroup's share of one frame: Doppler rows [l_begin, l_end), all delay columns.
+struct WorkItem {
+  int32_t frame;
+  int32_t tile;
+  int32_t l_begin;
+  int32_t l_end;
+};
+
+// Batch-wide buffers passed to a launch.  A null base means "use the per-frame pointer
+// in FrameDev" (server slots); otherwise the frame's data lives at base + off.
+struct Bases {
+  const void* y;
+  float2* x;
+  uint8_t* sym;
+  otfs_frame_stats* stats;
+};
+
+// ---- launchers (kernels.hip) -----------------------------------------------------------
+int pmax_bucket(int max_paths);   // 4, 8, 16, 32 or 64
+
+// One workgroup per item.  in/out are batch-wide complex64 buffers (frame at base + off).
+hipError_t launch_apply(bool adjoint, int pmax, const FrameDev* frames, const WorkItem* items,
+                        int nitems, const float2* in, float2* out, hipStream_t s);
+
+// Reset barrier counters and CG state of frames [0, nframes) and the abort word.
+hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_flag, hipStream_t s);
+
+// Fused persistent CG.  grid workgroups; workgroup w runs items sched[range[w].x ..
+// range[w].y) in order.  budget = iterations to run per frame in this launch.
+// abort_flag: one device word, zero before the launch; raised by a workgroup whose
+// per-frame barrier wait timed out so that every other wait ends at once.
+hipError_t launch_cg_fused(int pmax, const FrameDev* frames, const WorkItem* items,
+                           const int32_t* sched, const int2* ranges, int grid, int budget,
+                           Bases bases, hipStream_t s, unsigned* abort_flag);
+// Workgroups of the fused kernel that fit on one CU at once (occupancy).
+int fused_blocks_per_cu(int pmax);
+
+// Plain (unfused, one frame per launch sequence) form.
+hipError_t launch_plain_frame(int pmax, const FrameDev* frames_dev, int frame,
+                              const WorkItem* items_dev, int item_begin, int ntiles,
+                              int max_iters, Bases bases, hipStream_t s);
+
+// Build the stored bf16 D table of every frame.
+hipError_t launch_build_d(int pmax, const FrameDev* frames, const WorkItem* items, int nitems,
+                          hipStream_t s);
+
+}  // namespace otfs

@@ -1,0 +1,603 @@
+// Host side of libotfs: plan validation, coefficient tables, tiling and scheduling,
+// workspace layout, and the batch entry points of the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "otfs_internal.h"
+#include "plan_internal.h"
+
+namespace otfs {
+
+// ---------------------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+otfs_status fail(otfs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+otfs_status hip_fail(hipError_t e, const char* what) {
+  return fail(OTFS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------------------
+// validation and tables
+// ---------------------------------------------------------------------------------------
+otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out) {
+  otfs_cg_opts d{50, 1e-6f, 0, 0u};
+  if (o) d = *o;
+  if (d.max_iters < 1) return fail(OTFS_E_INVAL, "max_iters must be >= 1 (got %d)", d.max_iters);
+  if (!(d.rel_tol >= 0.f) || !std::isfinite(d.rel_tol))
+    return fail(OTFS_E_INVAL, "rel_tol must be finite and >= 0");
+  if (d.refresh_every < 0) return fail(OTFS_E_INVAL, "refresh_every must be >= 0");
+  const uint32_t known = OTFS_D_STORED_BF16 | OTFS_Y_BF16 | OTFS_USE_GRAPH | OTFS_TIME_KERNEL;
+  if (d.flags & ~known) return fail(OTFS_E_INVAL, "unknown flag bits 0x%x", d.flags & ~known);
+  *out = d;
+  return OTFS_OK;
+}
+
+otfs_status validate_frame(const otfs_frame_desc& f, int idx, HostFrame* out) {
+  if (f.M < 1 || f.N < 1)
+    return fail(OTFS_E_INVAL, "frame %d: M and N must be >= 1 (got %d x %d)", idx, f.M, f.N);
+  const int64_t E = (int64_t)f.M * f.N;
+  if (E > (int64_t(1) << 28))
+    return fail(OTFS_E_INVAL, "frame %d: M*N = %lld exceeds 2^28", idx, (long long)E);
+  if (f.P < 1 || f.P > kMaxPaths)
+    return fail(OTFS_E_INVAL, "frame %d: P must be in [1, %d] (got %d)", idx, kMaxPaths, f.P);
+  if (!f.h || !f.delay || !f.doppler)
+    return fail(OTFS_E_INVAL, "frame %d: h, delay and doppler must be non-null", idx);
+  if (!(f.noise_var >= 0.f) || !std::isfinite(f.noise_var))
+    return fail(OTFS_E_INVAL, "frame %d: noise_var must be finite and >= 0", idx);
+  if (!(f.qam == 0 || f.qam == 4 || f.qam == 16 || f.qam == 64 || f.qam == 256))
+    return fail(OTFS_E_INVAL, "frame %d: qam must be 0, 4, 16, 64 or 256 (got %d)", idx, f.qam);
+  HostFrame h;
+  h.M = f.M;
+  h.N = f.N;
+  h.P = f.P;
+  h.lam = f.noise_var;
+  h.qam = f.qam;
+  h.tau.resize(f.P);
+  h.nu.resize(f.P);
+  h.h.resize(f.P);
+  for (int p = 0; p < f.P; ++p) {
+    const int t = f.delay[p], v = f.doppler[p];
+    if (t <= -f.M || t >= f.M)
+      return fail(OTFS_E_INVAL, "frame %d path %d: need |delay| < M (delay %d, M %d)", idx, p, t, f.M);
+    if (v <= -f.N || v >= f.N)
+      return fail(OTFS_E_INVAL, "frame %d path %d: need |doppler| < N (doppler %d, N %d)", idx, p, v, f.N);
+    const float re = f.h[2 * p], im = f.h[2 * p + 1];
+    if (!std::isfinite(re) || !std::isfinite(im))
+      return fail(OTFS_E_INVAL, "frame %d path %d: gain is not finite", idx, p);
+    h.tau[p] = t;
+    h.nu[p] = v;
+    h.h[p] = {re, im};
+  }
+  *out = std::move(h);
+  return OTFS_OK;
+}
+
+// R_p[k] = h_p e^{j 2 pi nu_p (k - tau_p) / (MN)} for k in [0, M): the phase numerator is
+// reduced modulo MN in exact integer arithmetic before the angle is formed in FP64.
+void delay_ramp(const HostFrame& f, int p, std::vector<double2>& out) {
+  const int64_t MN = (int64_t)f.M * f.N;
+  const double hr = f.h[p].x, hi = f.h[p].y;
+  for (int k = 0; k < f.M; ++k) {
+    int64_t num = ((int64_t)f.nu[p] * (int64_t)(k - f.tau[p])) % MN;
+    if (num < 0) num += MN;
+    const double ang = 2.0 * M_PI * ((double)num / (double)MN);
+    const double c = std::cos(ang), s = std::sin(ang);
+    out.push_back(make_double2(hr * c - hi * s, hr * s + hi * c));
+  }
+}
+
+// W[l] = e^{j 2 pi l / N}
+void wrap_factors(const HostFrame& f, std::vector<double2>& out) {
+  for (int l = 0; l < f.N; ++l) {
+    const double ang = 2.0 * M_PI * ((double)l / (double)f.N);
+    out.push_back(make_double2(std::cos(ang), std::sin(ang)));
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// tiling: frame f is split into T_f bands of Doppler rows, one workgroup each
+// ---------------------------------------------------------------------------------------
+int default_tile_elems(int64_t total_elems, int cus) {
+  // aim at about four workgroups per CU for the whole batch
+  const int64_t target = std::max<int64_t>(1, (int64_t)cus * 4);
+  int64_t te = total_elems / target;
+  te = std::max<int64_t>(te, 2048);
+  te = std::min<int64_t>(te, 65536);
+  return (int)te;
+}
+
+void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vector<WorkItem>& items,
+                std::vector<int>& tile_base, std::vector<int>& tiles) {
+  items.clear();
+  tile_base.assign(frames.size(), 0);
+  tiles.assign(frames.size(), 0);
+  for (size_t f = 0; f < frames.size(); ++f) {
+    const HostFrame& fr = frames[f];
+    const int64_t E = (int64_t)fr.M * fr.N;
+    int64_t T = (E + tile_elems / 2) / tile_elems;
+    T = std::max<int64_t>(1, std::min<int64_t>(T, fr.N));
+    tile_base[f] = (int)items.size();
+    tiles[f] = (int)T;
+    for (int t = 0; t < T; ++t) {
+      WorkItem w;
+      w.frame = (int)f;
+      w.tile = t;
+      w.l_begin = (int)((int64_t)t * fr.N / T);
+      w.l_end = (int)((int64_t)(t + 1) * fr.N / T);
+      items.push_back(w);
+    }
+  }
+}
+
+// Persistent schedule.  If every tile gets its own workgroup, that is the schedule.
+// Otherwise frames are taken largest first and each frame's T_f tiles go to the T_f least
+// loaded workgroups (distinct ones).  Every workgroup runs its items in assignment order,
+// so the frame of lowest assignment index among those in progress always has all its
+// workgroups present: the per-frame barriers cannot deadlock while the whole grid is
+// resident.
+void make_schedule(const std::vector<HostFrame>& frames, const std::vector<WorkItem>& items,
+                   const std::vector<int>& tile_base, const std::vector<int>& tiles, int cap,
+                   std::vector<int32_t>& sched, std::vector<int2>& ranges, int* grid_out) {
+  const int nitems = (int)items.size();
+  sched.clear();
+  ranges.clear();
+  if (nitems == 0) {
+    *grid_out = 0;
+    return;
+  }
+  if (nitems <= cap) {
+    for (int i = 0; i < nitems; ++i) {
+      sched.push_back(i);
+      ranges.push_back(make_int2(i, i + 1));
+    }
+    *grid_out = nitems;
+    return;
+  }
+  const int grid = cap;
+  std::vector<int> order(frames.size());
+  std::iota(order.begin(), order.end(), 0);
+  auto work = [&](int f) {
+    const HostFrame& fr = frames[f];
+    return (double)fr.M * fr.N * (2.0 * fr.P + 6.0) / tiles[f];
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::vector<std::vector<int32_t>> lists(grid);
+  using Slot = std::pair<double, int>;   // (load, workgroup)
+  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> pq;
+  for (int w = 0; w < grid; ++w) pq.push({0.0, w});
+  std::vector<Slot> picked;
+  for (int f : order) {
+    const int T = tiles[f];
+    picked.clear();
+    double start = 0.0;
+    for (int t = 0; t < T; ++t) {
+      picked.push_back(pq.top());
+      pq.pop();
+      start = std::max(start, picked.back().first);
+    }
+    const double fin = start + work(f);
+    for (int t = 0; t < T; ++t) {
+      lists[picked[t].second].push_back(tile_base[f] + t);
+      pq.push({fin, picked[t].second});
+    }
+  }
+  for (int w = 0; w < grid; ++w) {
+    const int b = (int)sched.size();
+    sched.insert(sched.end(), lists[w].begin(), lists[w].end());
+    ranges.push_back(make_int2(b, (int)sched.size()));
+  }
+  *grid_out = grid;
+}
+
+// ---------------------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------------------
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+void compute_layout(otfs_plan_t* pl) {
+  Layout& L = pl->L;
+  const size_t nf = pl->frames.size();
+  size_t nitems = pl->items.size();
+  size_t rt = 0, wt = 0, np = 0, dt = 0;
+  for (auto& f : pl->frames) {
+    rt += (size_t)f.P * f.M;
+    wt += (size_t)f.N;
+    np += (size_t)f.P;
+    dt += (size_t)f.P * f.M * f.N;
+  }
+  const size_t E = (size_t)pl->total_elems;
+  const bool refresh = pl->opts.refresh_every > 0;
+  const bool stored = (pl->opts.flags & OTFS_D_STORED_BF16) != 0;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.frames = take(nf * sizeof(FrameDev));
+  L.items = take(nitems * sizeof(WorkItem));
+  L.sched = take(nitems * sizeof(int32_t));
+  L.ranges = take(nitems * sizeof(int2));
+  L.rtab = take(rt * sizeof(float2));
+  L.wtab = take(wt * sizeof(float2));
+  L.rtab64 = refresh ? take(rt * sizeof(double2)) : 0;
+  L.wtab64 = refresh ? take(wt * sizeof(double2)) : 0;
+  L.paths = take(np * sizeof(int2));
+  L.part_pa = take(nitems * sizeof(float));
+  L.part_cc = take(nitems * sizeof(float));
+  L.part_d = take(nitems * sizeof(double));
+  L.bar = take(nf * sizeof(unsigned));
+  L.st = take(nf * sizeof(FrameState));
+  L.abort = take(sizeof(unsigned));
+  L.c = take(E * sizeof(float2));
+  L.p0 = take(E * sizeof(float2));
+  L.p1 = take(E * sizeof(float2));
+  L.t = take(E * sizeof(float2));
+  L.a = take(E * sizeof(float2));
+  L.u = refresh ? take(E * sizeof(double2)) : 0;
+  L.dtab = stored ? take(dt * sizeof(uint32_t)) : 0;
+  L.total = std::max<size_t>(o, 256);
+}
+
+}  // namespace otfs
+
+using namespace otfs;
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+extern "C" const char* otfs_last_error(void) { return otfs::last_error(); }
+
+extern "C" otfs_status otfs_plan(const otfs_frame_desc* frames, int32_t nframes,
+                                 const otfs_cg_opts* opts, otfs_plan_t** out) {
+  if (!out) return fail(OTFS_E_INVAL, "out must be non-null");
+  *out = nullptr;
+  if (nframes < 0) return fail(OTFS_E_INVAL, "nframes must be >= 0");
+  if (nframes > 0 && !frames) return fail(OTFS_E_INVAL, "frames is null");
+  otfs_plan_t* pl = new (std::nothrow) otfs_plan_t();
+  if (!pl) return fail(OTFS_E_NOMEM, "out of host memory");
+  otfs_status st = validate_opts(opts, &pl->opts);
+  if (st != OTFS_OK) {
+    delete pl;
+    return st;
+  }
+  pl->frames.resize(nframes);
+  int64_t total = 0;
+  int maxp = 0;
+  for (int i = 0; i < nframes; ++i) {
+    st = validate_frame(frames[i], i, &pl->frames[i]);
+    if (st != OTFS_OK) {
+      delete pl;
+      return st;
+    }
+    pl->frames[i].off = total;
+    total += (int64_t)frames[i].M * frames[i].N;
+    maxp = std::max(maxp, frames[i].P);
+  }
+  pl->total_elems = total;
+  pl->max_paths = maxp;
+  pl->pmax = pmax_bucket(std::max(maxp, 1));
+  int cus = 256;
+  int dev = 0, ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 && hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  (void)hipGetLastError();
+  pl->cus = cus;
+  pl->tile_elems = default_tile_elems(total, cus);
+  make_tiles(pl->frames, pl->tile_elems, pl->items, pl->tile_base, pl->tiles);
+  compute_layout(pl);
+  *out = pl;
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_workspace_bytes(const otfs_plan_t* plan, size_t* bytes,
+                                                 int64_t* total_elems) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  if (bytes) *bytes = plan->L.total;
+  if (total_elems) *total_elems = plan->total_elems;
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info) {
+  if (!plan || !info) return fail(OTFS_E_INVAL, "plan and info must be non-null");
+  info->nframes = (int32_t)plan->frames.size();
+  info->total_elems = plan->total_elems;
+  info->grid = plan->grid;
+  info->block = kBlock;
+  info->max_paths = plan->max_paths;
+  info->tile_elems = plan->tile_elems;
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elems,
+                                            int32_t max_grid) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  if (tile_elems < 0 || max_grid < 0)
+    return fail(OTFS_E_INVAL, "tile_elems and max_grid must be >= 0");
+  plan->tile_elems = tile_elems > 0 ? tile_elems : default_tile_elems(plan->total_elems, plan->cus);
+  plan->max_grid_req = max_grid;
+  make_tiles(plan->frames, plan->tile_elems, plan->items, plan->tile_base, plan->tiles);
+  compute_layout(plan);
+  plan->bound = false;
+  plan->drop_graph();
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  if (!ws && plan->L.total > 0) return fail(OTFS_E_INVAL, "workspace is null");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
+    return fail(OTFS_E_INVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < plan->L.total)
+    return fail(OTFS_E_NOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, plan->L.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  plan->device = dev;
+  plan->drop_graph();
+
+  // schedule for the fused kernel (needs the occupancy of this device)
+  const int bpc = std::max(1, fused_blocks_per_cu(plan->pmax));
+  int cus = plan->cus;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    cus = v;
+  int cap = bpc * cus;
+  if (plan->max_grid_req > 0) cap = std::min(cap, plan->max_grid_req);
+  // a frame's tiles must run at the same time on distinct workgroups
+  int maxT = 1;
+  for (int t : plan->tiles) maxT = std::max(maxT, t);
+  if (maxT > cap)
+    return fail(OTFS_E_UNSUPPORTED, "a frame needs %d cooperating workgroups but only %d fit", maxT, cap);
+  make_schedule(plan->frames, plan->items, plan->tile_base, plan->tiles, cap, plan->sched,
+                plan->ranges, &plan->grid);
+
+  // host tables
+  const Layout& L = plan->L;
+  char* base = static_cast<char*>(ws);
+  std::vector<double2> r64, w64;
+  std::vector<int2> paths;
+  std::vector<FrameDev> fd(plan->frames.size());
+  size_t ro = 0, wo = 0, po = 0, dto = 0;
+  const bool refresh = plan->opts.refresh_every > 0;
+  const bool stored = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
+  for (size_t f = 0; f < plan->frames.size(); ++f) {
+    const HostFrame& fr = plan->frames[f];
+    FrameDev& d = fd[f];
+    std::memset(&d, 0, sizeof d);
+    for (int p = 0; p < fr.P; ++p) delay_ramp(fr, p, r64);
+    wrap_factors(fr, w64);
+    for (int p = 0; p < fr.P; ++p) paths.push_back(make_int2(fr.tau[p], fr.nu[p]));
+    const size_t E = (size_t)fr.M * fr.N;
+    const size_t eo = (size_t)fr.off;
+    d.c = reinterpret_cast<float2*>(base + L.c) + eo;
+    d.p0 = reinterpret_cast<float2*>(base + L.p0) + eo;
+    d.p1 = reinterpret_cast<float2*>(base + L.p1) + eo;
+    d.t = reinterpret_cast<float2*>(base + L.t) + eo;
+    d.a = reinterpret_cast<float2*>(base + L.a) + eo;
+    d.u = refresh ? reinterpret_cast<double2*>(base + L.u) + eo : nullptr;
+    d.rtab = reinterpret_cast<const float2*>(base + L.rtab) + ro;
+    d.wtab = reinterpret_cast<const float2*>(base + L.wtab) + wo;
+    d.rtab64 = refresh ? reinterpret_cast<const double2*>(base + L.rtab64) + ro : nullptr;
+    d.wtab64 = refresh ? reinterpret_cast<const double2*>(base + L.wtab64) + wo : nullptr;
+    d.paths = reinterpret_cast<const int2*>(base + L.paths) + po;
+    d.dtab = stored ? reinterpret_cast<const uint32_t*>(base + L.dtab) + dto : nullptr;
+    const int tb = plan->tile_base[f];
+    d.part_pa = reinterpret_cast<float*>(base + L.part_pa) + tb;
+    d.part_cc = reinterpret_cast<float*>(base + L.part_cc) + tb;
+    d.part_d = reinterpret_cast<double*>(base + L.part_d) + tb;
+    d.bar = reinterpret_cast<unsigned*>(base + L.bar) + f;
+    d.st = reinterpret_cast<FrameState*>(base + L.st) + f;
+    d.off = fr.off;
+    d.M = fr.M;
+    d.N = fr.N;
+    d.P = fr.P;
+    d.T = plan->tiles[f];
+    d.lam = fr.lam;
+    d.qside = fr.qam > 0 ? (int)std::lround(std::sqrt((double)fr.qam)) : 0;
+    d.qscale = fr.qam > 0 ? (float)std::sqrt(2.0 * (fr.qam - 1) / 3.0) : 0.f;
+    d.flags = (int32_t)plan->opts.flags;
+    d.max_iters = plan->opts.max_iters;
+    d.tol = plan->opts.rel_tol;
+    d.refresh_every = plan->opts.refresh_every;
+    d.index = (int32_t)f;
+    ro += (size_t)fr.P * fr.M;
+    wo += (size_t)fr.N;
+    po += (size_t)fr.P;
+    dto += (size_t)fr.P * E;
+  }
+  plan->h_rtab.resize(r64.size());
+  plan->h_wtab.resize(w64.size());
+  for (size_t i = 0; i < r64.size(); ++i) plan->h_rtab[i] = make_float2((float)r64[i].x, (float)r64[i].y);
+  for (size_t i = 0; i < w64.size(); ++i) plan->h_wtab[i] = make_float2((float)w64[i].x, (float)w64[i].y);
+  plan->h_rtab64 = refresh ? r64 : std::vector<double2>();
+  plan->h_wtab64 = refresh ? w64 : std::vector<double2>();
+  plan->h_paths = paths;
+  plan->h_frames = fd;
+
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  if ((e = up(L.frames, fd.data(), fd.size() * sizeof(FrameDev))) != hipSuccess ||
+      (e = up(L.items, plan->items.data(), plan->items.size() * sizeof(WorkItem))) != hipSuccess ||
+      (e = up(L.sched, plan->sched.data(), plan->sched.size() * sizeof(int32_t))) != hipSuccess ||
+      (e = up(L.ranges, plan->ranges.data(), plan->ranges.size() * sizeof(int2))) != hipSuccess ||
+      (e = up(L.rtab, plan->h_rtab.data(), plan->h_rtab.size() * sizeof(float2))) != hipSuccess ||
+      (e = up(L.wtab, plan->h_wtab.data(), plan->h_wtab.size() * sizeof(float2))) != hipSuccess ||
+      (e = up(L.paths, plan->h_paths.data(), plan->h_paths.size() * sizeof(int2))) != hipSuccess)
+    return hip_fail(e, "hipMemcpyAsync (plan tables)");
+  if (refresh) {
+    if ((e = up(L.rtab64, plan->h_rtab64.data(), plan->h_rtab64.size() * sizeof(double2))) != hipSuccess ||
+        (e = up(L.wtab64, plan->h_wtab64.data(), plan->h_wtab64.size() * sizeof(double2))) != hipSuccess)
+      return hip_fail(e, "hipMemcpyAsync (FP64 tables)");
+  }
+  plan->ws = ws;
+  plan->d_frames = reinterpret_cast<FrameDev*>(base + L.frames);
+  plan->d_items = reinterpret_cast<WorkItem*>(base + L.items);
+  plan->d_sched = reinterpret_cast<int32_t*>(base + L.sched);
+  plan->d_ranges = reinterpret_cast<int2*>(base + L.ranges);
+  plan->d_abort = reinterpret_cast<unsigned*>(base + L.abort);
+  if (stored) {
+    if ((e = launch_build_d(plan->pmax, plan->d_frames, plan->d_items, (int)plan->items.size(), s)) != hipSuccess)
+      return hip_fail(e, "build D");
+  }
+  // the host arrays above must outlive the copies
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize (bind)");
+  plan->bound = true;
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_free(otfs_plan_t* plan) {
+  if (!plan) return OTFS_OK;
+  plan->drop_graph();
+  if (plan->ev_begin) (void)hipEventDestroy(plan->ev_begin);
+  if (plan->ev_end) (void)hipEventDestroy(plan->ev_end);
+  delete plan;
+  return OTFS_OK;
+}
+
+static otfs_status check_bound(const otfs_plan_t* plan) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  if (!plan->bound) return fail(OTFS_E_STATE, "plan is not bound to a workspace (otfs_plan_bind)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+    return fail(OTFS_E_STATE, "current device %d differs from the bound device %d", dev, plan->device);
+  return OTFS_OK;
+}
+
+static otfs_status apply_common(const otfs_plan_t* plan, bool adj, const void* in, void* out,
+                                void* stream) {
+  otfs_status st = check_bound(plan);
+  if (st != OTFS_OK) return st;
+  if (plan->total_elems == 0) return OTFS_OK;
+  if (!in || !out) return fail(OTFS_E_INVAL, "input and output must be non-null");
+  if (in == out) return fail(OTFS_E_INVAL, "input and output must be distinct buffers");
+  hipError_t e = launch_apply(adj, plan->pmax, plan->d_frames, plan->d_items, (int)plan->items.size(),
+                              static_cast<const float2*>(in), static_cast<float2*>(out),
+                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, adj ? "apply H^H" : "apply H");
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_apply_H(const otfs_plan_t* plan, const void* x, void* y, void* stream) {
+  return apply_common(plan, false, x, y, stream);
+}
+extern "C" otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y, void* x, void* stream) {
+  return apply_common(plan, true, y, x, stream);
+}
+
+// the launch sequence of one fused solve: reset, persistent kernel (optionally timed)
+static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s, bool timed) {
+  hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort, s);
+  if (e != hipSuccess) return e;
+  if (timed && (e = hipEventRecord(plan->ev_begin, s)) != hipSuccess) return e;
+  e = launch_cg_fused(plan->pmax, plan->d_frames, plan->d_items, plan->d_sched, plan->d_ranges,
+                      plan->grid, plan->opts.max_iters, B, s, plan->d_abort);
+  if (e != hipSuccess) return e;
+  if (timed && (e = hipEventRecord(plan->ev_end, s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+extern "C" otfs_status otfs_lmmse_cg(otfs_plan_t* plan, const void* y, void* xhat, uint8_t* sym,
+                                     otfs_frame_stats* stats, void* stream) {
+  otfs_status st = check_bound(plan);
+  if (st != OTFS_OK) return st;
+  if (plan->frames.empty()) return OTFS_OK;
+  if (!y || !xhat) return fail(OTFS_E_INVAL, "y and xhat must be non-null");
+  if (y == xhat) return fail(OTFS_E_INVAL, "y and xhat must be distinct buffers");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Bases B{y, static_cast<float2*>(xhat), sym, stats};
+  const bool timed = (plan->opts.flags & OTFS_TIME_KERNEL) != 0;
+  hipError_t e;
+  if (timed && !plan->ev_begin) {
+    if ((e = hipEventCreate(&plan->ev_begin)) != hipSuccess || (e = hipEventCreate(&plan->ev_end)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+  }
+  if ((plan->opts.flags & OTFS_USE_GRAPH) && !timed) {
+    if (s == nullptr)
+      return fail(OTFS_E_INVAL, "OTFS_USE_GRAPH needs a created stream (the NULL stream cannot be captured)");
+    const GraphKey key{y, xhat, sym, stats, s};
+    if (!plan->gexec || !(plan->gkey == key)) {
+      plan->drop_graph();
+      if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+      hipError_t le = enqueue_fused(plan, B, s, false);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(s, &g);
+      if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "capture of the fused CG launch");
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        plan->gexec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+      plan->gkey = key;
+    }
+    if ((e = hipGraphLaunch(plan->gexec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return OTFS_OK;
+  }
+  if ((e = enqueue_fused(plan, B, s, timed)) != hipSuccess) return hip_fail(e, "fused CG launch");
+  plan->timed_pending = timed;
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y, void* xhat,
+                                           uint8_t* sym, otfs_frame_stats* stats, void* stream) {
+  otfs_status st = check_bound(plan);
+  if (st != OTFS_OK) return st;
+  if (plan->frames.empty()) return OTFS_OK;
+  if (!y || !xhat) return fail(OTFS_E_INVAL, "y and xhat must be non-null");
+  if (y == xhat) return fail(OTFS_E_INVAL, "y and xhat must be distinct buffers");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Bases B{y, static_cast<float2*>(xhat), sym, stats};
+  hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort, s);
+  if (e != hipSuccess) return hip_fail(e, "reset");
+  for (size_t f = 0; f < plan->frames.size(); ++f) {
+    e = launch_plain_frame(pmax_bucket(plan->frames[f].P), plan->d_frames, (int)f, plan->d_items,
+                           plan->tile_base[f], plan->tiles[f], plan->opts.max_iters, B, s);
+    if (e != hipSuccess) return hip_fail(e, "plain CG launch");
+  }
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_kernel_ms(otfs_plan_t* plan, float* ms) {
+  if (!plan || !ms) return fail(OTFS_E_INVAL, "plan and ms must be non-null");
+  if (!plan->timed_pending || !plan->ev_begin)
+    return fail(OTFS_E_STATE, "no timed otfs_lmmse_cg call (set OTFS_TIME_KERNEL)");
+  hipError_t e = hipEventSynchronize(plan->ev_end);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  if ((e = hipEventElapsedTime(ms, plan->ev_begin, plan->ev_end)) != hipSuccess)
+    return hip_fail(e, "hipEventElapsedTime");
+  return OTFS_OK;
+}

@@ -1,0 +1,97 @@
+// Host-side plan structures shared by plan.cpp and server.cpp.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "otfs_internal.h"
+
+namespace otfs {
+
+constexpr int kMaxPaths = 64;
+
+// A validated frame descriptor, owned by the host.
+struct HostFrame {
+  int M = 0, N = 0, P = 0;
+  float lam = 0.f;
+  int qam = 0;
+  std::vector<int> tau, nu;
+  std::vector<float2> h;
+  int64_t off = 0;   // element offset inside the batch
+};
+
+// Byte offsets of every region of a plan workspace.
+struct Layout {
+  size_t frames = 0, items = 0, sched = 0, ranges = 0;
+  size_t rtab = 0, wtab = 0, rtab64 = 0, wtab64 = 0, paths = 0;
+  size_t part_pa = 0, part_cc = 0, part_d = 0, bar = 0, st = 0, abort = 0;
+  size_t c = 0, p0 = 0, p1 = 0, t = 0, a = 0, u = 0, dtab = 0;
+  size_t total = 0;
+};
+
+struct GraphKey {
+  const void* y;
+  void* x;
+  void* sym;
+  void* stats;
+  hipStream_t s;
+  bool operator==(const GraphKey& o) const {
+    return y == o.y && x == o.x && sym == o.sym && stats == o.stats && s == o.s;
+  }
+};
+
+otfs_status fail(otfs_status st, const char* fmt, ...);
+otfs_status hip_fail(hipError_t e, const char* what);
+otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out);
+otfs_status validate_frame(const otfs_frame_desc& f, int idx, HostFrame* out);
+void delay_ramp(const HostFrame& f, int p, std::vector<double2>& out);
+void wrap_factors(const HostFrame& f, std::vector<double2>& out);
+int default_tile_elems(int64_t total_elems, int cus);
+void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vector<WorkItem>& items,
+                std::vector<int>& tile_base, std::vector<int>& tiles);
+void make_schedule(const std::vector<HostFrame>& frames, const std::vector<WorkItem>& items,
+                   const std::vector<int>& tile_base, const std::vector<int>& tiles, int cap,
+                   std::vector<int32_t>& sched, std::vector<int2>& ranges, int* grid_out);
+
+}  // namespace otfs
+
+struct otfs_plan {
+  std::vector<otfs::HostFrame> frames;
+  otfs_cg_opts opts{};
+  int64_t total_elems = 0;
+  int max_paths = 0, pmax = 4, cus = 256;
+  int tile_elems = 0, max_grid_req = 0;
+  // tiling (host) and schedule (chosen at bind)
+  std::vector<otfs::WorkItem> items;
+  std::vector<int> tile_base, tiles;
+  std::vector<int32_t> sched;
+  std::vector<int2> ranges;
+  int grid = 0;
+  otfs::Layout L;
+  // binding
+  bool bound = false;
+  int device = -1;
+  void* ws = nullptr;
+  otfs::FrameDev* d_frames = nullptr;
+  otfs::WorkItem* d_items = nullptr;
+  int32_t* d_sched = nullptr;
+  int2* d_ranges = nullptr;
+  unsigned* d_abort = nullptr;
+  // host copies of the uploaded tables (kept alive across the asynchronous copies)
+  std::vector<float2> h_rtab, h_wtab;
+  std::vector<double2> h_rtab64, h_wtab64;
+  std::vector<int2> h_paths;
+  std::vector<otfs::FrameDev> h_frames;
+  // kernel timing
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  bool timed_pending = false;
+  // captured launch sequence
+  hipGraphExec_t gexec = nullptr;
+  otfs::GraphKey gkey{};
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+};

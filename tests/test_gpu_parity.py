@@ -1,0 +1,301 @@
+"""GPU parity of libotfs against the FP64 oracle, through the C ABI.
+
+Inputs are seeded and synthetic; every received frame y is produced by the oracle
+(complex128, rounded once to complex64) and the GPU consumes exactly that y.  Operator
+applications are compared element by element; CG estimates per frame by NMSE <= 1e-5
+against the oracle's CG run under the identical stop rule; hard decisions bit-exactly
+(see helpers.check_decisions).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import SpecLike, check_decisions, oracle_batch, say, split, to_dev
+
+pytestmark = pytest.mark.gpu
+
+NMSE_TOL = 1e-5          # FP32 path vs FP64 oracle, per frame
+NMSE_TOL_BF16 = 1e-4     # y and D stored as bf16
+
+
+@pytest.fixture(scope="module")
+def otfs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_02266_amd as m
+    m.lib()
+    return m
+
+
+def _rand_c(rng, n):
+    return (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+
+
+# every wrap case of the operator: tau at 0 and M-1, negative tau, nu at +-(N-1),
+# M or N equal to one, sizes that are not powers of two, frames wider than a workgroup
+EDGE_FRAMES = [
+    (8, 4, [0, 7, -3, 2, 1, 0], [0, 3, -2, -3, 1, 2]),
+    (5, 3, [4, -4, 2], [2, -2, 1]),
+    (1, 4, [0, 0], [3, -3]),
+    (6, 1, [5, -5, 2], [0, 0, 0]),
+    (7, 5, [6, -6, 0, 3], [-4, 4, 0, -1]),
+    (64, 16, [0, 8, 63, -63], [0, -4, 15, -15]),
+    (100, 30, [0, 99, -50, 17], [29, -29, 3, 0]),
+    (300, 12, [299, -1, 150], [11, -11, 5]),
+    (256, 64, list(range(0, 16)), list(range(-8, 8))),
+    (1, 1, [0], [0]),
+]
+
+
+def _edge_specs(rng):
+    out = []
+    for M, N, tau, nu in EDGE_FRAMES:
+        h = _rand_c(rng, len(tau)).astype(np.complex128) / math.sqrt(len(tau))
+        out.append(SpecLike(M, N, tau, nu, h, lam=0.02, qam=16))
+    return out
+
+
+@pytest.mark.parametrize("tile_elems", [0, 64, 1024])
+def test_apply_parity_edge_batch(otfs, tile_elems):
+    rng = np.random.default_rng(7 + tile_elems)
+    specs = _edge_specs(rng)
+    say("apply parity", "tile_elems", tile_elems, [(s.M, s.N, s.P) for s in specs])
+    plan = otfs.Plan(specs, tile_elems=tile_elems)
+    E = plan.total_elems
+    x = _rand_c(rng, E)
+    y = _rand_c(rng, E)
+    yh = plan.apply_H(to_dev(x)).cpu().numpy()
+    xh = plan.apply_HH(to_dev(y)).cpu().numpy()
+    o = 0
+    for s in specs:
+        op = O.TwistedConvChannel(s.M, s.N, s.h, s.tau, s.nu)
+        sl = slice(o, o + s.E)
+        ref_f = op.apply(x[sl].astype(np.complex128))
+        ref_a = op.apply_adjoint(y[sl].astype(np.complex128))
+        scale = np.abs(s.h).sum()
+        assert np.abs(yh[sl] - ref_f).max() <= 1e-5 * scale * np.abs(x[sl]).max(), (s.M, s.N)
+        assert np.abs(xh[sl] - ref_a).max() <= 1e-5 * scale * np.abs(y[sl]).max(), (s.M, s.N)
+        o += s.E
+
+
+def _cg_check(plan_out, frames, ops, y, tol_nmse, form="fused"):
+    xg, symg, stg = plan_out
+    xs = split(xg, frames)
+    syms = split(symg, frames)
+    ys = split(y, frames)
+    amb_total = 0
+    for i, fr in enumerate(frames):
+        sp = fr.spec
+        xr, it_r, rel_r = O.cg_lmmse(ys[i], ops[i], sp.lam, sp.max_iters, sp.tol)
+        nm = O.nmse(xs[i], xr)
+        assert nm <= tol_nmse, f"{form} frame {i} ({sp.M}x{sp.N}, P={sp.P}): NMSE {nm:.3e}"
+        it_g = int(stg["iters"][i])
+        if rel_r > sp.tol * 1.5 and it_r == sp.max_iters:
+            assert it_g == it_r, (i, it_g, it_r)
+        else:
+            assert abs(it_g - it_r) <= 1, (i, it_g, it_r)
+        assert stg["status"][i] in (O_CONV, O_CAP)
+        amb_total += check_decisions(syms[i], xs[i], xr, sp.qam)
+    return amb_total
+
+
+O_CONV, O_CAP = 1, 2
+
+
+def _run(otfs, plan, y, form="fused"):
+    import torch
+    yd = to_dev(y)
+    sym = torch.zeros(plan.total_elems, dtype=torch.uint8, device="cuda")
+    stats = plan.new_stats()
+    fn = plan.lmmse_cg if form == "fused" else plan.lmmse_cg_plain
+    x = fn(yd, sym=sym, stats=stats)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), sym.cpu().numpy(), otfs.stats_numpy(stats)
+
+
+def _mixed_frames(seed, n, shapes, P_range, tau_max, nu_max, qams=(4, 16), snr=(10, 30),
+                  max_iters=50, tol=1e-6):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        M, N = shapes[i % len(shapes)]
+        P = int(rng.integers(P_range[0], P_range[1] + 1))
+        fr = W.small_frame(rng, M, N, P, (0, min(tau_max, M - 1)),
+                           (-min(nu_max, N - 1), min(nu_max, N - 1)),
+                           qam=int(qams[i % len(qams)]),
+                           snr_db=float(rng.uniform(*snr)), max_iters=max_iters, tol=tol)
+        out.append(fr)
+    return out
+
+
+def test_cg_single_64x16_config(otfs):
+    fr = W.draw_frame("single_64x16", 0)
+    frames = [fr]
+    ops, xs, y = oracle_batch(frames)
+    for form in ("fused", "plain"):
+        say("cg single_64x16", form)
+        plan = otfs.Plan([fr.spec], max_iters=30, rel_tol=1e-6)
+        _cg_check(_run(otfs, plan, y, form), frames, ops, y, NMSE_TOL, form)
+
+
+@pytest.mark.parametrize("tile_elems,max_grid", [(0, 0), (700, 0), (700, 8), (2048, 3)])
+def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid):
+    frames = _mixed_frames(11, 9, [(128, 32), (64, 16), (100, 30), (96, 8), (256, 16)],
+                           (1, 9), 12, 4)
+    ops, xs, y = oracle_batch(frames)
+    say("cg ragged", tile_elems, max_grid)
+    plan = otfs.Plan([f.spec for f in frames], tile_elems=tile_elems, max_grid=max_grid)
+    _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
+
+
+def test_cg_plain_matches_oracle_and_fused(otfs):
+    frames = _mixed_frames(12, 4, [(128, 32), (64, 16)], (2, 8), 8, 4)
+    ops, xs, y = oracle_batch(frames)
+    say("cg plain vs fused")
+    plan = otfs.Plan([f.spec for f in frames], tile_elems=1024)
+    xf, sf, stf = _run(otfs, plan, y, "fused")
+    xp, sp_, stp = _run(otfs, plan, y, "plain")
+    _cg_check((xp, sp_, stp), frames, ops, y, NMSE_TOL, "plain")
+    assert np.array_equal(stf["iters"], stp["iters"])
+    for a, b in zip(split(xf, frames), split(xp, frames)):
+        assert O.nmse(a, b) <= 1e-9
+
+
+def test_cg_fixed_iterations_and_first_step(otfs):
+    frames = _mixed_frames(13, 3, [(64, 16), (128, 32)], (3, 6), 8, 4, max_iters=1, tol=0.0)
+    ops, xs, y = oracle_batch(frames)
+    say("cg one iteration")
+    plan = otfs.Plan([f.spec for f in frames], max_iters=1, rel_tol=0.0)
+    x, sym, st = _run(otfs, plan, y)
+    assert np.all(st["iters"] == 1) and np.all(st["status"] == O_CAP)
+    for i, (fr, xg) in enumerate(zip(frames, split(x, frames))):
+        xr, _, _ = O.cg_lmmse(split(y, frames)[i], ops[i], fr.spec.lam, 1, 0.0)
+        assert O.nmse(xg, xr) <= 1e-10
+    frames10 = _mixed_frames(14, 3, [(64, 16)], (3, 6), 8, 4, max_iters=10, tol=0.0)
+    ops, xs, y = oracle_batch(frames10)
+    plan = otfs.Plan([f.spec for f in frames10], max_iters=10, rel_tol=0.0)
+    x, sym, st = _run(otfs, plan, y)
+    assert np.all(st["iters"] == 10)
+    _cg_check((x, sym, st), frames10, ops, y, NMSE_TOL)
+
+
+def test_cg_single_path_closed_form(otfs):
+    rng = np.random.default_rng(15)
+    M, N, h, lam = 64, 16, 0.6 + 0.9j, 0.05
+    s = SpecLike(M, N, [3], [-2], [h], lam=lam, qam=4)
+    y = _rand_c(rng, M * N)
+    say("cg P=1")
+    plan = otfs.Plan([s], max_iters=10, rel_tol=1e-5)
+    x, sym, st = _run(otfs, plan, y)
+    op = O.TwistedConvChannel(M, N, [h], [3], [-2])
+    ref = op.apply_adjoint(y.astype(np.complex128)) / (abs(h) ** 2 + lam)
+    assert st["iters"][0] == 1 and st["status"][0] == O_CONV
+    assert O.nmse(x, ref) <= 1e-12
+
+
+def test_cg_zero_and_nonfinite_frames_are_isolated(otfs):
+    frames = _mixed_frames(16, 4, [(128, 32), (64, 16)], (3, 6), 8, 4)
+    ops, xs, y = oracle_batch(frames)
+    offs = np.concatenate([[0], np.cumsum([f.spec.E for f in frames])])
+    say("cg isolation baseline")
+    plan = otfs.Plan([f.spec for f in frames], tile_elems=1024)
+    x0, s0, st0 = _run(otfs, plan, y)
+    y2 = y.copy()
+    y2[offs[1]:offs[2]] = 0                    # frame 1: H^H y = 0
+    y2[offs[2] + 17] = np.nan                  # frame 2: a NaN sample
+    say("cg isolation zero/nan")
+    x2, s2, st2 = _run(otfs, plan, y2)
+    assert st2["status"][1] == O_CONV and st2["iters"][1] == 0
+    assert not np.any(x2[offs[1]:offs[2]])
+    assert st2["status"][2] == 3               # OTFS_FRAME_NONFINITE
+    for f in (0, 3):                           # untouched frames: bit-identical
+        sl = slice(offs[f], offs[f + 1])
+        assert np.array_equal(x0[sl], x2[sl]) and np.array_equal(s0[sl], s2[sl])
+        assert st0["iters"][f] == st2["iters"][f]
+
+
+def test_graph_replay_is_bit_identical(otfs):
+    import torch
+    frames = _mixed_frames(17, 5, [(128, 32), (64, 16), (256, 16)], (2, 8), 8, 4)
+    ops, xs, y = oracle_batch(frames)
+    say("graph replay")
+    direct = otfs.Plan([f.spec for f in frames], tile_elems=2048)
+    xd, sd, std_ = _run(otfs, direct, y)
+    g = otfs.Plan([f.spec for f in frames], tile_elems=2048, flags=otfs.USE_GRAPH)
+    with pytest.raises(otfs.OtfsError):                # the NULL stream cannot be captured
+        g.lmmse_cg(to_dev(y), stream=torch.cuda.default_stream())
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        yd = to_dev(y)
+        sym = torch.zeros(g.total_elems, dtype=torch.uint8, device="cuda")
+        stats = g.new_stats()
+        x = torch.empty(g.total_elems, dtype=torch.complex64, device="cuda")
+        for rep in range(4):
+            x.fill_(float("nan"))
+            sym.fill_(255)
+            torch.zeros(1000, device="cuda").sum()      # unrelated eager work in between
+            g.lmmse_cg(yd, x, sym, stats)
+            side.synchronize()
+            assert np.array_equal(x.cpu().numpy(), xd), rep
+            assert np.array_equal(sym.cpu().numpy(), sd), rep
+            assert np.array_equal(otfs.stats_numpy(stats)["iters"], std_["iters"])
+
+
+def test_cg_fp64_refresh(otfs):
+    frames = _mixed_frames(18, 3, [(128, 32), (256, 16)], (4, 12), 10, 4, qams=(64,),
+                           snr=(30, 30))
+    ops, xs, y = oracle_batch(frames)
+    say("cg refresh every 5")
+    plan = otfs.Plan([f.spec for f in frames], refresh_every=5, tile_elems=1024)
+    _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
+
+
+def test_cg_bf16_stored_mode(otfs):
+    import torch
+    frames = _mixed_frames(19, 3, [(128, 32), (256, 16)], (4, 12), 10, 4, qams=(64,),
+                           snr=(30, 30))
+    ops, xs, y = oracle_batch(frames)
+    yb = torch.view_as_real(to_dev(y)).to(torch.bfloat16).contiguous().view(-1)
+    y_rounded = torch.view_as_complex(yb.view(-1, 2).float()).cpu().numpy()
+    say("cg bf16 y + stored D")
+    plan = otfs.Plan([f.spec for f in frames], refresh_every=10,
+                     flags=otfs.Y_BF16 | otfs.D_STORED_BF16, tile_elems=1024)
+    sym = torch.zeros(plan.total_elems, dtype=torch.uint8, device="cuda")
+    stats = plan.new_stats()
+    x = plan.lmmse_cg(yb, sym=sym, stats=stats).cpu().numpy()
+    st = otfs.stats_numpy(stats)
+    for i, (fr, xg) in enumerate(zip(frames, split(x, frames))):
+        xr, _, _ = O.cg_lmmse(split(y_rounded, frames)[i], ops[i], fr.spec.lam,
+                              fr.spec.max_iters, fr.spec.tol)
+        assert O.nmse(xg, xr) <= NMSE_TOL_BF16, i
+        assert st["status"][i] in (O_CONV, O_CAP)
+
+
+def _full_config(otfs, name, sample, tol):
+    import torch
+    frames = list(W.iter_frames(name))
+    say("full size", name, len(frames), "frames")
+    ops, xs, y = oracle_batch(frames)
+    plan = otfs.Plan([f.spec for f in frames], max_iters=frames[0].spec.max_iters,
+                     rel_tol=frames[0].spec.tol)
+    x, sym, st = _run(otfs, plan, y)
+    assert np.all(np.isin(st["status"], [O_CONV, O_CAP]))
+    xsplit, ysplit, ssplit = split(x, frames), split(y, frames), split(sym, frames)
+    for i in sample:
+        sp = frames[i].spec
+        xr, it_r, rel_r = O.cg_lmmse(ysplit[i], ops[i], sp.lam, sp.max_iters, sp.tol)
+        assert O.nmse(xsplit[i], xr) <= tol, (name, i)
+        check_decisions(ssplit[i], xsplit[i], xr, sp.qam)
+    return plan
+
+
+def test_full_size_batch64_512x128_sampled(otfs):
+    _full_config(otfs, "batch64_512x128", [0, 31, 63], NMSE_TOL)
+
+
+def test_full_size_uneven256_sampled(otfs):
+    _full_config(otfs, "uneven256", [0, 1, 2, 3, 128, 255], NMSE_TOL)
