@@ -83,8 +83,12 @@ enum {
   OTFS_USE_GRAPH = 1u << 2,      /* otfs_lmmse_cg replays a captured hipGraph of its launch
                                     sequence (re-captured when buffers or stream change);
                                     needs a created stream, not the NULL stream             */
-  OTFS_TIME_KERNEL = 1u << 3     /* bracket the fused CG kernel with hipEvents on the caller's
+  OTFS_TIME_KERNEL = 1u << 3,    /* bracket the fused CG kernel with hipEvents on the caller's
                                     stream; read with otfs_plan_kernel_ms                    */
+  OTFS_AGENT_BARRIER = 1u << 4   /* fused kernel: one work queue and device-wide coherent
+                                    per-frame barriers, independent of workgroup placement
+                                    (default: frames stay on one XCD, barriers coherent
+                                    through that XCD's L2)                                   */
 };
 
 /* CG options (Algorithm 1 with a per-frame stop test added in front of the direction
@@ -151,6 +155,8 @@ typedef struct {
   int32_t block;            /* threads per workgroup                                        */
   int32_t max_paths;        /* largest P in the batch                                       */
   int32_t tile_elems;       /* target elements per workgroup tile                           */
+  int32_t groups;           /* work-queue groups of the fused launch (XCDs, or 1)           */
+  int32_t xcd_local;        /* 1: frames stay on one XCD (see OTFS_AGENT_BARRIER)           */
 } otfs_plan_info_t;
 otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
 

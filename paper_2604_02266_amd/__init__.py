@@ -27,6 +27,7 @@ D_STORED_BF16 = 1 << 0
 Y_BF16 = 1 << 1
 USE_GRAPH = 1 << 2
 TIME_KERNEL = 1 << 3
+AGENT_BARRIER = 1 << 4
 FRAME_RUNNING, FRAME_CONVERGED, FRAME_CAPPED, FRAME_NONFINITE, FRAME_BREAKDOWN, FRAME_TIMEOUT = range(6)
 
 
@@ -57,7 +58,8 @@ class FrameStats(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("nframes", ctypes.c_int32), ("total_elems", ctypes.c_int64),
                 ("grid", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("max_paths", ctypes.c_int32), ("tile_elems", ctypes.c_int32)]
+                ("max_paths", ctypes.c_int32), ("tile_elems", ctypes.c_int32),
+                ("groups", ctypes.c_int32), ("xcd_local", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):

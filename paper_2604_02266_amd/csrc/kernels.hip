@@ -114,222 +114,220 @@ __device__ __forceinline__ double tile_sum_d(const double* part, int T) {
 // ---------------------------------------------------------------------------------------
 // per-frame barrier among the T workgroups that share a frame
 // ---------------------------------------------------------------------------------------
-// Every thread releases its own stores at agent scope (the L2s of different XCDs are not
-// coherent), the workgroup meets, one lane counts the arrival and waits for all T arrivals
-// of this barrier round, the workgroup meets again and every thread acquires.  The wait is
-// bounded: after `timeout` ticks of the 100 MHz wall clock, or when another workgroup has
-// raised the launch-wide abort flag, it gives up and reports failure.
-__device__ bool frame_barrier(unsigned* ctr, unsigned target, unsigned* abort_flag,
-                              uint64_t timeout, int* sflag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+// Two coherence modes.
+//  XCD-local (all workgroups of the frame run on one XCD, whose L2 they share): every
+//  thread waits for its own stores to reach the L2 (s_waitcnt vmcnt(0)), one lane counts
+//  the arrival with an L2 atomic and polls the count with L2 atomics, and after the
+//  workgroup meets again every thread drops its CU's L1 (buffer_inv sc0).  These are the
+//  release / acquire sequences the AMDGPU memory model uses for workgroup scope when the
+//  waves of a workgroup may sit on different CUs of one XCD; the L2 keeps its contents.
+//  Agent (fallback, any placement): agent-scope release and acquire fences (L2 write-back
+//  and invalidate, the L2s of different XCDs not being coherent) around an agent-scope
+//  counter.
+// The wait is bounded: after `timeout` ticks of the 100 MHz wall clock, or when another
+// workgroup has raised the launch-wide abort flag, it gives up and reports failure.
+__device__ __forceinline__ void xcd_release() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void xcd_acquire() {
+  asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc0" ::: "memory");
+}
+
+// Current value of a counter kept in the L2 by workgroup-scope atomics.  A plain or
+// idempotent read could be served by this CU's L1 (the compiler turns an idempotent RMW
+// such as fetch_add(0) into a load), so the poll is a compare-and-swap whose compare
+// value the counter never holds: it always executes in the L2 and never writes.
+__device__ __forceinline__ unsigned l2_poll(unsigned* ctr) {
+  unsigned expected = 0xffffffffu;
+  __hip_atomic_compare_exchange_strong(ctr, &expected, 0xfffffffeu, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return expected;
+}
+
+__device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
+                              unsigned* abort_flag, uint64_t timeout, int* sflag) {
+  if (xcd_local)
+    xcd_release();
+  else
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > timeout) {
-        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
+    if (xcd_local) {
+      unsigned v = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) + 1u;
+      while (v < target) {
+        __builtin_amdgcn_s_sleep(1);
+        v = l2_poll(ctr);
+        if (v >= target) break;
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > timeout) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    } else {
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > timeout) {
+          __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
       }
     }
     *sflag = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (xcd_local)
+    xcd_acquire();
+  else
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *sflag != 0;
 }
 
 // ---------------------------------------------------------------------------------------
-// Tiled operator applications.  src(i) returns element i (frame-local index) of the
-// vector being multiplied; sink(q, v) receives output element q of the band.  Threads
-// with nothing to do return early; callers put block-wide work after the call.
+// Band application of H (ADJ = false) or H^H (ADJ = true).
+//
+// A workgroup owns Doppler rows [lb, le) of one frame.  Thread (tx, ty) walks delay
+// columns k = tx, tx + TX, ... and, for each, the rows lb + ty + i*TY of the band in
+// chunks of R rows.  For one chunk the loop runs over the paths: the chunk's R gathers of
+// path p are independent loads issued together (R loads in flight per lane), each a
+// contiguous run of a source row across the wave, and the coefficient of the column is
+// loaded once per (chunk, path).  Nothing is sized by P, so one kernel serves every P.
+//
+// src(i) returns element i (frame-local index) of the vector being multiplied;
+// sink(q, v) receives output element q.  Threads without a column return early; callers
+// put block-wide work after the call.
 // ---------------------------------------------------------------------------------------
-template <int PMAX, bool STORED, class Src, class Sink>
-__device__ __forceinline__ void apply_fwd(const FrameDev& F, int lb, int le, Src src,
-                                          Sink sink) {
+template <int R, bool ADJ, bool STORED, class Src, class Sink>
+__device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Src src, Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
   const int TY = kBlock / TX;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   if (ty >= TY) return;
   const int64_t E = (int64_t)M * N;
+  const int nrows = le - lb - ty > 0 ? (le - lb - ty + TY - 1) / TY : 0;
+  const int2* __restrict__ paths = F.paths;
+  const float2* __restrict__ rtab = F.rtab;
+  const float2* __restrict__ wtab = F.wtab;
   for (int k = tx; k < M; k += TX) {
-    float2 cf[PMAX];
-    int ks[PMAX], nw[PMAX], nu[PMAX];
+    for (int r0 = 0; r0 < nrows; r0 += R) {
+      float2 acc[R];
 #pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-      if (p < P) {
-        const int2 tn = F.paths[p];
-        const int K = k - tn.x;                        // raw source delay
-        const int n = K < 0 ? -1 : (K >= M ? 1 : 0);   // delay wrap count
-        ks[p] = K - n * M;
-        nw[p] = n;
-        nu[p] = tn.y;
-        if (!STORED) cf[p] = F.rtab[p * M + k];
-      }
-    }
-    for (int l = lb + ty; l < le; l += TY) {
-      float2 acc = make_float2(0.f, 0.f);
-      const int q = l * M + k;
-#pragma unroll
-      for (int p = 0; p < PMAX; ++p) {
-        if (p < P) {
-          int ls = l - nu[p];
-          ls += ls < 0 ? N : 0;
-          ls -= ls >= N ? N : 0;
-          const float2 v = src(ls * M + ks[p]);
-          float2 c;
-          if (STORED) {
-            c = bf16x2_to_f2(F.dtab[(int64_t)p * E + q]);
-          } else {
-            c = cf[p];
-            if (nw[p] != 0) {
-              float2 w = F.wtab[ls];
-              if (nw[p] < 0) w.y = -w.y;
-              c = cmulf(c, w);
-            }
-          }
-          cmacf(acc, c, v);
-        }
-      }
-      sink(q, acc);
-    }
-  }
-}
-
-template <int PMAX, bool STORED, class Src, class Sink>
-__device__ __forceinline__ void apply_adj(const FrameDev& F, int lb, int le, Src src,
-                                          Sink sink) {
-  const int M = F.M, N = F.N, P = F.P;
-  const int TX = M < kBlock ? M : kBlock;
-  const int TY = kBlock / TX;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  if (ty >= TY) return;
-  const int64_t E = (int64_t)M * N;
-  for (int k = tx; k < M; k += TX) {
-    float2 cf[PMAX];
-    int kq[PMAX], ww[PMAX], nu[PMAX];
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-      if (p < P) {
-        const int2 tn = F.paths[p];
-        const int Kq = k + tn.x;
-        const int w = Kq < 0 ? -1 : (Kq >= M ? 1 : 0);   // the gathered row wraps by -w
-        kq[p] = Kq - w * M;
-        ww[p] = w;
-        nu[p] = tn.y;
-        if (!STORED) {
-          const float2 r = F.rtab[p * M + kq[p]];
-          cf[p] = make_float2(r.x, -r.y);
-        }
-      }
-    }
-    for (int l = lb + ty; l < le; l += TY) {
-      float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int p = 0; p < PMAX; ++p) {
-        if (p < P) {
-          int lq = l + nu[p];
-          lq += lq < 0 ? N : 0;
-          lq -= lq >= N ? N : 0;
-          const int qs = lq * M + kq[p];
-          const float2 v = src(qs);
-          float2 c;
-          if (STORED) {
-            const float2 d = bf16x2_to_f2(F.dtab[(int64_t)p * E + qs]);
-            c = make_float2(d.x, -d.y);
-          } else {
-            c = cf[p];
-            if (ww[p] != 0) {        // conj(W[l]^{-w}) = W[l]^{w}
-              float2 w = F.wtab[l];
-              if (ww[p] < 0) w.y = -w.y;
-              c = cmulf(c, w);
-            }
-          }
-          cmacf(acc, c, v);
-        }
-      }
-      sink(l * M + k, acc);
-    }
-  }
-}
-
-// FP64 versions (coefficients from the FP64 tables) for the true-residual refresh.
-template <int PMAX, class Src, class Sink>
-__device__ __forceinline__ void apply_fwd64(const FrameDev& F, int lb, int le, Src src,
-                                            Sink sink) {
-  const int M = F.M, N = F.N, P = F.P;
-  const int TX = M < kBlock ? M : kBlock;
-  const int TY = kBlock / TX;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  if (ty >= TY) return;
-  for (int k = tx; k < M; k += TX) {
-    for (int l = lb + ty; l < le; l += TY) {
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int p = 0; p < PMAX; ++p) {
-        if (p < P) {
-          const int2 tn = F.paths[p];
+      for (int i = 0; i < R; ++i) acc[i] = make_float2(0.f, 0.f);
+      for (int p = 0; p < P; ++p) {
+        const int2 tn = paths[p];
+        int kk, n;
+        if (!ADJ) {                       // source column <k - tau>_M, wrap count n
           const int K = k - tn.x;
-          const int n = K < 0 ? -1 : (K >= M ? 1 : 0);
-          int ls = l - tn.y;
-          ls += ls < 0 ? N : 0;
-          ls -= ls >= N ? N : 0;
-          const double2 v = src(ls * M + (K - n * M));
-          double2 c = F.rtab64[p * M + k];
-          if (n != 0) {
-            double2 w = F.wtab64[ls];
-            if (n < 0) w.y = -w.y;
-            c = cmuld(c, w);
+          n = K < 0 ? -1 : (K >= M ? 1 : 0);
+          kk = K - n * M;
+        } else {                          // gathered row's column <k + tau>_M
+          const int K = k + tn.x;
+          n = K < 0 ? -1 : (K >= M ? 1 : 0);
+          kk = K - n * M;
+        }
+        float2 cf = make_float2(0.f, 0.f);
+        if (!STORED) {
+          const float2 r = rtab[p * M + (ADJ ? kk : k)];
+          cf = ADJ ? make_float2(r.x, -r.y) : r;
+        }
+        float2 v[R];
+        int qs[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (r0 + i < nrows) {
+            const int l = lb + ty + (r0 + i) * TY;
+            int ls = ADJ ? l + tn.y : l - tn.y;
+            ls += ls < 0 ? N : 0;
+            ls -= ls >= N ? N : 0;
+            qs[i] = ls * M + kk;
+            v[i] = src(qs[i]);
           }
-          cmacd(acc, c, v);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (r0 + i < nrows) {
+            const int l = lb + ty + (r0 + i) * TY;
+            float2 c;
+            if (STORED) {
+              if (ADJ) {
+                const float2 d = bf16x2_to_f2(F.dtab[(int64_t)p * E + qs[i]]);
+                c = make_float2(d.x, -d.y);
+              } else {
+                c = bf16x2_to_f2(F.dtab[(int64_t)p * E + (int64_t)l * M + k]);
+              }
+            } else {
+              c = cf;
+              if (n != 0) {   // forward: W[source row]^n; adjoint: W[own row]^w
+                float2 w = wtab[ADJ ? l : qs[i] / M];
+                if (n < 0) w.y = -w.y;
+                c = cmulf(c, w);
+              }
+            }
+            cmacf(acc[i], c, v[i]);
+          }
         }
       }
-      sink(l * M + k, acc);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (r0 + i < nrows) sink((lb + ty + (r0 + i) * TY) * M + k, acc[i]);
     }
   }
 }
 
-template <int PMAX, class Src, class Sink>
-__device__ __forceinline__ void apply_adj64(const FrameDev& F, int lb, int le, Src src,
-                                            Sink sink) {
+// FP64 version (coefficients from the FP64 tables) for the true-residual refresh.
+template <int R, bool ADJ, class Src, class Sink>
+__device__ __forceinline__ void band_apply64(const FrameDev& F, int lb, int le, Src src,
+                                             Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
   const int TY = kBlock / TX;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   if (ty >= TY) return;
+  const int nrows = le - lb - ty > 0 ? (le - lb - ty + TY - 1) / TY : 0;
   for (int k = tx; k < M; k += TX) {
-    for (int l = lb + ty; l < le; l += TY) {
-      double2 acc = make_double2(0.0, 0.0);
+    for (int r0 = 0; r0 < nrows; r0 += R) {
+      double2 acc[R];
 #pragma unroll
-      for (int p = 0; p < PMAX; ++p) {
-        if (p < P) {
-          const int2 tn = F.paths[p];
-          const int Kq = k + tn.x;
-          const int w = Kq < 0 ? -1 : (Kq >= M ? 1 : 0);
-          const int kq = Kq - w * M;
-          int lq = l + tn.y;
-          lq += lq < 0 ? N : 0;
-          lq -= lq >= N ? N : 0;
-          const double2 v = src(lq * M + kq);
-          const double2 r = F.rtab64[p * M + kq];
-          double2 c = make_double2(r.x, -r.y);
-          if (w != 0) {
-            double2 wl = F.wtab64[l];
-            if (w < 0) wl.y = -wl.y;
-            c = cmuld(c, wl);
+      for (int i = 0; i < R; ++i) acc[i] = make_double2(0.0, 0.0);
+      for (int p = 0; p < P; ++p) {
+        const int2 tn = F.paths[p];
+        const int K = ADJ ? k + tn.x : k - tn.x;
+        const int n = K < 0 ? -1 : (K >= M ? 1 : 0);
+        const int kk = K - n * M;
+        const double2 r = F.rtab64[p * M + (ADJ ? kk : k)];
+        const double2 cf = ADJ ? make_double2(r.x, -r.y) : r;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (r0 + i < nrows) {
+            const int l = lb + ty + (r0 + i) * TY;
+            int ls = ADJ ? l + tn.y : l - tn.y;
+            ls += ls < 0 ? N : 0;
+            ls -= ls >= N ? N : 0;
+            const double2 v = src(ls * M + kk);
+            double2 c = cf;
+            if (n != 0) {
+              double2 w = F.wtab64[ADJ ? l : ls];
+              if (n < 0) w.y = -w.y;
+              c = cmuld(c, w);
+            }
+            cmacd(acc[i], c, v);
           }
-          cmacd(acc, c, v);
         }
       }
-      sink(l * M + k, acc);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (r0 + i < nrows) sink((lb + ty + (r0 + i) * TY) * M + k, acc[i]);
     }
   }
 }
+
+constexpr int kRows = 8;     // rows in flight per thread in the FP32 gathers
+constexpr int kRows64 = 4;   // and in the FP64 refresh gathers
 
 // ---------------------------------------------------------------------------------------
 // hard decisions (Eq. demod): nearest square-QAM level per axis, ties to the upper level
@@ -415,9 +413,10 @@ __device__ void finish_tile(const FrameDev& F, const WorkItem& wi, const FrameVe
 struct LaunchCtx {
   unsigned* abort_flag;
   uint64_t timeout;
+  int xcd_local;     // barrier coherence mode (see frame_barrier)
 };
 
-template <int PMAX, bool STORED>
+template <bool STORED>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                         const LaunchCtx& L, float* red, double* redd, int* sflag) {
   const FrameVecs V = frame_vecs(F, B);
@@ -427,6 +426,10 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   const int lb = wi.l_begin, le = wi.l_end;
   const int64_t q0 = (int64_t)lb * M, q1 = (int64_t)le * M;
   const float lam = F.lam;
+  float2* __restrict__ cvec = F.c;
+  float2* __restrict__ tvec = F.t;
+  float2* __restrict__ avec = F.a;
+  float2* __restrict__ xvec = V.x;
   unsigned nbar = 0;
   auto bar = [&]() -> bool {
     if (T == 1) {
@@ -434,7 +437,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       return true;
     }
     nbar += (unsigned)T;
-    return frame_barrier(F.bar, nbar, L.abort_flag, L.timeout, sflag);
+    return frame_barrier(F.bar, nbar, L.xcd_local != 0, L.abort_flag, L.timeout, sflag);
   };
   auto fail_timeout = [&]() {
     if (wi.tile == 0 && threadIdx.x == 0) {
@@ -451,12 +454,12 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line) ----
   if (!s.init) {
     float acc = 0.f;
-    apply_adj<PMAX, STORED>(
+    band_apply<kRows, true, STORED>(
         F, lb, le, [&](int i) { return load_y(V.y, i, V.ybf16); },
         [&](int q, float2 v) {
-          F.c[q] = v;
+          cvec[q] = v;
           F.p0[q] = v;
-          V.x[q] = make_float2(0.f, 0.f);
+          xvec[q] = make_float2(0.f, 0.f);
           acc = fmaf(v.x, v.x, acc);
           acc = fmaf(v.y, v.y, acc);
         });
@@ -481,27 +484,27 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
 
   for (int step = 0; step < budget; ++step) {
     const int xi = s.iter + 1;
-    float2* pold = s.pbuf ? F.p1 : F.p0;
+    float2* __restrict__ pold = s.pbuf ? F.p1 : F.p0;
     const bool dirp = (s.pending & 2) != 0, xp = (s.pending & 1) != 0;
-    float2* pnew = dirp ? (s.pbuf ? F.p0 : F.p1) : pold;
+    float2* __restrict__ pnew = dirp ? (s.pbuf ? F.p0 : F.p1) : pold;
     const float al = s.alpha, be = s.beta;
 
     // ---- A: deferred updates of the band, t = H p ----
     if (dirp) {
-      apply_fwd<PMAX, STORED>(
-          F, lb, le, [&](int i) { return axpyf(be, pold[i], F.c[i]); },
+      band_apply<kRows, false, STORED>(
+          F, lb, le, [&](int i) { return axpyf(be, pold[i], cvec[i]); },
           [&](int q, float2 v) {
-            F.t[q] = v;
+            tvec[q] = v;
             const float2 po = pold[q];
-            pnew[q] = axpyf(be, po, F.c[q]);
-            if (xp) V.x[q] = axpyf(al, po, V.x[q]);
+            pnew[q] = axpyf(be, po, cvec[q]);
+            if (xp) xvec[q] = axpyf(al, po, xvec[q]);
           });
     } else {
-      apply_fwd<PMAX, STORED>(
+      band_apply<kRows, false, STORED>(
           F, lb, le, [&](int i) { return pold[i]; },
           [&](int q, float2 v) {
-            F.t[q] = v;
-            if (xp) V.x[q] = axpyf(al, pold[q], V.x[q]);
+            tvec[q] = v;
+            if (xp) xvec[q] = axpyf(al, pold[q], xvec[q]);
           });
     }
     if (!bar()) return fail_timeout();
@@ -509,12 +512,12 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
       float acc = 0.f;
-      apply_adj<PMAX, STORED>(
-          F, lb, le, [&](int i) { return F.t[i]; },
+      band_apply<kRows, true, STORED>(
+          F, lb, le, [&](int i) { return tvec[i]; },
           [&](int q, float2 v) {
             const float2 p = pnew[q];
             const float2 a = axpyf(lam, p, v);
-            F.a[q] = a;
+            avec[q] = a;
             acc = fmaf(p.x, a.x, acc);
             acc = fmaf(p.y, a.y, acc);
           });
@@ -536,9 +539,10 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     // ---- C: c -= alpha a, partial ||c||^2 ----
     {
       float acc = 0.f;
+#pragma unroll 4
       for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
-        const float2 c = axpyf(-alpha, F.a[q], F.c[q]);
-        F.c[q] = c;
+        const float2 c = axpyf(-alpha, avec[q], cvec[q]);
+        cvec[q] = c;
         acc = fmaf(c.x, c.x, acc);
         acc = fmaf(c.y, c.y, acc);
       }
@@ -555,10 +559,10 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     if (F.refresh_every > 0 && xi % F.refresh_every == 0 && xi < F.max_iters &&
         isfinite(cn_new)) {
       // R1: u = y - H (x + alpha p) in FP64 (x itself is not written while others read it)
-      apply_fwd64<PMAX>(
+      band_apply64<kRows64, false>(
           F, lb, le,
           [&](int i) {
-            const float2 xv = axpyf(alpha, pnew[i], V.x[i]);
+            const float2 xv = axpyf(alpha, pnew[i], xvec[i]);
             return make_double2((double)xv.x, (double)xv.y);
           },
           [&](int q, double2 v) {
@@ -568,14 +572,14 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       if (!bar()) return fail_timeout();
       // R2: c = H^H u - lam x, with x += alpha p applied here
       double acc = 0.0;
-      apply_adj64<PMAX>(
+      band_apply64<kRows64, true>(
           F, lb, le, [&](int i) { return F.u[i]; },
           [&](int q, double2 v) {
-            const float2 xn = axpyf(alpha, pnew[q], V.x[q]);
-            V.x[q] = xn;
+            const float2 xn = axpyf(alpha, pnew[q], xvec[q]);
+            xvec[q] = xn;
             const float2 cf = make_float2((float)(v.x - (double)lam * (double)xn.x),
                                           (float)(v.y - (double)lam * (double)xn.y));
-            F.c[q] = cf;
+            cvec[q] = cf;
             acc = fma((double)cf.x, (double)cf.x, acc);
             acc = fma((double)cf.y, (double)cf.y, acc);
           });
@@ -599,53 +603,73 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   if (wi.tile == 0 && threadIdx.x == 0) *F.st = s;
 }
 
-template <int PMAX>
+// XCC (XCD) this wave runs on, from the hardware register XCC_ID, bits [3:0].
+__device__ __forceinline__ int xcc_id() {
+  return (int)(__builtin_amdgcn_s_getreg((15 << 11) | (0 << 6) | 20) & 0xfu);
+}
+
+// Work queues: group g owns items qitems[qrange[g].x .. qrange[g].y); its workgroups take
+// them in order with an atomic cursor.  In XCD-local mode a workgroup serves the group of
+// the XCD it runs on, so every frame (all of whose tiles sit in one group) is handled by
+// workgroups sharing one L2.  A frame's tiles are consecutive in its group's queue and a
+// group never has fewer resident workgroups than a frame has tiles, so the first frame
+// with an untaken tile is always being completed: the per-frame barriers cannot deadlock.
+template <bool STORED>
 __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict__ frames,
                                                      const WorkItem* __restrict__ items,
-                                                     const int32_t* __restrict__ sched,
-                                                     const int2* __restrict__ ranges,
+                                                     const int32_t* __restrict__ qitems,
+                                                     const int2* __restrict__ qrange,
+                                                     unsigned* __restrict__ qhead, int ngroups,
                                                      int budget, Bases B, LaunchCtx L) {
   __shared__ float red[kWaves];
   __shared__ double redd[kWaves];
   __shared__ int sflag;
-  const int2 r = ranges[blockIdx.x];
-  for (int j = r.x; j < r.y; ++j) {
-    const WorkItem wi = items[sched[j]];
-    const FrameDev F = frames[wi.frame];
-    if (F.dtab)
-      cg_item<PMAX, true>(F, wi, budget, B, L, red, redd, &sflag);
-    else
-      cg_item<PMAX, false>(F, wi, budget, B, L, red, redd, &sflag);
+  __shared__ int s_item;
+  const int g = L.xcd_local ? xcc_id() : 0;
+  if (g >= ngroups) return;
+  const int2 r = qrange[g];
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const unsigned j = __hip_atomic_fetch_add(&qhead[g], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = (int)j < r.y - r.x ? qitems[r.x + (int)j] : -1;
+    }
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it < 0) break;
+    const WorkItem wi = items[it];
+    cg_item<STORED>(frames[wi.frame], wi, budget, B, L, red, redd, &sflag);
     __syncthreads();
   }
+}
+
+__global__ void k_xcc_probe(int* out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 // ---------------------------------------------------------------------------------------
 // standalone operator applications (one workgroup per tile)
 // ---------------------------------------------------------------------------------------
-template <int PMAX, bool ADJ>
+template <bool ADJ, bool STORED>
 __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ frames,
                                                   const WorkItem* __restrict__ items,
                                                   const float2* __restrict__ in,
                                                   float2* __restrict__ out) {
   const WorkItem wi = items[blockIdx.x];
-  const FrameDev F = frames[wi.frame];
-  const float2* src = in + F.off;
-  float2* dst = out + F.off;
-  auto ld = [&](int i) { return src[i]; };
-  auto st = [&](int q, float2 v) { dst[q] = v; };
-  if (F.dtab) {
-    if (ADJ) apply_adj<PMAX, true>(F, wi.l_begin, wi.l_end, ld, st);
-    else apply_fwd<PMAX, true>(F, wi.l_begin, wi.l_end, ld, st);
-  } else {
-    if (ADJ) apply_adj<PMAX, false>(F, wi.l_begin, wi.l_end, ld, st);
-    else apply_fwd<PMAX, false>(F, wi.l_begin, wi.l_end, ld, st);
-  }
+  const FrameDev& F = frames[wi.frame];
+  const float2* __restrict__ src = in + F.off;
+  float2* __restrict__ dst = out + F.off;
+  band_apply<kRows, ADJ, STORED>(
+      F, wi.l_begin, wi.l_end, [&](int i) { return src[i]; },
+      [&](int q, float2 v) { dst[q] = v; });
 }
 
-__global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsigned* abort_flag) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && abort_flag) *abort_flag = 0u;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nframes; i += gridDim.x * blockDim.x) {
+__global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsigned* abort_flag,
+                        unsigned* qhead, int ngroups) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && abort_flag) *abort_flag = 0u;
+  if (qhead && t < ngroups) qhead[t] = 0u;
+  for (int i = t; i < nframes; i += gridDim.x * blockDim.x) {
     const FrameDev& F = frames[i];
     *F.bar = 0u;
     FrameState s;
@@ -661,11 +685,10 @@ __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsign
 }
 
 // Stored coefficients D_{p,q} (Eq. D_definition) of every frame as bf16 pairs.
-template <int PMAX>
 __global__ __launch_bounds__(kBlock) void k_build_d(const FrameDev* __restrict__ frames,
                                                     const WorkItem* __restrict__ items) {
   const WorkItem wi = items[blockIdx.x];
-  const FrameDev F = frames[wi.frame];
+  const FrameDev& F = frames[wi.frame];
   const int M = F.M, N = F.N;
   const int64_t E = (int64_t)M * N;
   uint32_t* d = const_cast<uint32_t*>(F.dtab);
@@ -693,15 +716,14 @@ __global__ __launch_bounds__(kBlock) void k_build_d(const FrameDev* __restrict__
 // ---------------------------------------------------------------------------------------
 // Plain form: one frame at a time, unfused kernels, scalars on the device
 // ---------------------------------------------------------------------------------------
-template <int PMAX>
 __global__ __launch_bounds__(kBlock) void k_plain_init(const FrameDev* __restrict__ frames,
                                                        int f, const WorkItem* items, Bases B) {
   __shared__ float red[kWaves];
   const WorkItem wi = items[blockIdx.x];
-  const FrameDev F = frames[f];
+  const FrameDev& F = frames[f];
   const FrameVecs V = frame_vecs(F, B);
   float acc = 0.f;
-  apply_adj<PMAX, false>(
+  band_apply<kRows, true, false>(
       F, wi.l_begin, wi.l_end, [&](int i) { return load_y(V.y, i, V.ybf16); },
       [&](int q, float2 v) {
         F.c[q] = v;
@@ -716,7 +738,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_init(const FrameDev* __restric
 
 __global__ void k_plain_start(const FrameDev* __restrict__ frames, int f) {
   if (threadIdx.x != 0) return;
-  const FrameDev F = frames[f];
+  const FrameDev& F = frames[f];
   const float cn0 = (float)tile_sum(F.part_cc, F.T);
   FrameState s = *F.st;
   s.cn0 = cn0;
@@ -729,27 +751,25 @@ __global__ void k_plain_start(const FrameDev* __restrict__ frames, int f) {
   *F.st = s;
 }
 
-template <int PMAX>
 __global__ __launch_bounds__(kBlock) void k_plain_H(const FrameDev* __restrict__ frames, int f,
                                                     const WorkItem* items) {
-  const FrameDev F = frames[f];
+  const FrameDev& F = frames[f];
   if (F.st->status != OTFS_FRAME_RUNNING) return;
   const WorkItem wi = items[blockIdx.x];
-  apply_fwd<PMAX, false>(
+  band_apply<kRows, false, false>(
       F, wi.l_begin, wi.l_end, [&](int i) { return F.p0[i]; },
       [&](int q, float2 v) { F.t[q] = v; });
 }
 
-template <int PMAX>
 __global__ __launch_bounds__(kBlock) void k_plain_HH(const FrameDev* __restrict__ frames, int f,
                                                      const WorkItem* items) {
   __shared__ float red[kWaves];
-  const FrameDev F = frames[f];
+  const FrameDev& F = frames[f];
   if (F.st->status != OTFS_FRAME_RUNNING) return;
   const WorkItem wi = items[blockIdx.x];
   const float lam = F.lam;
   float acc = 0.f;
-  apply_adj<PMAX, false>(
+  band_apply<kRows, true, false>(
       F, wi.l_begin, wi.l_end, [&](int i) { return F.t[i]; },
       [&](int q, float2 v) {
         const float2 p = F.p0[q];
@@ -766,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_update(const FrameDev* __restr
                                                          int f, const WorkItem* items, int xi,
                                                          Bases B) {
   __shared__ float red[kWaves];
-  const FrameDev F = frames[f];
+  const FrameDev& F = frames[f];
   FrameState* st = F.st;
   if (st->status != OTFS_FRAME_RUNNING) return;
   const FrameVecs V = frame_vecs(F, B);
@@ -795,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_update(const FrameDev* __restr
 
 __global__ __launch_bounds__(kBlock) void k_plain_dir(const FrameDev* __restrict__ frames,
                                                       int f, const WorkItem* items, int xi) {
-  const FrameDev F = frames[f];
+  const FrameDev& F = frames[f];
   FrameState* st = F.st;
   if (st->status != OTFS_FRAME_RUNNING) return;
   const WorkItem wi = items[blockIdx.x];
@@ -826,7 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_dir(const FrameDev* __restrict
 
 __global__ __launch_bounds__(kBlock) void k_plain_finish(const FrameDev* __restrict__ frames,
                                                          int f, const WorkItem* items, Bases B) {
-  const FrameDev F = frames[f];
+  const FrameDev& F = frames[f];
   const FrameVecs V = frame_vecs(F, B);
   const WorkItem wi = items[blockIdx.x];
   const FrameState s = *F.st;
@@ -847,39 +867,27 @@ __global__ __launch_bounds__(kBlock) void k_plain_finish(const FrameDev* __restr
 // ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
-int pmax_bucket(int max_paths) {
-  if (max_paths <= 4) return 4;
-  if (max_paths <= 8) return 8;
-  if (max_paths <= 16) return 16;
-  if (max_paths <= 32) return 32;
-  return 64;
-}
-
-#define OTFS_PMAX_SWITCH(pm, BODY)            \
-  switch (pm) {                               \
-    case 4: { constexpr int PM = 4; BODY; } break;   \
-    case 8: { constexpr int PM = 8; BODY; } break;   \
-    case 16: { constexpr int PM = 16; BODY; } break; \
-    case 32: { constexpr int PM = 32; BODY; } break; \
-    default: { constexpr int PM = 64; BODY; } break; \
-  }
-
-hipError_t launch_apply(bool adjoint, int pmax, const FrameDev* frames, const WorkItem* items,
+hipError_t launch_apply(bool adjoint, bool stored, const FrameDev* frames, const WorkItem* items,
                         int nitems, const float2* in, float2* out, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  OTFS_PMAX_SWITCH(pmax, {
-    if (adjoint)
-      hipLaunchKernelGGL((k_apply<PM, true>), dim3(nitems), dim3(kBlock), 0, s, frames, items, in, out);
-    else
-      hipLaunchKernelGGL((k_apply<PM, false>), dim3(nitems), dim3(kBlock), 0, s, frames, items, in, out);
-  });
+  const dim3 g(nitems), b(kBlock);
+  if (adjoint) {
+    if (stored) hipLaunchKernelGGL((k_apply<true, true>), g, b, 0, s, frames, items, in, out);
+    else hipLaunchKernelGGL((k_apply<true, false>), g, b, 0, s, frames, items, in, out);
+  } else {
+    if (stored) hipLaunchKernelGGL((k_apply<false, true>), g, b, 0, s, frames, items, in, out);
+    else hipLaunchKernelGGL((k_apply<false, false>), g, b, 0, s, frames, items, in, out);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_flag, hipStream_t s) {
-  if (nframes <= 0) return hipSuccess;
-  const int grid = (nframes + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_reset, dim3(grid), dim3(kBlock), 0, s, frames, nframes, abort_flag);
+hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_flag,
+                        unsigned* qhead, int ngroups, hipStream_t s) {
+  const int n = nframes > ngroups ? nframes : ngroups;
+  if (n <= 0) return hipSuccess;
+  const int grid = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_reset, dim3(grid), dim3(kBlock), 0, s, frames, nframes, abort_flag,
+                     qhead, ngroups);
   return hipGetLastError();
 }
 
@@ -887,7 +895,7 @@ static uint64_t wallclock_timeout_ticks() {
   static uint64_t ticks = 0;
   if (ticks == 0) {
     int dev = 0, khz = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
       khz = 100000;
     ticks = (uint64_t)khz * 1000ull * 20ull;   // 20 s
@@ -895,52 +903,53 @@ static uint64_t wallclock_timeout_ticks() {
   return ticks;
 }
 
-hipError_t launch_cg_fused(int pmax, const FrameDev* frames, const WorkItem* items,
-                           const int32_t* sched, const int2* ranges, int grid, int budget,
-                           Bases bases, hipStream_t s, unsigned* abort_flag) {
+hipError_t launch_cg_fused(bool stored, const FrameDev* frames, const WorkItem* items,
+                           const int32_t* qitems, const int2* qrange, unsigned* qhead,
+                           int ngroups, int grid, int budget, Bases bases, bool xcd_local,
+                           unsigned* abort_flag, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  LaunchCtx L{abort_flag, wallclock_timeout_ticks()};
-  OTFS_PMAX_SWITCH(pmax, {
-    hipLaunchKernelGGL((k_cg_fused<PM>), dim3(grid), dim3(kBlock), 0, s, frames, items, sched,
-                       ranges, budget, bases, L);
-  });
+  LaunchCtx L{abort_flag, wallclock_timeout_ticks(), xcd_local ? 1 : 0};
+  if (stored)
+    hipLaunchKernelGGL((k_cg_fused<true>), dim3(grid), dim3(kBlock), 0, s, frames, items, qitems,
+                       qrange, qhead, ngroups, budget, bases, L);
+  else
+    hipLaunchKernelGGL((k_cg_fused<false>), dim3(grid), dim3(kBlock), 0, s, frames, items, qitems,
+                       qrange, qhead, ngroups, budget, bases, L);
   return hipGetLastError();
 }
 
-int fused_blocks_per_cu(int pmax) {
+int fused_blocks_per_cu(bool stored) {
   int n = 0;
-  OTFS_PMAX_SWITCH(pmax, {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_cg_fused<PM>), kBlock, 0) != hipSuccess)
-      n = 0;
-  });
+  const void* fn = stored ? reinterpret_cast<const void*>(&k_cg_fused<true>)
+                          : reinterpret_cast<const void*>(&k_cg_fused<false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, 0) != hipSuccess) n = 0;
   return n;
 }
 
-hipError_t launch_plain_frame(int pmax, const FrameDev* frames_dev, int f,
-                              const WorkItem* items_dev, int item_begin, int ntiles,
-                              int max_iters, Bases B, hipStream_t s) {
-  const WorkItem* it = items_dev + item_begin;
-  const dim3 g(ntiles), b(kBlock);
-  OTFS_PMAX_SWITCH(pmax, {
-    hipLaunchKernelGGL((k_plain_init<PM>), g, b, 0, s, frames_dev, f, it, B);
-    hipLaunchKernelGGL(k_plain_start, dim3(1), dim3(64), 0, s, frames_dev, f);
-    for (int xi = 1; xi <= max_iters; ++xi) {
-      hipLaunchKernelGGL((k_plain_H<PM>), g, b, 0, s, frames_dev, f, it);
-      hipLaunchKernelGGL((k_plain_HH<PM>), g, b, 0, s, frames_dev, f, it);
-      hipLaunchKernelGGL(k_plain_update, g, b, 0, s, frames_dev, f, it, xi, B);
-      hipLaunchKernelGGL(k_plain_dir, g, b, 0, s, frames_dev, f, it, xi);
-    }
-    hipLaunchKernelGGL(k_plain_finish, g, b, 0, s, frames_dev, f, it, B);
-  });
+hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_xcc_probe, dim3(nblocks), dim3(64), 0, s, out);
   return hipGetLastError();
 }
 
-hipError_t launch_build_d(int pmax, const FrameDev* frames, const WorkItem* items, int nitems,
-                          hipStream_t s) {
+hipError_t launch_plain_frame(const FrameDev* frames_dev, int f, const WorkItem* items_dev,
+                              int item_begin, int ntiles, int max_iters, Bases B, hipStream_t s) {
+  const WorkItem* it = items_dev + item_begin;
+  const dim3 g(ntiles), b(kBlock);
+  hipLaunchKernelGGL(k_plain_init, g, b, 0, s, frames_dev, f, it, B);
+  hipLaunchKernelGGL(k_plain_start, dim3(1), dim3(64), 0, s, frames_dev, f);
+  for (int xi = 1; xi <= max_iters; ++xi) {
+    hipLaunchKernelGGL(k_plain_H, g, b, 0, s, frames_dev, f, it);
+    hipLaunchKernelGGL(k_plain_HH, g, b, 0, s, frames_dev, f, it);
+    hipLaunchKernelGGL(k_plain_update, g, b, 0, s, frames_dev, f, it, xi, B);
+    hipLaunchKernelGGL(k_plain_dir, g, b, 0, s, frames_dev, f, it, xi);
+  }
+  hipLaunchKernelGGL(k_plain_finish, g, b, 0, s, frames_dev, f, it, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_d(const FrameDev* frames, const WorkItem* items, int nitems, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  OTFS_PMAX_SWITCH(pmax, {
-    hipLaunchKernelGGL((k_build_d<PM>), dim3(nitems), dim3(kBlock), 0, s, frames, items);
-  });
+  hipLaunchKernelGGL(k_build_d, dim3(nitems), dim3(kBlock), 0, s, frames, items);
   return hipGetLastError();
 }
 

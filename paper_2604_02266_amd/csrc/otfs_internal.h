@@ -83,32 +83,40 @@ struct Bases {
 };
 
 // ---- launchers (kernels.hip) -----------------------------------------------------------
-int pmax_bucket(int max_paths);   // 4, 8, 16, 32 or 64
+constexpr int kMaxGroups = 16;   // work-queue groups (one per XCD in XCD-local mode)
 
 // One workgroup per item.  in/out are batch-wide complex64 buffers (frame at base + off).
-hipError_t launch_apply(bool adjoint, int pmax, const FrameDev* frames, const WorkItem* items,
+hipError_t launch_apply(bool adjoint, bool stored, const FrameDev* frames, const WorkItem* items,
                         int nitems, const float2* in, float2* out, hipStream_t s);
 
-// Reset barrier counters and CG state of frames [0, nframes) and the abort word.
-hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_flag, hipStream_t s);
+// Reset barrier counters and CG state of frames [0, nframes), the abort word and the
+// queue cursors of ngroups groups.
+hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_flag,
+                        unsigned* qhead, int ngroups, hipStream_t s);
 
-// Fused persistent CG.  grid workgroups; workgroup w runs items sched[range[w].x ..
-// range[w].y) in order.  budget = iterations to run per frame in this launch.
-// abort_flag: one device word, zero before the launch; raised by a workgroup whose
-// per-frame barrier wait timed out so that every other wait ends at once.
-hipError_t launch_cg_fused(int pmax, const FrameDev* frames, const WorkItem* items,
-                           const int32_t* sched, const int2* ranges, int grid, int budget,
-                           Bases bases, hipStream_t s, unsigned* abort_flag);
+// Fused persistent CG over work queues: group g holds item indices
+// qitems[qrange[g].x .. qrange[g].y); qhead[g] is its cursor (zero before the launch).
+// xcd_local: workgroups serve the group of the XCD they run on and frame barriers use
+// XCD-local coherence; otherwise there is one group and agent-scope barriers.
+// abort_flag: zero before the launch; raised by a workgroup whose barrier wait timed out
+// so that every other wait ends at once.  budget = iterations per frame in this launch.
+hipError_t launch_cg_fused(bool stored, const FrameDev* frames, const WorkItem* items,
+                           const int32_t* qitems, const int2* qrange, unsigned* qhead,
+                           int ngroups, int grid, int budget, Bases bases, bool xcd_local,
+                           unsigned* abort_flag, hipStream_t s);
 // Workgroups of the fused kernel that fit on one CU at once (occupancy).
-int fused_blocks_per_cu(int pmax);
+int fused_blocks_per_cu(bool stored);
 
-// Plain (unfused, one frame per launch sequence) form.
-hipError_t launch_plain_frame(int pmax, const FrameDev* frames_dev, int frame,
-                              const WorkItem* items_dev, int item_begin, int ntiles,
-                              int max_iters, Bases bases, hipStream_t s);
+// out[b] = XCC id of workgroup b, for b < nblocks.
+hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
+
+// Plain (unfused, one frame per launch sequence) form of one frame.
+hipError_t launch_plain_frame(const FrameDev* frames_dev, int frame, const WorkItem* items_dev,
+                              int item_begin, int ntiles, int max_iters, Bases bases,
+                              hipStream_t s);
 
 // Build the stored bf16 D table of every frame.
-hipError_t launch_build_d(int pmax, const FrameDev* frames, const WorkItem* items, int nitems,
+hipError_t launch_build_d(const FrameDev* frames, const WorkItem* items, int nitems,
                           hipStream_t s);
 
 }  // namespace otfs

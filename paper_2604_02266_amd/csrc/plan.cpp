@@ -48,7 +48,8 @@ otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out) {
   if (!(d.rel_tol >= 0.f) || !std::isfinite(d.rel_tol))
     return fail(OTFS_E_INVAL, "rel_tol must be finite and >= 0");
   if (d.refresh_every < 0) return fail(OTFS_E_INVAL, "refresh_every must be >= 0");
-  const uint32_t known = OTFS_D_STORED_BF16 | OTFS_Y_BF16 | OTFS_USE_GRAPH | OTFS_TIME_KERNEL;
+  const uint32_t known = OTFS_D_STORED_BF16 | OTFS_Y_BF16 | OTFS_USE_GRAPH | OTFS_TIME_KERNEL |
+                         OTFS_AGENT_BARRIER;
   if (d.flags & ~known) return fail(OTFS_E_INVAL, "unknown flag bits 0x%x", d.flags & ~known);
   *out = d;
   return OTFS_OK;
@@ -151,64 +152,73 @@ void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vecto
   }
 }
 
-// Persistent schedule.  If every tile gets its own workgroup, that is the schedule.
-// Otherwise frames are taken largest first and each frame's T_f tiles go to the T_f least
-// loaded workgroups (distinct ones).  Every workgroup runs its items in assignment order,
-// so the frame of lowest assignment index among those in progress always has all its
-// workgroups present: the per-frame barriers cannot deadlock while the whole grid is
-// resident.
-void make_schedule(const std::vector<HostFrame>& frames, const std::vector<WorkItem>& items,
-                   const std::vector<int>& tile_base, const std::vector<int>& tiles, int cap,
-                   std::vector<int32_t>& sched, std::vector<int2>& ranges, int* grid_out) {
-  const int nitems = (int)items.size();
-  sched.clear();
-  ranges.clear();
-  if (nitems == 0) {
-    *grid_out = 0;
-    return;
-  }
-  if (nitems <= cap) {
-    for (int i = 0; i < nitems; ++i) {
-      sched.push_back(i);
-      ranges.push_back(make_int2(i, i + 1));
-    }
-    *grid_out = nitems;
-    return;
-  }
-  const int grid = cap;
+bool make_queues(const std::vector<HostFrame>& frames, const std::vector<int>& tile_base,
+                 const std::vector<int>& tiles, int ngroups, int per_group_cap,
+                 std::vector<int32_t>& qitems, std::vector<int2>& qrange, int* per_group_grid) {
+  qitems.clear();
+  qrange.assign(kMaxGroups, make_int2(0, 0));
+  *per_group_grid = 0;
+  for (int t : tiles)
+    if (t > per_group_cap) return false;
+  // frames largest first, each to the least loaded group
   std::vector<int> order(frames.size());
   std::iota(order.begin(), order.end(), 0);
   auto work = [&](int f) {
     const HostFrame& fr = frames[f];
-    return (double)fr.M * fr.N * (2.0 * fr.P + 6.0) / tiles[f];
+    return (double)fr.M * fr.N * (2.0 * fr.P + 6.0);
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-  std::vector<std::vector<int32_t>> lists(grid);
-  using Slot = std::pair<double, int>;   // (load, workgroup)
-  std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> pq;
-  for (int w = 0; w < grid; ++w) pq.push({0.0, w});
-  std::vector<Slot> picked;
+  std::vector<std::vector<int32_t>> lists(ngroups);
+  std::vector<double> load(ngroups, 0.0);
   for (int f : order) {
-    const int T = tiles[f];
-    picked.clear();
-    double start = 0.0;
-    for (int t = 0; t < T; ++t) {
-      picked.push_back(pq.top());
-      pq.pop();
-      start = std::max(start, picked.back().first);
-    }
-    const double fin = start + work(f);
-    for (int t = 0; t < T; ++t) {
-      lists[picked[t].second].push_back(tile_base[f] + t);
-      pq.push({fin, picked[t].second});
-    }
+    int g = 0;
+    for (int i = 1; i < ngroups; ++i)
+      if (load[i] < load[g]) g = i;
+    load[g] += work(f);
+    for (int t = 0; t < tiles[f]; ++t) lists[g].push_back(tile_base[f] + t);
   }
-  for (int w = 0; w < grid; ++w) {
-    const int b = (int)sched.size();
-    sched.insert(sched.end(), lists[w].begin(), lists[w].end());
-    ranges.push_back(make_int2(b, (int)sched.size()));
+  int per = 1;
+  for (int g = 0; g < ngroups; ++g) {
+    const int b = (int)qitems.size();
+    qitems.insert(qitems.end(), lists[g].begin(), lists[g].end());
+    qrange[g] = make_int2(b, (int)qitems.size());
+    per = std::max(per, (int)lists[g].size());
   }
-  *grid_out = grid;
+  *per_group_grid = std::min(per, per_group_cap);
+  return true;
+}
+
+otfs_status probe_xcds(int device, void* scratch_dev, hipStream_t s, XcdInfo* out) {
+  static std::vector<int> cached_n(64, 0);
+  static std::vector<int> cached_rr(64, 0);
+  if (device >= 0 && device < 64 && cached_n[device] > 0) {
+    out->nxcd = cached_n[device];
+    out->round_robin = cached_rr[device] != 0;
+    return OTFS_OK;
+  }
+  hipError_t e = launch_xcc_probe(static_cast<int*>(scratch_dev), kProbeBlocks, s);
+  if (e != hipSuccess) return hip_fail(e, "XCC probe launch");
+  std::vector<int> ids(kProbeBlocks, -1);
+  if ((e = hipMemcpyAsync(ids.data(), scratch_dev, ids.size() * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "XCC probe readback");
+  int mx = 0;
+  bool ok = true;
+  for (int v : ids) {
+    if (v < 0 || v >= kMaxGroups) ok = false;
+    mx = std::max(mx, v);
+  }
+  XcdInfo info;
+  info.nxcd = ok ? mx + 1 : 1;
+  info.round_robin = ok && info.nxcd > 1;
+  for (int b = 0; b < kProbeBlocks && info.round_robin; ++b)
+    if (ids[b] != b % info.nxcd) info.round_robin = false;
+  if (device >= 0 && device < 64) {
+    cached_n[device] = info.nxcd;
+    cached_rr[device] = info.round_robin ? 1 : 0;
+  }
+  *out = info;
+  return OTFS_OK;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -238,8 +248,10 @@ void compute_layout(otfs_plan_t* pl) {
   };
   L.frames = take(nf * sizeof(FrameDev));
   L.items = take(nitems * sizeof(WorkItem));
-  L.sched = take(nitems * sizeof(int32_t));
-  L.ranges = take(nitems * sizeof(int2));
+  L.qitems = take(nitems * sizeof(int32_t));
+  L.qrange = take(kMaxGroups * sizeof(int2));
+  L.qhead = take(kMaxGroups * sizeof(unsigned));
+  L.probe = take(kProbeBlocks * sizeof(int));
   L.rtab = take(rt * sizeof(float2));
   L.wtab = take(wt * sizeof(float2));
   L.rtab64 = refresh ? take(rt * sizeof(double2)) : 0;
@@ -298,7 +310,6 @@ extern "C" otfs_status otfs_plan(const otfs_frame_desc* frames, int32_t nframes,
   }
   pl->total_elems = total;
   pl->max_paths = maxp;
-  pl->pmax = pmax_bucket(std::max(maxp, 1));
   int cus = 256;
   int dev = 0, ndev = 0;
   if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 && hipGetDevice(&dev) == hipSuccess) {
@@ -331,6 +342,8 @@ extern "C" otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t*
   info->block = kBlock;
   info->max_paths = plan->max_paths;
   info->tile_elems = plan->tile_elems;
+  info->groups = plan->ngroups;
+  info->xcd_local = plan->xcd_local ? 1 : 0;
   return OTFS_OK;
 }
 
@@ -362,21 +375,41 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   plan->device = dev;
   plan->drop_graph();
 
-  // schedule for the fused kernel (needs the occupancy of this device)
-  const int bpc = std::max(1, fused_blocks_per_cu(plan->pmax));
+  // work queues of the fused kernel (need the occupancy and XCD layout of this device)
+  const bool stored_mode = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
+  const int bpc = std::max(1, fused_blocks_per_cu(stored_mode));
   int cus = plan->cus;
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
     cus = v;
   int cap = bpc * cus;
   if (plan->max_grid_req > 0) cap = std::min(cap, plan->max_grid_req);
-  // a frame's tiles must run at the same time on distinct workgroups
-  int maxT = 1;
-  for (int t : plan->tiles) maxT = std::max(maxT, t);
-  if (maxT > cap)
-    return fail(OTFS_E_UNSUPPORTED, "a frame needs %d cooperating workgroups but only %d fit", maxT, cap);
-  make_schedule(plan->frames, plan->items, plan->tile_base, plan->tiles, cap, plan->sched,
-                plan->ranges, &plan->grid);
+  XcdInfo xi;
+  otfs_status pst = probe_xcds(dev, static_cast<char*>(ws) + plan->L.probe, s, &xi);
+  if (pst != OTFS_OK) return pst;
+  plan->xcd_local = false;
+  plan->ngroups = 1;
+  int per = 0;
+  if (!(plan->opts.flags & OTFS_AGENT_BARRIER) && xi.round_robin && cap >= xi.nxcd) {
+    const int per_cap = cap / xi.nxcd;
+    if (make_queues(plan->frames, plan->tile_base, plan->tiles, xi.nxcd, per_cap, plan->qitems,
+                    plan->qrange, &per)) {
+      plan->xcd_local = true;
+      plan->ngroups = xi.nxcd;
+      plan->grid = per * xi.nxcd;
+    }
+  }
+  if (!plan->xcd_local) {
+    if (!make_queues(plan->frames, plan->tile_base, plan->tiles, 1, cap, plan->qitems,
+                     plan->qrange, &per)) {
+      int maxT = 1;
+      for (int t : plan->tiles) maxT = std::max(maxT, t);
+      return fail(OTFS_E_UNSUPPORTED, "a frame needs %d cooperating workgroups but only %d fit",
+                  maxT, cap);
+    }
+    plan->grid = per;
+  }
+  if (plan->items.empty()) plan->grid = 0;
 
   // host tables
   const Layout& L = plan->L;
@@ -447,8 +480,8 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   };
   if ((e = up(L.frames, fd.data(), fd.size() * sizeof(FrameDev))) != hipSuccess ||
       (e = up(L.items, plan->items.data(), plan->items.size() * sizeof(WorkItem))) != hipSuccess ||
-      (e = up(L.sched, plan->sched.data(), plan->sched.size() * sizeof(int32_t))) != hipSuccess ||
-      (e = up(L.ranges, plan->ranges.data(), plan->ranges.size() * sizeof(int2))) != hipSuccess ||
+      (e = up(L.qitems, plan->qitems.data(), plan->qitems.size() * sizeof(int32_t))) != hipSuccess ||
+      (e = up(L.qrange, plan->qrange.data(), plan->qrange.size() * sizeof(int2))) != hipSuccess ||
       (e = up(L.rtab, plan->h_rtab.data(), plan->h_rtab.size() * sizeof(float2))) != hipSuccess ||
       (e = up(L.wtab, plan->h_wtab.data(), plan->h_wtab.size() * sizeof(float2))) != hipSuccess ||
       (e = up(L.paths, plan->h_paths.data(), plan->h_paths.size() * sizeof(int2))) != hipSuccess)
@@ -461,11 +494,12 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   plan->ws = ws;
   plan->d_frames = reinterpret_cast<FrameDev*>(base + L.frames);
   plan->d_items = reinterpret_cast<WorkItem*>(base + L.items);
-  plan->d_sched = reinterpret_cast<int32_t*>(base + L.sched);
-  plan->d_ranges = reinterpret_cast<int2*>(base + L.ranges);
+  plan->d_qitems = reinterpret_cast<int32_t*>(base + L.qitems);
+  plan->d_qrange = reinterpret_cast<int2*>(base + L.qrange);
+  plan->d_qhead = reinterpret_cast<unsigned*>(base + L.qhead);
   plan->d_abort = reinterpret_cast<unsigned*>(base + L.abort);
   if (stored) {
-    if ((e = launch_build_d(plan->pmax, plan->d_frames, plan->d_items, (int)plan->items.size(), s)) != hipSuccess)
+    if ((e = launch_build_d(plan->d_frames, plan->d_items, (int)plan->items.size(), s)) != hipSuccess)
       return hip_fail(e, "build D");
   }
   // the host arrays above must outlive the copies
@@ -499,7 +533,8 @@ static otfs_status apply_common(const otfs_plan_t* plan, bool adj, const void* i
   if (plan->total_elems == 0) return OTFS_OK;
   if (!in || !out) return fail(OTFS_E_INVAL, "input and output must be non-null");
   if (in == out) return fail(OTFS_E_INVAL, "input and output must be distinct buffers");
-  hipError_t e = launch_apply(adj, plan->pmax, plan->d_frames, plan->d_items, (int)plan->items.size(),
+  const bool stored = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
+  hipError_t e = launch_apply(adj, stored, plan->d_frames, plan->d_items, (int)plan->items.size(),
                               static_cast<const float2*>(in), static_cast<float2*>(out),
                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, adj ? "apply H^H" : "apply H");
@@ -515,11 +550,13 @@ extern "C" otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y, voi
 
 // the launch sequence of one fused solve: reset, persistent kernel (optionally timed)
 static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s, bool timed) {
-  hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort, s);
+  hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort,
+                              plan->d_qhead, plan->ngroups, s);
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_begin, s)) != hipSuccess) return e;
-  e = launch_cg_fused(plan->pmax, plan->d_frames, plan->d_items, plan->d_sched, plan->d_ranges,
-                      plan->grid, plan->opts.max_iters, B, s, plan->d_abort);
+  e = launch_cg_fused((plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->d_frames, plan->d_items,
+                      plan->d_qitems, plan->d_qrange, plan->d_qhead, plan->ngroups, plan->grid,
+                      plan->opts.max_iters, B, plan->xcd_local, plan->d_abort, s);
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_end, s)) != hipSuccess) return e;
   return hipSuccess;
@@ -581,11 +618,14 @@ extern "C" otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y, voi
   if (y == xhat) return fail(OTFS_E_INVAL, "y and xhat must be distinct buffers");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Bases B{y, static_cast<float2*>(xhat), sym, stats};
-  hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort, s);
+  if (plan->opts.flags & OTFS_D_STORED_BF16)
+    return fail(OTFS_E_UNSUPPORTED, "the plain form synthesises D on the fly only");
+  hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort,
+                              plan->d_qhead, plan->ngroups, s);
   if (e != hipSuccess) return hip_fail(e, "reset");
   for (size_t f = 0; f < plan->frames.size(); ++f) {
-    e = launch_plain_frame(pmax_bucket(plan->frames[f].P), plan->d_frames, (int)f, plan->d_items,
-                           plan->tile_base[f], plan->tiles[f], plan->opts.max_iters, B, s);
+    e = launch_plain_frame(plan->d_frames, (int)f, plan->d_items, plan->tile_base[f],
+                           plan->tiles[f], plan->opts.max_iters, B, s);
     if (e != hipSuccess) return hip_fail(e, "plain CG launch");
   }
   return OTFS_OK;

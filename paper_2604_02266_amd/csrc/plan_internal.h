@@ -24,7 +24,7 @@ struct HostFrame {
 
 // Byte offsets of every region of a plan workspace.
 struct Layout {
-  size_t frames = 0, items = 0, sched = 0, ranges = 0;
+  size_t frames = 0, items = 0, qitems = 0, qrange = 0, qhead = 0, probe = 0;
   size_t rtab = 0, wtab = 0, rtab64 = 0, wtab64 = 0, paths = 0;
   size_t part_pa = 0, part_cc = 0, part_d = 0, bar = 0, st = 0, abort = 0;
   size_t c = 0, p0 = 0, p1 = 0, t = 0, a = 0, u = 0, dtab = 0;
@@ -51,9 +51,20 @@ void wrap_factors(const HostFrame& f, std::vector<double2>& out);
 int default_tile_elems(int64_t total_elems, int cus);
 void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vector<WorkItem>& items,
                 std::vector<int>& tile_base, std::vector<int>& tiles);
-void make_schedule(const std::vector<HostFrame>& frames, const std::vector<WorkItem>& items,
-                   const std::vector<int>& tile_base, const std::vector<int>& tiles, int cap,
-                   std::vector<int32_t>& sched, std::vector<int2>& ranges, int* grid_out);
+// Work queues of the fused kernel.  ngroups groups (one per XCD in XCD-local mode, else
+// one); every frame's tiles go, consecutively, to one group; groups are balanced by work.
+// per_group_cap: workgroups one group can hold resident.  Returns false if some frame has
+// more tiles than that.
+bool make_queues(const std::vector<HostFrame>& frames, const std::vector<int>& tile_base,
+                 const std::vector<int>& tiles, int ngroups, int per_group_cap,
+                 std::vector<int32_t>& qitems, std::vector<int2>& qrange, int* per_group_grid);
+// XCD layout of a device, found once per device by a probe launch.
+struct XcdInfo {
+  int nxcd = 1;          // number of XCDs seen
+  bool round_robin = false;  // workgroup b ran on XCD b % nxcd for every probed b
+};
+otfs_status probe_xcds(int device, void* scratch_dev, hipStream_t s, XcdInfo* out);
+constexpr int kProbeBlocks = 1024;
 
 }  // namespace otfs
 
@@ -61,13 +72,15 @@ struct otfs_plan {
   std::vector<otfs::HostFrame> frames;
   otfs_cg_opts opts{};
   int64_t total_elems = 0;
-  int max_paths = 0, pmax = 4, cus = 256;
+  int max_paths = 0, cus = 256;
   int tile_elems = 0, max_grid_req = 0;
   // tiling (host) and schedule (chosen at bind)
   std::vector<otfs::WorkItem> items;
   std::vector<int> tile_base, tiles;
-  std::vector<int32_t> sched;
-  std::vector<int2> ranges;
+  std::vector<int32_t> qitems;
+  std::vector<int2> qrange;
+  int ngroups = 1;
+  bool xcd_local = false;
   int grid = 0;
   otfs::Layout L;
   // binding
@@ -76,8 +89,9 @@ struct otfs_plan {
   void* ws = nullptr;
   otfs::FrameDev* d_frames = nullptr;
   otfs::WorkItem* d_items = nullptr;
-  int32_t* d_sched = nullptr;
-  int2* d_ranges = nullptr;
+  int32_t* d_qitems = nullptr;
+  int2* d_qrange = nullptr;
+  unsigned* d_qhead = nullptr;
   unsigned* d_abort = nullptr;
   // host copies of the uploaded tables (kept alive across the asynchronous copies)
   std::vector<float2> h_rtab, h_wtab;

@@ -142,13 +142,20 @@ def test_cg_single_64x16_config(otfs):
         _cg_check(_run(otfs, plan, y, form), frames, ops, y, NMSE_TOL, form)
 
 
-@pytest.mark.parametrize("tile_elems,max_grid", [(0, 0), (700, 0), (700, 8), (2048, 3)])
-def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid):
+@pytest.mark.parametrize("tile_elems,max_grid,agent", [(0, 0, 0), (700, 0, 0), (700, 8, 1),
+                                                       (700, 64, 0), (2048, 3, 1),
+                                                       (0, 0, 1)])
+def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent):
     frames = _mixed_frames(11, 9, [(128, 32), (64, 16), (100, 30), (96, 8), (256, 16)],
                            (1, 9), 12, 4)
     ops, xs, y = oracle_batch(frames)
-    say("cg ragged", tile_elems, max_grid)
-    plan = otfs.Plan([f.spec for f in frames], tile_elems=tile_elems, max_grid=max_grid)
+    say("cg ragged", tile_elems, max_grid, "agent" if agent else "xcd")
+    plan = otfs.Plan([f.spec for f in frames], tile_elems=tile_elems, max_grid=max_grid,
+                     flags=otfs.AGENT_BARRIER if agent else 0)
+    inf = plan.info()
+    say("  groups", inf.groups, "xcd_local", inf.xcd_local, "grid", inf.grid)
+    if agent:
+        assert inf.groups == 1 and inf.xcd_local == 0
     _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
 
 
