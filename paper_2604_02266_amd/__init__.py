@@ -18,7 +18,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libotfs.so")
+# OTFS_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("OTFS_LIB") or os.path.join(_HERE, "libotfs.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "otfs.h")
 
 # status codes and flags (include/otfs.h)

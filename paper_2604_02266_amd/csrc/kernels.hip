@@ -20,6 +20,8 @@
 // the operator is a sparse gather, not a dense contraction.
 #include <math.h>
 
+#include <type_traits>
+
 #include "otfs_internal.h"
 
 namespace otfs {
@@ -116,11 +118,12 @@ __device__ __forceinline__ double tile_sum_d(const double* part, int T) {
 // ---------------------------------------------------------------------------------------
 // Two coherence modes.
 //  XCD-local (all workgroups of the frame run on one XCD, whose L2 they share): every
-//  thread waits for its own stores to reach the L2 (s_waitcnt vmcnt(0)), one lane counts
-//  the arrival with an L2 atomic and polls the count with L2 atomics, and after the
-//  workgroup meets again every thread drops its CU's L1 (buffer_inv sc0).  These are the
-//  release / acquire sequences the AMDGPU memory model uses for workgroup scope when the
-//  waves of a workgroup may sit on different CUs of one XCD; the L2 keeps its contents.
+//  thread waits for its own stores to reach the L2 (s_waitcnt vmcnt(0); no L2 write-back,
+//  so the data stays in the shared L2), one lane counts the arrival with an L2 atomic and
+//  polls the count with L2 atomics, and after the workgroup meets again every thread
+//  takes an agent-scope acquire (buffer_inv sc1), which drops this CU's L1.  The
+//  workgroup-scope invalidate (buffer_inv sc0) is not enough: outside threadgroup-split
+//  mode it leaves L1 lines written by other CUs stale (measured).
 //  Agent (fallback, any placement): agent-scope release and acquire fences (L2 write-back
 //  and invalidate, the L2s of different XCDs not being coherent) around an agent-scope
 //  counter.
@@ -128,7 +131,8 @@ __device__ __forceinline__ double tile_sum_d(const double* part, int T) {
 // workgroup has raised the launch-wide abort flag, it gives up and reports failure.
 __device__ __forceinline__ void xcd_release() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void xcd_acquire() {
-  asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc0" ::: "memory");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Current value of a counter kept in the L2 by workgroup-scope atomics.  A plain or
@@ -201,7 +205,7 @@ __device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
 // sink(q, v) receives output element q.  Threads without a column return early; callers
 // put block-wide work after the call.
 // ---------------------------------------------------------------------------------------
-template <int R, bool ADJ, bool STORED, class Src, class Sink>
+template <int R, int U, bool ADJ, bool STORED, class Src, class Sink>
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Src src, Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
@@ -218,60 +222,70 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Sr
       float2 acc[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) acc[i] = make_float2(0.f, 0.f);
-      for (int p = 0; p < P; ++p) {
-        const int2 tn = paths[p];
-        int kk, n;
-        if (!ADJ) {                       // source column <k - tau>_M, wrap count n
-          const int K = k - tn.x;
-          n = K < 0 ? -1 : (K >= M ? 1 : 0);
-          kk = K - n * M;
-        } else {                          // gathered row's column <k + tau>_M
-          const int K = k + tn.x;
-          n = K < 0 ? -1 : (K >= M ? 1 : 0);
-          kk = K - n * M;
-        }
-        float2 cf = make_float2(0.f, 0.f);
-        if (!STORED) {
-          const float2 r = rtab[p * M + (ADJ ? kk : k)];
-          cf = ADJ ? make_float2(r.x, -r.y) : r;
-        }
-        float2 v[R];
-        int qs[R];
+      // NP paths at once: all NP*R gathers are issued before any is consumed
+      auto step = [&](auto npc, int p0) {
+        constexpr int NP = decltype(npc)::value;
+        int kk[NP], nw[NP], nuv[NP];
+        float2 cf[NP];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          if (r0 + i < nrows) {
-            const int l = lb + ty + (r0 + i) * TY;
-            int ls = ADJ ? l + tn.y : l - tn.y;
-            ls += ls < 0 ? N : 0;
-            ls -= ls >= N ? N : 0;
-            qs[i] = ls * M + kk;
-            v[i] = src(qs[i]);
+        for (int u = 0; u < NP; ++u) {
+          const int2 tn = paths[p0 + u];
+          const int K = ADJ ? k + tn.x : k - tn.x;   // H: <k - tau>_M; H^H: <k + tau>_M
+          nw[u] = K < 0 ? -1 : (K >= M ? 1 : 0);     // wrap count
+          kk[u] = K - nw[u] * M;
+          nuv[u] = tn.y;
+          if (!STORED) {
+            const float2 r = rtab[(p0 + u) * M + (ADJ ? kk[u] : k)];
+            cf[u] = ADJ ? make_float2(r.x, -r.y) : r;
           }
         }
+        float2 v[NP][R];
+        float2 d[NP][R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          if (r0 + i < nrows) {
-            const int l = lb + ty + (r0 + i) * TY;
-            float2 c;
-            if (STORED) {
-              if (ADJ) {
-                const float2 d = bf16x2_to_f2(F.dtab[(int64_t)p * E + qs[i]]);
-                c = make_float2(d.x, -d.y);
-              } else {
-                c = bf16x2_to_f2(F.dtab[(int64_t)p * E + (int64_t)l * M + k]);
-              }
-            } else {
-              c = cf;
-              if (n != 0) {   // forward: W[source row]^n; adjoint: W[own row]^w
-                float2 w = wtab[ADJ ? l : qs[i] / M];
-                if (n < 0) w.y = -w.y;
-                c = cmulf(c, w);
-              }
+        for (int u = 0; u < NP; ++u) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            if (r0 + i < nrows) {
+              const int l = lb + ty + (r0 + i) * TY;
+              int ls = ADJ ? l + nuv[u] : l - nuv[u];
+              ls += ls < 0 ? N : 0;
+              ls -= ls >= N ? N : 0;
+              const int qs = ls * M + kk[u];
+              v[u][i] = src(qs);
+              if (STORED)
+                d[u][i] = bf16x2_to_f2(
+                    F.dtab[(int64_t)(p0 + u) * E + (ADJ ? (int64_t)qs : (int64_t)l * M + k)]);
             }
-            cmacf(acc[i], c, v[i]);
           }
         }
-      }
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            if (r0 + i < nrows) {
+              float2 c;
+              if (STORED) {
+                c = ADJ ? make_float2(d[u][i].x, -d[u][i].y) : d[u][i];
+              } else {
+                c = cf[u];
+                if (nw[u] != 0) {   // H: W[source row]^n;  H^H: W[own row]^w
+                  const int l = lb + ty + (r0 + i) * TY;
+                  int ls = l - nuv[u];
+                  ls += ls < 0 ? N : 0;
+                  ls -= ls >= N ? N : 0;
+                  float2 w = wtab[ADJ ? l : ls];
+                  if (nw[u] < 0) w.y = -w.y;
+                  c = cmulf(c, w);
+                }
+              }
+              cmacf(acc[i], c, v[u][i]);
+            }
+          }
+        }
+      };
+      int p = 0;
+      for (; p + U <= P; p += U) step(std::integral_constant<int, U>{}, p);
+      for (; p < P; ++p) step(std::integral_constant<int, 1>{}, p);
 #pragma unroll
       for (int i = 0; i < R; ++i)
         if (r0 + i < nrows) sink((lb + ty + (r0 + i) * TY) * M + k, acc[i]);
@@ -326,8 +340,15 @@ __device__ __forceinline__ void band_apply64(const FrameDev& F, int lb, int le, 
   }
 }
 
-constexpr int kRows = 8;     // rows in flight per thread in the FP32 gathers
-constexpr int kRows64 = 4;   // and in the FP64 refresh gathers
+#ifndef OTFS_ROWS
+#define OTFS_ROWS 4
+#endif
+#ifndef OTFS_PATHS
+#define OTFS_PATHS 2
+#endif
+constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
+constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
+constexpr int kRows64 = 4;   // rows per thread chunk in the FP64 refresh gathers
 
 // ---------------------------------------------------------------------------------------
 // hard decisions (Eq. demod): nearest square-QAM level per axis, ties to the upper level
@@ -416,7 +437,7 @@ struct LaunchCtx {
   int xcd_local;     // barrier coherence mode (see frame_barrier)
 };
 
-template <bool STORED>
+template <bool STORED, bool REFRESH>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                         const LaunchCtx& L, float* red, double* redd, int* sflag) {
   const FrameVecs V = frame_vecs(F, B);
@@ -426,10 +447,10 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   const int lb = wi.l_begin, le = wi.l_end;
   const int64_t q0 = (int64_t)lb * M, q1 = (int64_t)le * M;
   const float lam = F.lam;
-  float2* __restrict__ cvec = F.c;
-  float2* __restrict__ tvec = F.t;
-  float2* __restrict__ avec = F.a;
-  float2* __restrict__ xvec = V.x;
+  float2* cvec = F.c;
+  float2* tvec = F.t;
+  float2* avec = F.a;
+  float2* xvec = V.x;
   unsigned nbar = 0;
   auto bar = [&]() -> bool {
     if (T == 1) {
@@ -454,7 +475,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line) ----
   if (!s.init) {
     float acc = 0.f;
-    band_apply<kRows, true, STORED>(
+    band_apply<kRows, kPaths, true, STORED>(
         F, lb, le, [&](int i) { return load_y(V.y, i, V.ybf16); },
         [&](int q, float2 v) {
           cvec[q] = v;
@@ -484,35 +505,27 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
 
   for (int step = 0; step < budget; ++step) {
     const int xi = s.iter + 1;
-    float2* __restrict__ pold = s.pbuf ? F.p1 : F.p0;
-    const bool dirp = (s.pending & 2) != 0, xp = (s.pending & 1) != 0;
-    float2* __restrict__ pnew = dirp ? (s.pbuf ? F.p0 : F.p1) : pold;
-    const float al = s.alpha, be = s.beta;
+    float2* pold = s.pbuf ? F.p1 : F.p0;
+    float2* pnew = s.pbuf ? F.p0 : F.p1;
+    // iteration 1 has no pending update: beta = 0 gives p_new = c = b exactly
+    const bool xp = (s.pending & 1) != 0;
+    const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
 
     // ---- A: deferred updates of the band, t = H p ----
-    if (dirp) {
-      band_apply<kRows, false, STORED>(
-          F, lb, le, [&](int i) { return axpyf(be, pold[i], cvec[i]); },
-          [&](int q, float2 v) {
-            tvec[q] = v;
-            const float2 po = pold[q];
-            pnew[q] = axpyf(be, po, cvec[q]);
-            if (xp) xvec[q] = axpyf(al, po, xvec[q]);
-          });
-    } else {
-      band_apply<kRows, false, STORED>(
-          F, lb, le, [&](int i) { return pold[i]; },
-          [&](int q, float2 v) {
-            tvec[q] = v;
-            if (xp) xvec[q] = axpyf(al, pold[q], xvec[q]);
-          });
-    }
+    band_apply<kRows, kPaths, false, STORED>(
+        F, lb, le, [&](int i) { return axpyf(be, pold[i], cvec[i]); },
+        [&](int q, float2 v) {
+          tvec[q] = v;
+          const float2 po = pold[q];
+          pnew[q] = axpyf(be, po, cvec[q]);
+          if (xp) xvec[q] = axpyf(al, po, xvec[q]);
+        });
     if (!bar()) return fail_timeout();
 
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
       float acc = 0.f;
-      band_apply<kRows, true, STORED>(
+      band_apply<kRows, kPaths, true, STORED>(
           F, lb, le, [&](int i) { return tvec[i]; },
           [&](int q, float2 v) {
             const float2 p = pnew[q];
@@ -525,7 +538,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       if (threadIdx.x == 0) F.part_pa[wi.tile] = bs;
     }
     if (!bar()) return fail_timeout();
-    s.pbuf = (pnew == F.p1) ? 1 : 0;
+    s.pbuf ^= 1;
     s.pending = 0;                                   // both deferred updates are applied
 
     const float den = (float)tile_sum(F.part_pa, T);
@@ -556,7 +569,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     bool xpend = true;                               // x += alpha p_new still to do
 
     // ---- FP64 true-residual refresh ----
-    if (F.refresh_every > 0 && xi % F.refresh_every == 0 && xi < F.max_iters &&
+    if (REFRESH && F.refresh_every > 0 && xi % F.refresh_every == 0 && xi < F.max_iters &&
         isfinite(cn_new)) {
       // R1: u = y - H (x + alpha p) in FP64 (x itself is not written while others read it)
       band_apply64<kRows64, false>(
@@ -614,7 +627,7 @@ __device__ __forceinline__ int xcc_id() {
 // workgroups sharing one L2.  A frame's tiles are consecutive in its group's queue and a
 // group never has fewer resident workgroups than a frame has tiles, so the first frame
 // with an untaken tile is always being completed: the per-frame barriers cannot deadlock.
-template <bool STORED>
+template <bool STORED, bool REFRESH>
 __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict__ frames,
                                                      const WorkItem* __restrict__ items,
                                                      const int32_t* __restrict__ qitems,
@@ -625,8 +638,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict_
   __shared__ double redd[kWaves];
   __shared__ int sflag;
   __shared__ int s_item;
+  // Data this launch reads may have been written by other kernels, copies or XCDs since
+  // this XCD's L2 last saw it, and the per-frame barriers of XCD-local mode never
+  // invalidate the L2: take one device-wide acquire before the first read, and publish
+  // this workgroup's results device-wide before it exits.
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const int g = L.xcd_local ? xcc_id() : 0;
-  if (g >= ngroups) return;
+  if (g >= ngroups) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    return;
+  }
   const int2 r = qrange[g];
   for (;;) {
     if (threadIdx.x == 0) {
@@ -638,9 +659,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict_
     __syncthreads();
     if (it < 0) break;
     const WorkItem wi = items[it];
-    cg_item<STORED>(frames[wi.frame], wi, budget, B, L, red, redd, &sflag);
+    cg_item<STORED, REFRESH>(frames[wi.frame], wi, budget, B, L, red, redd, &sflag);
     __syncthreads();
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
 
 __global__ void k_xcc_probe(int* out) {
@@ -659,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ f
   const FrameDev& F = frames[wi.frame];
   const float2* __restrict__ src = in + F.off;
   float2* __restrict__ dst = out + F.off;
-  band_apply<kRows, ADJ, STORED>(
+  band_apply<kRows, kPaths, ADJ, STORED>(
       F, wi.l_begin, wi.l_end, [&](int i) { return src[i]; },
       [&](int q, float2 v) { dst[q] = v; });
 }
@@ -723,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_init(const FrameDev* __restric
   const FrameDev& F = frames[f];
   const FrameVecs V = frame_vecs(F, B);
   float acc = 0.f;
-  band_apply<kRows, true, false>(
+  band_apply<kRows, kPaths, true, false>(
       F, wi.l_begin, wi.l_end, [&](int i) { return load_y(V.y, i, V.ybf16); },
       [&](int q, float2 v) {
         F.c[q] = v;
@@ -756,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_H(const FrameDev* __restrict__
   const FrameDev& F = frames[f];
   if (F.st->status != OTFS_FRAME_RUNNING) return;
   const WorkItem wi = items[blockIdx.x];
-  band_apply<kRows, false, false>(
+  band_apply<kRows, kPaths, false, false>(
       F, wi.l_begin, wi.l_end, [&](int i) { return F.p0[i]; },
       [&](int q, float2 v) { F.t[q] = v; });
 }
@@ -769,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_HH(const FrameDev* __restrict_
   const WorkItem wi = items[blockIdx.x];
   const float lam = F.lam;
   float acc = 0.f;
-  band_apply<kRows, true, false>(
+  band_apply<kRows, kPaths, true, false>(
       F, wi.l_begin, wi.l_end, [&](int i) { return F.t[i]; },
       [&](int q, float2 v) {
         const float2 p = F.p0[q];
@@ -903,25 +925,36 @@ static uint64_t wallclock_timeout_ticks() {
   return ticks;
 }
 
-hipError_t launch_cg_fused(bool stored, const FrameDev* frames, const WorkItem* items,
-                           const int32_t* qitems, const int2* qrange, unsigned* qhead,
-                           int ngroups, int grid, int budget, Bases bases, bool xcd_local,
-                           unsigned* abort_flag, hipStream_t s) {
+template <bool STORED, bool REFRESH>
+static void launch_fused_t(const FrameDev* frames, const WorkItem* items, const int32_t* qitems,
+                           const int2* qrange, unsigned* qhead, int ngroups, int grid, int budget,
+                           const Bases& bases, const LaunchCtx& L, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_fused<STORED, REFRESH>), dim3(grid), dim3(kBlock), 0, s, frames, items,
+                     qitems, qrange, qhead, ngroups, budget, bases, L);
+}
+
+hipError_t launch_cg_fused(bool stored, bool refresh, const FrameDev* frames,
+                           const WorkItem* items, const int32_t* qitems, const int2* qrange,
+                           unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
+                           bool xcd_local, unsigned* abort_flag, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   LaunchCtx L{abort_flag, wallclock_timeout_ticks(), xcd_local ? 1 : 0};
-  if (stored)
-    hipLaunchKernelGGL((k_cg_fused<true>), dim3(grid), dim3(kBlock), 0, s, frames, items, qitems,
-                       qrange, qhead, ngroups, budget, bases, L);
-  else
-    hipLaunchKernelGGL((k_cg_fused<false>), dim3(grid), dim3(kBlock), 0, s, frames, items, qitems,
-                       qrange, qhead, ngroups, budget, bases, L);
+  if (stored) {
+    if (refresh) launch_fused_t<true, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+    else launch_fused_t<true, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+  } else {
+    if (refresh) launch_fused_t<false, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+    else launch_fused_t<false, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+  }
   return hipGetLastError();
 }
 
-int fused_blocks_per_cu(bool stored) {
+int fused_blocks_per_cu(bool stored, bool refresh) {
   int n = 0;
-  const void* fn = stored ? reinterpret_cast<const void*>(&k_cg_fused<true>)
-                          : reinterpret_cast<const void*>(&k_cg_fused<false>);
+  const void* fn = stored ? (refresh ? reinterpret_cast<const void*>(&k_cg_fused<true, true>)
+                                     : reinterpret_cast<const void*>(&k_cg_fused<true, false>))
+                          : (refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true>)
+                                     : reinterpret_cast<const void*>(&k_cg_fused<false, false>));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, 0) != hipSuccess) n = 0;
   return n;
 }

@@ -100,12 +100,12 @@ hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_fla
 // XCD-local coherence; otherwise there is one group and agent-scope barriers.
 // abort_flag: zero before the launch; raised by a workgroup whose barrier wait timed out
 // so that every other wait ends at once.  budget = iterations per frame in this launch.
-hipError_t launch_cg_fused(bool stored, const FrameDev* frames, const WorkItem* items,
-                           const int32_t* qitems, const int2* qrange, unsigned* qhead,
-                           int ngroups, int grid, int budget, Bases bases, bool xcd_local,
-                           unsigned* abort_flag, hipStream_t s);
+hipError_t launch_cg_fused(bool stored, bool refresh, const FrameDev* frames,
+                           const WorkItem* items, const int32_t* qitems, const int2* qrange,
+                           unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
+                           bool xcd_local, unsigned* abort_flag, hipStream_t s);
 // Workgroups of the fused kernel that fit on one CU at once (occupancy).
-int fused_blocks_per_cu(bool stored);
+int fused_blocks_per_cu(bool stored, bool refresh);
 
 // out[b] = XCC id of workgroup b, for b < nblocks.
 hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);

@@ -377,7 +377,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
 
   // work queues of the fused kernel (need the occupancy and XCD layout of this device)
   const bool stored_mode = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
-  const int bpc = std::max(1, fused_blocks_per_cu(stored_mode));
+  const int bpc = std::max(1, fused_blocks_per_cu(stored_mode, plan->opts.refresh_every > 0));
   int cus = plan->cus;
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
@@ -554,7 +554,8 @@ static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s
                               plan->d_qhead, plan->ngroups, s);
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_begin, s)) != hipSuccess) return e;
-  e = launch_cg_fused((plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->d_frames, plan->d_items,
+  e = launch_cg_fused((plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->opts.refresh_every > 0,
+                      plan->d_frames, plan->d_items,
                       plan->d_qitems, plan->d_qrange, plan->d_qhead, plan->ngroups, plan->grid,
                       plan->opts.max_iters, B, plan->xcd_local, plan->d_abort, s);
   if (e != hipSuccess) return e;

@@ -144,7 +144,8 @@ def test_cg_single_64x16_config(otfs):
 
 @pytest.mark.parametrize("tile_elems,max_grid,agent", [(0, 0, 0), (700, 0, 0), (700, 8, 1),
                                                        (700, 64, 0), (2048, 3, 1),
-                                                       (0, 0, 1)])
+                                                       (0, 0, 1), (350, 0, 0), (200, 0, 0),
+                                                       (200, 0, 1)])
 def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent):
     frames = _mixed_frames(11, 9, [(128, 32), (64, 16), (100, 30), (96, 8), (256, 16)],
                            (1, 9), 12, 4)
@@ -157,6 +158,19 @@ def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent):
     if agent:
         assert inf.groups == 1 and inf.xcd_local == 0
     _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
+
+
+def test_cg_fresh_plans_reusing_memory(otfs):
+    # Regression: each new plan gets memory that earlier plans (other frame-to-XCD
+    # assignments) used; stale cache lines must not leak into the solve.
+    frames = _mixed_frames(11, 9, [(128, 32), (64, 16), (100, 30), (96, 8), (256, 16)],
+                           (1, 9), 12, 4)
+    ops, xs, y = oracle_batch(frames)
+    for rep, te in enumerate([700, 350, 200, 700, 1024, 200]):
+        say("cg fresh plan", rep, "tile_elems", te)
+        plan = otfs.Plan([f.spec for f in frames], tile_elems=te)
+        _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
+        del plan
 
 
 def test_cg_plain_matches_oracle_and_fused(otfs):
