@@ -107,7 +107,8 @@ enum {
   OTFS_FRAME_CAPPED = 2,      /* max_iters reached                                          */
   OTFS_FRAME_NONFINITE = 3,   /* a NaN/Inf appeared; x_hat holds the last finite iterate    */
   OTFS_FRAME_BREAKDOWN = 4,   /* Re(p^H a_p) <= 0; x_hat holds the last iterate             */
-  OTFS_FRAME_TIMEOUT = 5      /* an in-kernel wait exceeded its limit (should not happen)    */
+  OTFS_FRAME_TIMEOUT = 5,     /* an in-kernel wait exceeded its limit (should not happen)    */
+  OTFS_FRAME_DRYRUN = 6       /* server created on device -1: scheduled only, no arithmetic  */
 };
 
 /* Per-frame result, written to device memory by the solver (16 bytes). */
@@ -157,6 +158,7 @@ typedef struct {
   int32_t tile_elems;       /* target elements per workgroup tile                           */
   int32_t groups;           /* work-queue groups of the fused launch (XCDs, or 1)           */
   int32_t xcd_local;        /* 1: frames stay on one XCD (see OTFS_AGENT_BARRIER)           */
+  int32_t lds_bytes;        /* LDS per workgroup for staged gather windows (0: none staged) */
 } otfs_plan_info_t;
 otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
 
@@ -164,6 +166,13 @@ otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
  * rule) and the workgroup cap of the fused kernel (0 = occupancy limit).  Takes effect at
  * the next otfs_plan_bind.  Used by the autotuner. */
 otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elems, int32_t max_grid);
+
+/* LDS budget per workgroup for staging the gather windows of H and H^H (Eqs. sparse_mvm,
+ * sparse_herm_mvm): a workgroup copies the source rows and columns its block of outputs
+ * can reach into LDS, then does every path's gather from there.  Frames whose smallest
+ * window exceeds the budget gather straight from memory.  0 disables staging; at most
+ * 65536.  Default 40 KiB.  Takes effect at the next otfs_plan_bind. */
+otfs_status otfs_plan_set_staging(otfs_plan_t* plan, int32_t lds_bytes);
 
 /* ------------------------------------------------------------------------------------ */
 /* Operator applications (Eq. sparse_mvm and Eq. sparse_herm_mvm), every frame of the   */
@@ -200,16 +209,24 @@ otfs_status otfs_plan_kernel_ms(otfs_plan_t* plan, float* ms);
 typedef struct otfs_server otfs_server_t;
 
 /* Start a server on `device`.  pool_dev / pool_bytes: caller-owned device memory that
- * bounds the CG state of admitted frames (the HBM admission budget).  A scheduler thread
- * admits queued frames while their state fits the pool, runs steps of `step_iters` CG
- * iterations over all admitted frames in one fused launch, and retires frames as they
- * finish; frames that arrive meanwhile join at the next step.  opts as for otfs_plan
- * (NULL = defaults). */
+ * bounds the CG state of admitted frames (the HBM admission budget); a fixed control
+ * region at its start holds the step descriptors.  A scheduler thread admits queued
+ * frames in arrival order while their state fits the pool, runs steps of `step_iters`
+ * (>= 1) CG iterations over all admitted frames in one fused launch, and retires frames as
+ * they finish; frames that arrive meanwhile join at the next step, so their work overlaps
+ * on the device with frames already in flight.  A frame's tiling depends only on its own
+ * shape, so its result is the same alone or among others.  opts as for otfs_plan (NULL =
+ * defaults; the bf16 flags are not supported here).  device = -1 starts a dry-run server
+ * that schedules and completes frames without any device work (x_hat = 0, status
+ * OTFS_FRAME_DRYRUN), for testing admission on hosts without a GPU; pool_dev is then
+ * not touched. */
 otfs_status otfs_server_create(int device, void* pool_dev, size_t pool_bytes,
                                const otfs_cg_opts* opts, int32_t step_iters,
                                otfs_server_t** out);
 
-/* Queue one frame; y_host (M*N complex64, host memory) is copied before returning. */
+/* Queue one frame; y_host (M*N complex64, host memory) is copied before returning.
+ * OTFS_E_BUDGET if the frame's state can never fit the pool; OTFS_E_DEVICE once the server
+ * has failed (see otfs_last_error). */
 otfs_status otfs_submit(otfs_server_t* srv, const otfs_frame_desc* frame, const void* y_host,
                         uint64_t* ticket);
 
@@ -218,6 +235,12 @@ otfs_status otfs_submit(otfs_server_t* srv, const otfs_frame_desc* frame, const 
  * submit to completion in nanoseconds (nullable) and forgets the ticket. */
 otfs_status otfs_poll(otfs_server_t* srv, uint64_t ticket, void* xhat_host, uint8_t* sym_host,
                       otfs_frame_stats* stats, uint64_t* latency_ns);
+
+/* Pool bytes one frame of this shape holds while admitted (frame_bytes, nullable) and the
+ * size of the server's fixed control region at the start of the pool (control_bytes,
+ * nullable): a pool of control_bytes + n * frame_bytes admits n such frames at once. */
+otfs_status otfs_server_frame_bytes(otfs_server_t* srv, const otfs_frame_desc* frame,
+                                    size_t* frame_bytes, size_t* control_bytes);
 
 typedef struct {
   uint64_t submitted, completed, steps;

@@ -29,7 +29,8 @@ Y_BF16 = 1 << 1
 USE_GRAPH = 1 << 2
 TIME_KERNEL = 1 << 3
 AGENT_BARRIER = 1 << 4
-FRAME_RUNNING, FRAME_CONVERGED, FRAME_CAPPED, FRAME_NONFINITE, FRAME_BREAKDOWN, FRAME_TIMEOUT = range(6)
+(FRAME_RUNNING, FRAME_CONVERGED, FRAME_CAPPED, FRAME_NONFINITE, FRAME_BREAKDOWN, FRAME_TIMEOUT,
+ FRAME_DRYRUN) = range(7)
 
 
 class OtfsError(RuntimeError):
@@ -60,7 +61,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("nframes", ctypes.c_int32), ("total_elems", ctypes.c_int64),
                 ("grid", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("max_paths", ctypes.c_int32), ("tile_elems", ctypes.c_int32),
-                ("groups", ctypes.c_int32), ("xcd_local", ctypes.c_int32)]
+                ("groups", ctypes.c_int32), ("xcd_local", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -100,6 +102,7 @@ def lib() -> ctypes.CDLL:
         "otfs_plan_free": (st, [_vp]),
         "otfs_plan_info": (st, [_vp, ctypes.POINTER(PlanInfo)]),
         "otfs_plan_set_tiling": (st, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "otfs_plan_set_staging": (st, [_vp, ctypes.c_int32]),
         "otfs_apply_H": (st, [_vp, _vp, _vp, _vp]),
         "otfs_apply_HH": (st, [_vp, _vp, _vp, _vp]),
         "otfs_lmmse_cg": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
@@ -112,6 +115,9 @@ def lib() -> ctypes.CDLL:
         "otfs_poll": (st, [_vp, ctypes.c_uint64, _vp, _vp, ctypes.POINTER(FrameStats),
                            ctypes.POINTER(ctypes.c_uint64)]),
         "otfs_server_stats": (st, [_vp, ctypes.POINTER(ServerStats)]),
+        "otfs_server_frame_bytes": (st, [_vp, ctypes.POINTER(FrameDesc),
+                                         ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
         "otfs_server_free": (st, [_vp]),
     }
     for name, (res, args) in sig.items():
@@ -176,7 +182,7 @@ class Plan:
 
     def __init__(self, frames: Sequence, max_iters: int = 50, rel_tol: float = 1e-6,
                  refresh_every: int = 0, flags: int = 0, tile_elems: int = 0,
-                 max_grid: int = 0, bind: bool = True):
+                 max_grid: int = 0, stage_bytes: Optional[int] = None, bind: bool = True):
         self._lib = lib()
         self.frames = list(frames)
         self.opts = make_opts(max_iters, rel_tol, refresh_every, flags)
@@ -188,6 +194,8 @@ class Plan:
         self.ws = None
         if tile_elems or max_grid:
             _check(self._lib.otfs_plan_set_tiling(self._h, int(tile_elems), int(max_grid)))
+        if stage_bytes is not None:
+            _check(self._lib.otfs_plan_set_staging(self._h, int(stage_bytes)))
         if bind:
             self.bind()
 
@@ -300,6 +308,102 @@ class Plan:
         ms = ctypes.c_float()
         _check(self._lib.otfs_plan_kernel_ms(self._h, ctypes.byref(ms)))
         return float(ms.value)
+
+
+class Server:
+    """Continuous-batching server: otfs_server_create over a torch-owned pool.
+
+    device=-1 gives a dry run (scheduling only, no device work, no torch needed).
+    """
+
+    def __init__(self, pool_bytes: int, max_iters: int = 50, rel_tol: float = 1e-6,
+                 refresh_every: int = 0, flags: int = 0, step_iters: int = 10,
+                 device: Optional[int] = None):
+        self._lib = lib()
+        self.opts = make_opts(max_iters, rel_tol, refresh_every, flags)
+        self.pool = None
+        ptr = 0
+        if device is None:
+            device = _torch().cuda.current_device()
+        if device >= 0:
+            torch = _torch()
+            raw = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8,
+                              device=f"cuda:{device}")
+            ptr = raw.data_ptr() + (-raw.data_ptr()) % 256
+            self.pool = raw
+        h = _vp()
+        _check(self._lib.otfs_server_create(int(device), _vp(ptr), int(pool_bytes),
+                                            ctypes.byref(self.opts), int(step_iters),
+                                            ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.otfs_server_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, frame, y) -> int:
+        """Queue one frame; y: host complex64 array of M*N values (copied)."""
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.complex64).reshape(-1))
+        if y.size != int(frame.M) * int(frame.N):
+            raise ValueError(f"y: need {int(frame.M) * int(frame.N)} values, got {y.size}")
+        descs = _Descs([frame])
+        t = ctypes.c_uint64()
+        _check(self._lib.otfs_submit(self._h, descs.arr, _vp(y.ctypes.data), ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int, frame):
+        """None while running; else (xhat, sym or None, FrameStats, latency_s)."""
+        E = int(frame.M) * int(frame.N)
+        x = np.empty(E, dtype=np.complex64)
+        sym = np.empty(E, dtype=np.uint8) if int(getattr(frame, "qam", 0) or 0) > 0 else None
+        st = FrameStats()
+        lat = ctypes.c_uint64()
+        status = self._lib.otfs_poll(self._h, ctypes.c_uint64(ticket), _vp(x.ctypes.data),
+                                     _vp(sym.ctypes.data) if sym is not None else None,
+                                     ctypes.byref(st), ctypes.byref(lat))
+        if status == E_AGAIN:
+            return None
+        _check(status)
+        return x, sym, st, lat.value * 1e-9
+
+    def wait(self, ticket: int, frame, timeout: float = 60.0, sleep: float = 1e-4):
+        import time
+        t_end = time.monotonic() + timeout
+        while True:
+            r = self.poll(ticket, frame)
+            if r is not None:
+                return r
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+            time.sleep(sleep)
+
+    def frame_bytes(self, frame):
+        """(pool bytes one admitted frame of this shape holds, control region bytes)."""
+        fb = ctypes.c_size_t()
+        cb = ctypes.c_size_t()
+        descs = _Descs([frame])
+        _check(self._lib.otfs_server_frame_bytes(self._h, descs.arr, ctypes.byref(fb),
+                                                 ctypes.byref(cb)))
+        return int(fb.value), int(cb.value)
+
+    def stats(self) -> ServerStats:
+        out = ServerStats()
+        _check(self._lib.otfs_server_stats(self._h, ctypes.byref(out)))
+        return out
 
 
 def stats_numpy(stats) -> np.ndarray:

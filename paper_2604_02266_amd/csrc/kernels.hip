@@ -205,6 +205,16 @@ __device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
 // sink(q, v) receives output element q.  Threads without a column return early; callers
 // put block-wide work after the call.
 // ---------------------------------------------------------------------------------------
+#ifndef OTFS_ROWS
+#define OTFS_ROWS 4
+#endif
+#ifndef OTFS_PATHS
+#define OTFS_PATHS 2
+#endif
+constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
+constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
+constexpr int kRows64 = 4;   // rows per thread chunk in the FP64 refresh gathers
+
 template <int R, int U, bool ADJ, bool STORED, class Src, class Sink>
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Src src, Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
@@ -293,6 +303,133 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Sr
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// LDS-staged band application (frames with F.skc > 0, coefficients synthesised).
+//
+// The band is processed in blocks of ssb rows x skc delay columns.  For one block the
+// workgroup first copies into LDS every source element its outputs can reach -- the rows
+// shifted by [nu_lo, nu_hi] and the columns shifted by [tau_lo, tau_hi] (whole rows when
+// skc = M, all N rows when the row window wraps the frame) -- with coalesced loads issued
+// in batches, then runs every path's gather from LDS.  The staged value is stage(i) of
+// the source element, computed once per element (phase A stages c + beta p).
+// ---------------------------------------------------------------------------------------
+constexpr int kStageBatch = 8;   // staging loads in flight per thread
+
+template <bool ADJ, class Stage, class Sink>
+__device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, float2* lds,
+                                             Stage stage, Sink sink) {
+  const int M = F.M, N = F.N, P = F.P;
+  const int KC = F.skc, SB = F.ssb;
+  const int dtau = F.tau_hi - F.tau_lo, dnu = F.nu_hi - F.nu_lo;
+  const bool full_cols = KC >= M;
+  const int TXc = KC < kBlock ? KC : kBlock;
+  const int TYc = kBlock / TXc;
+  const int tx = threadIdx.x % TXc, ty = threadIdx.x / TXc;
+  const bool active = ty < TYc;
+  const int2* __restrict__ paths = F.paths;
+  const float2* __restrict__ rtab = F.rtab;
+  const float2* __restrict__ wtab = F.wtab;
+  for (int sb0 = lb; sb0 < le; sb0 += SB) {
+    const int sbn = min(SB, le - sb0);
+    const bool full_rows = sbn + dnu >= N;
+    const int WR = full_rows ? N : sbn + dnu;
+    const int row0 = full_rows ? 0 : (ADJ ? sb0 + F.nu_lo : sb0 - F.nu_hi);
+    for (int k0 = 0; k0 < M; k0 += KC) {
+      const int kcn = min(KC, M - k0);
+      const int WC = full_cols ? M : kcn + dtau;
+      const int col0 = full_cols ? 0 : (ADJ ? k0 + F.tau_lo : k0 - F.tau_hi);
+      const int nwin = WR * WC;
+      const float inv_wc = 1.0f / (float)WC;
+      __syncthreads();                         // the previous block's readers are done
+      for (int e0 = 0; e0 < nwin; e0 += kBlock * kStageBatch) {
+        float2 v[kStageBatch];
+        int at[kStageBatch];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) {
+          const int e = e0 + j * kBlock + (int)threadIdx.x;
+          at[j] = -1;
+          if (e < nwin) {
+            int r = (int)((float)e * inv_wc);
+            int c = e - r * WC;
+            if (c < 0) { --r; c += WC; }
+            if (c >= WC) { ++r; c -= WC; }
+            int sr = row0 + r;
+            sr += sr < 0 ? N : 0;
+            sr -= sr >= N ? N : 0;
+            int sc = col0 + c;
+            sc += sc < 0 ? M : 0;
+            sc -= sc >= M ? M : 0;
+            v[j] = stage(sr * M + sc);
+            at[j] = e;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j)
+          if (at[j] >= 0) lds[at[j]] = v[j];
+      }
+      __syncthreads();
+      if (!active) continue;
+      for (int cc = tx; cc < kcn; cc += TXc) {
+        const int k = k0 + cc;
+        float2 acc[kStageRows];
+#pragma unroll
+        for (int i = 0; i < kStageRows; ++i) acc[i] = make_float2(0.f, 0.f);
+        for (int p = 0; p < P; ++p) {
+          const int2 tn = paths[p];
+          const int K = ADJ ? k + tn.x : k - tn.x;
+          const int n = K < 0 ? -1 : (K >= M ? 1 : 0);
+          const int kk = K - n * M;
+          const float2 r = rtab[p * M + (ADJ ? kk : k)];
+          const float2 cf = ADJ ? make_float2(r.x, -r.y) : r;
+          const int lc = full_cols ? kk : (ADJ ? cc + (tn.x - F.tau_lo) : cc + (F.tau_hi - tn.x));
+#pragma unroll
+          for (int i = 0; i < kStageRows; ++i) {
+            const int rr = ty + i * TYc;
+            if (rr < sbn) {
+              const int l = sb0 + rr;
+              int lr;
+              if (full_rows) {
+                lr = ADJ ? l + tn.y : l - tn.y;
+                lr += lr < 0 ? N : 0;
+                lr -= lr >= N ? N : 0;
+              } else {
+                lr = ADJ ? rr + (tn.y - F.nu_lo) : rr + (F.nu_hi - tn.y);
+              }
+              const float2 val = lds[lr * WC + lc];
+              float2 c = cf;
+              if (n != 0) {   // H: W[source row]^n;  H^H: W[own row]^w
+                int ls = l - tn.y;
+                ls += ls < 0 ? N : 0;
+                ls -= ls >= N ? N : 0;
+                float2 w = wtab[ADJ ? l : ls];
+                if (n < 0) w.y = -w.y;
+                c = cmulf(c, w);
+              }
+              cmacf(acc[i], c, val);
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kStageRows; ++i) {
+          const int rr = ty + i * TYc;
+          if (rr < sbn) sink((sb0 + rr) * M + k, acc[i]);
+        }
+      }
+    }
+  }
+}
+
+// Band application of H / H^H: staged through LDS when the frame's geometry allows it,
+// gathered straight from memory otherwise.
+template <bool ADJ, bool STORED, class Src, class Sink>
+__device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, float2* lds,
+                                           Src src, Sink sink) {
+  if (!STORED && F.skc > 0 && lds != nullptr)
+    staged_apply<ADJ>(F, lb, le, lds, src, sink);
+  else
+    band_apply<kRows, kPaths, ADJ, STORED>(F, lb, le, src, sink);
+}
+
 // FP64 version (coefficients from the FP64 tables) for the true-residual refresh.
 template <int R, bool ADJ, class Src, class Sink>
 __device__ __forceinline__ void band_apply64(const FrameDev& F, int lb, int le, Src src,
@@ -340,15 +477,6 @@ __device__ __forceinline__ void band_apply64(const FrameDev& F, int lb, int le, 
   }
 }
 
-#ifndef OTFS_ROWS
-#define OTFS_ROWS 4
-#endif
-#ifndef OTFS_PATHS
-#define OTFS_PATHS 2
-#endif
-constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
-constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
-constexpr int kRows64 = 4;   // rows per thread chunk in the FP64 refresh gathers
 
 // ---------------------------------------------------------------------------------------
 // hard decisions (Eq. demod): nearest square-QAM level per axis, ties to the upper level
@@ -439,7 +567,7 @@ struct LaunchCtx {
 
 template <bool STORED, bool REFRESH>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
-                        const LaunchCtx& L, float* red, double* redd, int* sflag) {
+                        const LaunchCtx& L, float* red, double* redd, int* sflag, float2* lds) {
   const FrameVecs V = frame_vecs(F, B);
   FrameState s = *F.st;
   if (s.status != OTFS_FRAME_RUNNING) return;
@@ -475,8 +603,8 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line) ----
   if (!s.init) {
     float acc = 0.f;
-    band_apply<kRows, kPaths, true, STORED>(
-        F, lb, le, [&](int i) { return load_y(V.y, i, V.ybf16); },
+    apply_band<true, STORED>(
+        F, lb, le, lds, [&](int i) { return load_y(V.y, i, V.ybf16); },
         [&](int q, float2 v) {
           cvec[q] = v;
           F.p0[q] = v;
@@ -512,8 +640,8 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
 
     // ---- A: deferred updates of the band, t = H p ----
-    band_apply<kRows, kPaths, false, STORED>(
-        F, lb, le, [&](int i) { return axpyf(be, pold[i], cvec[i]); },
+    apply_band<false, STORED>(
+        F, lb, le, lds, [&](int i) { return axpyf(be, pold[i], cvec[i]); },
         [&](int q, float2 v) {
           tvec[q] = v;
           const float2 po = pold[q];
@@ -525,8 +653,8 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
       float acc = 0.f;
-      band_apply<kRows, kPaths, true, STORED>(
-          F, lb, le, [&](int i) { return tvec[i]; },
+      apply_band<true, STORED>(
+          F, lb, le, lds, [&](int i) { return tvec[i]; },
           [&](int q, float2 v) {
             const float2 p = pnew[q];
             const float2 a = axpyf(lam, p, v);
@@ -638,6 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict_
   __shared__ double redd[kWaves];
   __shared__ int sflag;
   __shared__ int s_item;
+  extern __shared__ float2 stage_lds[];
   // Data this launch reads may have been written by other kernels, copies or XCDs since
   // this XCD's L2 last saw it, and the per-frame barriers of XCD-local mode never
   // invalidate the L2: take one device-wide acquire before the first read, and publish
@@ -659,7 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict_
     __syncthreads();
     if (it < 0) break;
     const WorkItem wi = items[it];
-    cg_item<STORED, REFRESH>(frames[wi.frame], wi, budget, B, L, red, redd, &sflag);
+    cg_item<STORED, REFRESH>(frames[wi.frame], wi, budget, B, L, red, redd, &sflag, stage_lds);
     __syncthreads();
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -679,10 +808,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ f
                                                   float2* __restrict__ out) {
   const WorkItem wi = items[blockIdx.x];
   const FrameDev& F = frames[wi.frame];
+  extern __shared__ float2 stage_lds[];
   const float2* __restrict__ src = in + F.off;
   float2* __restrict__ dst = out + F.off;
-  band_apply<kRows, kPaths, ADJ, STORED>(
-      F, wi.l_begin, wi.l_end, [&](int i) { return src[i]; },
+  apply_band<ADJ, STORED>(
+      F, wi.l_begin, wi.l_end, stage_lds, [&](int i) { return src[i]; },
       [&](int q, float2 v) { dst[q] = v; });
 }
 
@@ -703,6 +833,23 @@ __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsign
     s.init = 0;
     s.cn_hist[0] = s.cn_hist[1] = 0.f;
     *F.st = s;
+  }
+}
+
+// Between two serving steps: clear the barrier counters, queue cursors and abort word,
+// and mark each frame's stats slot as running; the CG state of the frames is kept.
+__global__ void k_step_reset(const FrameDev* __restrict__ frames, int nframes,
+                             unsigned* abort_flag, unsigned* qhead, int ngroups) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && abort_flag) *abort_flag = 0u;
+  if (qhead && t < ngroups) qhead[t] = 0u;
+  for (int i = t; i < nframes; i += gridDim.x * blockDim.x) {
+    const FrameDev& F = frames[i];
+    *F.bar = 0u;
+    if (F.stats) {
+      otfs_frame_stats st{0, 0.f, OTFS_FRAME_RUNNING, F.T};
+      *F.stats = st;
+    }
   }
 }
 
@@ -890,15 +1037,16 @@ __global__ __launch_bounds__(kBlock) void k_plain_finish(const FrameDev* __restr
 // host-side launchers
 // ---------------------------------------------------------------------------------------
 hipError_t launch_apply(bool adjoint, bool stored, const FrameDev* frames, const WorkItem* items,
-                        int nitems, const float2* in, float2* out, hipStream_t s) {
+                        int nitems, const float2* in, float2* out, int lds_bytes, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const dim3 g(nitems), b(kBlock);
+  const int lb = stored ? 0 : lds_bytes;
   if (adjoint) {
-    if (stored) hipLaunchKernelGGL((k_apply<true, true>), g, b, 0, s, frames, items, in, out);
-    else hipLaunchKernelGGL((k_apply<true, false>), g, b, 0, s, frames, items, in, out);
+    if (stored) hipLaunchKernelGGL((k_apply<true, true>), g, b, lb, s, frames, items, in, out);
+    else hipLaunchKernelGGL((k_apply<true, false>), g, b, lb, s, frames, items, in, out);
   } else {
-    if (stored) hipLaunchKernelGGL((k_apply<false, true>), g, b, 0, s, frames, items, in, out);
-    else hipLaunchKernelGGL((k_apply<false, false>), g, b, 0, s, frames, items, in, out);
+    if (stored) hipLaunchKernelGGL((k_apply<false, true>), g, b, lb, s, frames, items, in, out);
+    else hipLaunchKernelGGL((k_apply<false, false>), g, b, lb, s, frames, items, in, out);
   }
   return hipGetLastError();
 }
@@ -909,6 +1057,16 @@ hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_fla
   if (n <= 0) return hipSuccess;
   const int grid = (n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_reset, dim3(grid), dim3(kBlock), 0, s, frames, nframes, abort_flag,
+                     qhead, ngroups);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abort_flag,
+                             unsigned* qhead, int ngroups, hipStream_t s) {
+  const int n = nframes > ngroups ? nframes : ngroups;
+  if (n <= 0) return hipSuccess;
+  const int grid = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_step_reset, dim3(grid), dim3(kBlock), 0, s, frames, nframes, abort_flag,
                      qhead, ngroups);
   return hipGetLastError();
 }
@@ -928,34 +1086,36 @@ static uint64_t wallclock_timeout_ticks() {
 template <bool STORED, bool REFRESH>
 static void launch_fused_t(const FrameDev* frames, const WorkItem* items, const int32_t* qitems,
                            const int2* qrange, unsigned* qhead, int ngroups, int grid, int budget,
-                           const Bases& bases, const LaunchCtx& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_fused<STORED, REFRESH>), dim3(grid), dim3(kBlock), 0, s, frames, items,
-                     qitems, qrange, qhead, ngroups, budget, bases, L);
+                           const Bases& bases, const LaunchCtx& L, int lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_fused<STORED, REFRESH>), dim3(grid), dim3(kBlock), lds_bytes, s,
+                     frames, items, qitems, qrange, qhead, ngroups, budget, bases, L);
 }
 
 hipError_t launch_cg_fused(bool stored, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
-                           bool xcd_local, unsigned* abort_flag, hipStream_t s) {
+                           bool xcd_local, unsigned* abort_flag, int lds_bytes, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   LaunchCtx L{abort_flag, wallclock_timeout_ticks(), xcd_local ? 1 : 0};
+  if (stored) lds_bytes = 0;
   if (stored) {
-    if (refresh) launch_fused_t<true, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
-    else launch_fused_t<true, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+    if (refresh) launch_fused_t<true, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+    else launch_fused_t<true, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
   } else {
-    if (refresh) launch_fused_t<false, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
-    else launch_fused_t<false, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+    if (refresh) launch_fused_t<false, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+    else launch_fused_t<false, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
   }
   return hipGetLastError();
 }
 
-int fused_blocks_per_cu(bool stored, bool refresh) {
+int fused_blocks_per_cu(bool stored, bool refresh, int lds_bytes) {
   int n = 0;
   const void* fn = stored ? (refresh ? reinterpret_cast<const void*>(&k_cg_fused<true, true>)
                                      : reinterpret_cast<const void*>(&k_cg_fused<true, false>))
                           : (refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true>)
                                      : reinterpret_cast<const void*>(&k_cg_fused<false, false>));
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, 0) != hipSuccess) n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, stored ? 0 : lds_bytes) != hipSuccess)
+    n = 0;
   return n;
 }
 

@@ -63,6 +63,10 @@ struct FrameDev {
   float tol;
   int32_t refresh_every;
   int32_t index;          // frame index in its batch (stats slot)
+  // LDS staging of the gathers (0 = gather straight from memory): column chunk and row
+  // sub-band of one staged block, and the delay / Doppler shift ranges of the paths
+  int32_t skc, ssb;
+  int32_t tau_lo, tau_hi, nu_lo, nu_hi;
 };
 
 // One workgroup's share of one frame: Doppler rows [l_begin, l_end), all delay columns.
@@ -84,15 +88,23 @@ struct Bases {
 
 // ---- launchers (kernels.hip) -----------------------------------------------------------
 constexpr int kMaxGroups = 16;   // work-queue groups (one per XCD in XCD-local mode)
+constexpr int kStageRows = 8;    // output rows per thread in one staged block
+constexpr int kDefaultStageBytes = 40 * 1024;   // LDS per workgroup for staged windows
 
 // One workgroup per item.  in/out are batch-wide complex64 buffers (frame at base + off).
+// lds_bytes: dynamic LDS for staged windows (0 if no frame is staged).
 hipError_t launch_apply(bool adjoint, bool stored, const FrameDev* frames, const WorkItem* items,
-                        int nitems, const float2* in, float2* out, hipStream_t s);
+                        int nitems, const float2* in, float2* out, int lds_bytes, hipStream_t s);
 
 // Reset barrier counters and CG state of frames [0, nframes), the abort word and the
 // queue cursors of ngroups groups.
 hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_flag,
                         unsigned* qhead, int ngroups, hipStream_t s);
+
+// Serving step preamble: clear barrier counters, queue cursors and abort word, mark stats
+// slots running; keeps the frames' CG state.
+hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abort_flag,
+                             unsigned* qhead, int ngroups, hipStream_t s);
 
 // Fused persistent CG over work queues: group g holds item indices
 // qitems[qrange[g].x .. qrange[g].y); qhead[g] is its cursor (zero before the launch).
@@ -103,9 +115,10 @@ hipError_t launch_reset(const FrameDev* frames, int nframes, unsigned* abort_fla
 hipError_t launch_cg_fused(bool stored, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
-                           bool xcd_local, unsigned* abort_flag, hipStream_t s);
-// Workgroups of the fused kernel that fit on one CU at once (occupancy).
-int fused_blocks_per_cu(bool stored, bool refresh);
+                           bool xcd_local, unsigned* abort_flag, int lds_bytes, hipStream_t s);
+// Workgroups of the fused kernel that fit on one CU at once (occupancy) with lds_bytes of
+// dynamic LDS.
+int fused_blocks_per_cu(bool stored, bool refresh, int lds_bytes);
 
 // out[b] = XCC id of workgroup b, for b < nblocks.
 hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);

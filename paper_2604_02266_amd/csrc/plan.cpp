@@ -10,6 +10,7 @@
 #include <numeric>
 #include <queue>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "otfs_internal.h"
@@ -109,6 +110,29 @@ void delay_ramp(const HostFrame& f, int p, std::vector<double2>& out) {
   }
 }
 
+// Scalar fields of a frame descriptor: shape, regulariser, decision constants, solver
+// options and staging geometry (from stage_geometry).
+void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const FrameDev& geo,
+                   FrameDev* d) {
+  d->M = fr.M;
+  d->N = fr.N;
+  d->P = fr.P;
+  d->T = tiles;
+  d->lam = fr.lam;
+  d->qside = fr.qam > 0 ? (int)std::lround(std::sqrt((double)fr.qam)) : 0;
+  d->qscale = fr.qam > 0 ? (float)std::sqrt(2.0 * (fr.qam - 1) / 3.0) : 0.f;
+  d->flags = (int32_t)o.flags;
+  d->max_iters = o.max_iters;
+  d->tol = o.rel_tol;
+  d->refresh_every = o.refresh_every;
+  d->skc = geo.skc;
+  d->ssb = geo.ssb;
+  d->tau_lo = geo.tau_lo;
+  d->tau_hi = geo.tau_hi;
+  d->nu_lo = geo.nu_lo;
+  d->nu_hi = geo.nu_hi;
+}
+
 // W[l] = e^{j 2 pi l / N}
 void wrap_factors(const HostFrame& f, std::vector<double2>& out) {
   for (int l = 0; l < f.N; ++l) {
@@ -188,9 +212,57 @@ bool make_queues(const std::vector<HostFrame>& frames, const std::vector<int>& t
   return true;
 }
 
+int stage_geometry(const HostFrame& f, int band_rows, int budget_elems, FrameDev* d) {
+  int tlo = f.tau[0], thi = f.tau[0], vlo = f.nu[0], vhi = f.nu[0];
+  for (int p = 1; p < f.P; ++p) {
+    tlo = std::min(tlo, f.tau[p]);
+    thi = std::max(thi, f.tau[p]);
+    vlo = std::min(vlo, f.nu[p]);
+    vhi = std::max(vhi, f.nu[p]);
+  }
+  d->tau_lo = tlo;
+  d->tau_hi = thi;
+  d->nu_lo = vlo;
+  d->nu_hi = vhi;
+  d->skc = 0;
+  d->ssb = 0;
+  if (budget_elems <= 0) return 0;
+  const int dtau = thi - tlo, dnu = vhi - vlo;
+  // column chunks: whole rows, or 64-multiples with a delay halo
+  int cands[8], nc = 0;
+  cands[nc++] = f.M;
+  for (int kc : {512, 256, 128, 64})
+    if (kc < f.M) cands[nc++] = kc;
+  double best = 1e300;
+  int best_win = 0;
+  for (int i = 0; i < nc; ++i) {
+    int kc = cands[i];
+    int wc = kc + dtau;
+    if (kc == f.M || wc >= f.M) {   // the window spans whole rows: no halo, modular columns
+      kc = f.M;
+      wc = f.M;
+    }
+    const int tyc = kBlock / std::min(kc, kBlock);
+    const int sb = std::max(1, std::min(kStageRows * tyc, band_rows));
+    const int wr = sb + dnu >= f.N ? f.N : sb + dnu;
+    const long long win = (long long)wr * wc;
+    if (win > budget_elems) continue;
+    const double cost = (double)win / ((double)sb * kc);
+    if (cost < best - 1e-9) {
+      best = cost;
+      best_win = (int)win;
+      d->skc = kc;
+      d->ssb = sb;
+    }
+  }
+  return d->skc > 0 ? best_win : 0;
+}
+
 otfs_status probe_xcds(int device, void* scratch_dev, hipStream_t s, XcdInfo* out) {
+  static std::mutex mu;
   static std::vector<int> cached_n(64, 0);
   static std::vector<int> cached_rr(64, 0);
+  std::lock_guard<std::mutex> guard(mu);
   if (device >= 0 && device < 64 && cached_n[device] > 0) {
     out->nxcd = cached_n[device];
     out->round_robin = cached_rr[device] != 0;
@@ -344,6 +416,7 @@ extern "C" otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t*
   info->tile_elems = plan->tile_elems;
   info->groups = plan->ngroups;
   info->xcd_local = plan->xcd_local ? 1 : 0;
+  info->lds_bytes = plan->lds_bytes;
   return OTFS_OK;
 }
 
@@ -356,6 +429,16 @@ extern "C" otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elem
   plan->max_grid_req = max_grid;
   make_tiles(plan->frames, plan->tile_elems, plan->items, plan->tile_base, plan->tiles);
   compute_layout(plan);
+  plan->bound = false;
+  plan->drop_graph();
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_set_staging(otfs_plan_t* plan, int32_t lds_bytes) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  if (lds_bytes < 0 || lds_bytes > 65536)
+    return fail(OTFS_E_INVAL, "lds_bytes must be in [0, 65536] (got %d)", lds_bytes);
+  plan->stage_bytes = lds_bytes;
   plan->bound = false;
   plan->drop_graph();
   return OTFS_OK;
@@ -375,9 +458,25 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   plan->device = dev;
   plan->drop_graph();
 
+  // staged-gather geometry per frame (decides the dynamic LDS of the launches)
+  std::vector<FrameDev> geo(plan->frames.size());
+  int max_win = 0;
+  for (size_t f = 0; f < plan->frames.size(); ++f) {
+    int band = 1;
+    for (int t = 0; t < plan->tiles[f]; ++t) {
+      const WorkItem& w = plan->items[plan->tile_base[f] + t];
+      band = std::max(band, w.l_end - w.l_begin);
+    }
+    std::memset(&geo[f], 0, sizeof(FrameDev));
+    max_win = std::max(max_win, stage_geometry(plan->frames[f], band,
+                                               plan->stage_bytes / (int)sizeof(float2), &geo[f]));
+  }
+  plan->lds_bytes = max_win * (int)sizeof(float2);
+
   // work queues of the fused kernel (need the occupancy and XCD layout of this device)
   const bool stored_mode = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
-  const int bpc = std::max(1, fused_blocks_per_cu(stored_mode, plan->opts.refresh_every > 0));
+  const int bpc = std::max(1, fused_blocks_per_cu(stored_mode, plan->opts.refresh_every > 0,
+                                                  plan->lds_bytes));
   int cus = plan->cus;
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
@@ -447,18 +546,8 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
     d.part_d = reinterpret_cast<double*>(base + L.part_d) + tb;
     d.bar = reinterpret_cast<unsigned*>(base + L.bar) + f;
     d.st = reinterpret_cast<FrameState*>(base + L.st) + f;
+    frame_scalars(fr, plan->opts, plan->tiles[f], geo[f], &d);
     d.off = fr.off;
-    d.M = fr.M;
-    d.N = fr.N;
-    d.P = fr.P;
-    d.T = plan->tiles[f];
-    d.lam = fr.lam;
-    d.qside = fr.qam > 0 ? (int)std::lround(std::sqrt((double)fr.qam)) : 0;
-    d.qscale = fr.qam > 0 ? (float)std::sqrt(2.0 * (fr.qam - 1) / 3.0) : 0.f;
-    d.flags = (int32_t)plan->opts.flags;
-    d.max_iters = plan->opts.max_iters;
-    d.tol = plan->opts.rel_tol;
-    d.refresh_every = plan->opts.refresh_every;
     d.index = (int32_t)f;
     ro += (size_t)fr.P * fr.M;
     wo += (size_t)fr.N;
@@ -536,7 +625,7 @@ static otfs_status apply_common(const otfs_plan_t* plan, bool adj, const void* i
   const bool stored = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
   hipError_t e = launch_apply(adj, stored, plan->d_frames, plan->d_items, (int)plan->items.size(),
                               static_cast<const float2*>(in), static_cast<float2*>(out),
-                              static_cast<hipStream_t>(stream));
+                              plan->lds_bytes, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, adj ? "apply H^H" : "apply H");
   return OTFS_OK;
 }
@@ -557,7 +646,7 @@ static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s
   e = launch_cg_fused((plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->opts.refresh_every > 0,
                       plan->d_frames, plan->d_items,
                       plan->d_qitems, plan->d_qrange, plan->d_qhead, plan->ngroups, plan->grid,
-                      plan->opts.max_iters, B, plan->xcd_local, plan->d_abort, s);
+                      plan->opts.max_iters, B, plan->xcd_local, plan->d_abort, plan->lds_bytes, s);
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_end, s)) != hipSuccess) return e;
   return hipSuccess;

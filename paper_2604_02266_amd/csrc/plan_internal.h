@@ -48,6 +48,8 @@ otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out);
 otfs_status validate_frame(const otfs_frame_desc& f, int idx, HostFrame* out);
 void delay_ramp(const HostFrame& f, int p, std::vector<double2>& out);
 void wrap_factors(const HostFrame& f, std::vector<double2>& out);
+void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const FrameDev& geo,
+                   FrameDev* d);
 int default_tile_elems(int64_t total_elems, int cus);
 void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vector<WorkItem>& items,
                 std::vector<int>& tile_base, std::vector<int>& tiles);
@@ -64,6 +66,9 @@ struct XcdInfo {
   bool round_robin = false;  // workgroup b ran on XCD b % nxcd for every probed b
 };
 otfs_status probe_xcds(int device, void* scratch_dev, hipStream_t s, XcdInfo* out);
+// Staged-gather geometry of one frame whose widest tile has band_rows rows: fills
+// skc/ssb (0 = direct gathers) and the shift ranges; returns the window size in elements.
+int stage_geometry(const HostFrame& f, int band_rows, int budget_elems, FrameDev* d);
 constexpr int kProbeBlocks = 1024;
 
 }  // namespace otfs
@@ -74,6 +79,8 @@ struct otfs_plan {
   int64_t total_elems = 0;
   int max_paths = 0, cus = 256;
   int tile_elems = 0, max_grid_req = 0;
+  int stage_bytes = otfs::kDefaultStageBytes;   // LDS budget for staged windows, 0 = off
+  int lds_bytes = 0;                            // dynamic LDS of the launches (bind)
   // tiling (host) and schedule (chosen at bind)
   std::vector<otfs::WorkItem> items;
   std::vector<int> tile_base, tiles;

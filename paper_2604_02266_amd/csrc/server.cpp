@@ -1,22 +1,653 @@
-// Serving entry points (continuous batching).  Implemented in a later step.
+// Serving: continuous batching of LMMSE-CG frames that arrive over time.
+//
+// A scheduler thread owns the device side.  Frames wait in a FIFO queue until their state
+// fits the caller's pool (the HBM admission budget); an admitted frame gets one slot of
+// the pool holding its vectors, tables and CG state.  Each step runs `step_iters` CG
+// iterations of every admitted frame in one launch of the fused kernel; the frames'
+// state stays on the device between steps, frames that finish are copied out and leave,
+// and frames that arrived meanwhile are admitted before the next step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "otfs_internal.h"
 #include "plan_internal.h"
 
+namespace otfs {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr int kServeTileElems = 4096;   // frame-local tiling rule (independent of the mix)
+constexpr int kMaxActive = 2048;        // frames admitted at once
+constexpr int kMaxItems = 65536;        // tiles of the admitted frames
+constexpr size_t kAlign = 256;
+constexpr int kDryRunCap = 512;         // resident workgroups assumed by a dry run
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing free blocks.
+class PoolAlloc {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0;
+};
+
+// Byte offsets inside one frame's slot.
+struct SlotLayout {
+  size_t y, x, c, p0, p1, t, a, u, rtab, wtab, rtab64, wtab64, paths, part_pa, part_cc, part_d,
+      bar, st, sym, total;
+};
+
+SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
+  SlotLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o = align_up(o + b);
+    return at;
+  };
+  const size_t E = (size_t)f.M * f.N;
+  L.y = take(E * 8);
+  L.x = take(E * 8);
+  L.c = take(E * 8);
+  L.p0 = take(E * 8);
+  L.p1 = take(E * 8);
+  L.t = take(E * 8);
+  L.a = take(E * 8);
+  L.u = refresh ? take(E * 16) : 0;
+  L.rtab = take((size_t)f.P * f.M * 8);
+  L.wtab = take((size_t)f.N * 8);
+  L.rtab64 = refresh ? take((size_t)f.P * f.M * 16) : 0;
+  L.wtab64 = refresh ? take((size_t)f.N * 16) : 0;
+  L.paths = take((size_t)f.P * 8);
+  L.part_pa = take((size_t)tiles * 4);
+  L.part_cc = take((size_t)tiles * 4);
+  L.part_d = take((size_t)tiles * 8);
+  L.bar = take(4);
+  L.st = take(sizeof(FrameState));
+  L.sym = take(E);
+  L.total = o;
+  return L;
+}
+
+// Control region at the start of the pool: step descriptors.
+struct CtrlLayout {
+  size_t frames, items, qitems, qrange, qhead, abort, stats, probe, total;
+};
+CtrlLayout ctrl_layout() {
+  CtrlLayout C{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o = align_up(o + b);
+    return at;
+  };
+  C.frames = take(kMaxActive * sizeof(FrameDev));
+  C.items = take(kMaxItems * sizeof(WorkItem));
+  C.qitems = take(kMaxItems * sizeof(int32_t));
+  C.qrange = take(kMaxGroups * sizeof(int2));
+  C.qhead = take(kMaxGroups * sizeof(unsigned));
+  C.abort = take(sizeof(unsigned));
+  C.stats = take(kMaxActive * sizeof(otfs_frame_stats));
+  C.probe = take(kProbeBlocks * sizeof(int));
+  C.total = o;
+  return C;
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  HostFrame hf;
+  std::vector<float2> y;
+  Clock::time_point t_submit, t_done;
+  int state = 0;   // 0 queued, 1 admitted, 2 done
+  // slot
+  size_t slot_off = 0;
+  SlotLayout L{};
+  int tiles = 1;
+  std::vector<WorkItem> items;   // frame-local tiles (frame index patched per step)
+  FrameDev dev{};
+  FrameDev geo{};                // staging geometry
+  // results
+  std::vector<float2> xhat;
+  std::vector<uint8_t> sym;
+  otfs_frame_stats stats{};
+};
+
+}  // namespace
+}  // namespace otfs
+
 using namespace otfs;
 
-extern "C" otfs_status otfs_server_create(int, void*, size_t, const otfs_cg_opts*, int32_t,
+struct otfs_server {
+  int device = -1;
+  bool dry = false;
+  char* pool = nullptr;
+  size_t pool_bytes = 0;
+  otfs_cg_opts opts{};
+  int step_iters = 10;
+  CtrlLayout C{};
+  PoolAlloc alloc;
+  size_t slot_base = 0;   // first byte of the slot area (after the control region)
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::vector<Request*> active;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  bool failed = false;
+  std::string fail_msg;
+  std::thread th;
+  // device objects (scheduler thread)
+  hipStream_t s = nullptr;
+  XcdInfo xcd;
+  int bpc = 1, cus = 256;
+  int lds_bytes = 0;
+  int cap = 0;              // workgroups of the fused kernel resident at once
+  bool ready = false;       // scheduler_init finished
+  int active_tiles = 0;
+  // counters
+  uint64_t submitted = 0, completed = 0, steps = 0, peak = 0;
+};
+
+namespace otfs {
+namespace {
+
+bool frame_fits_ever(otfs_server* S, const SlotLayout& L) {
+  return L.total <= S->pool_bytes - S->slot_base;
+}
+
+// Host-side tables and descriptor of an admitted frame (device pointers into its slot).
+void build_frame_dev(otfs_server* S, Request* r, std::vector<double2>& r64,
+                     std::vector<double2>& w64, std::vector<int2>& paths) {
+  const HostFrame& f = r->hf;
+  char* base = S->pool + S->slot_base + r->slot_off;
+  const SlotLayout& L = r->L;
+  const bool refresh = S->opts.refresh_every > 0;
+  r64.clear();
+  w64.clear();
+  paths.clear();
+  for (int p = 0; p < f.P; ++p) delay_ramp(f, p, r64);
+  wrap_factors(f, w64);
+  for (int p = 0; p < f.P; ++p) paths.push_back(make_int2(f.tau[p], f.nu[p]));
+  FrameDev& d = r->dev;
+  std::memset(&d, 0, sizeof d);
+  d.y = base + L.y;
+  d.x = reinterpret_cast<float2*>(base + L.x);
+  d.c = reinterpret_cast<float2*>(base + L.c);
+  d.p0 = reinterpret_cast<float2*>(base + L.p0);
+  d.p1 = reinterpret_cast<float2*>(base + L.p1);
+  d.t = reinterpret_cast<float2*>(base + L.t);
+  d.a = reinterpret_cast<float2*>(base + L.a);
+  d.u = refresh ? reinterpret_cast<double2*>(base + L.u) : nullptr;
+  d.rtab = reinterpret_cast<const float2*>(base + L.rtab);
+  d.wtab = reinterpret_cast<const float2*>(base + L.wtab);
+  d.rtab64 = refresh ? reinterpret_cast<const double2*>(base + L.rtab64) : nullptr;
+  d.wtab64 = refresh ? reinterpret_cast<const double2*>(base + L.wtab64) : nullptr;
+  d.paths = reinterpret_cast<const int2*>(base + L.paths);
+  d.part_pa = reinterpret_cast<float*>(base + L.part_pa);
+  d.part_cc = reinterpret_cast<float*>(base + L.part_cc);
+  d.part_d = reinterpret_cast<double*>(base + L.part_d);
+  d.bar = reinterpret_cast<unsigned*>(base + L.bar);
+  d.st = reinterpret_cast<FrameState*>(base + L.st);
+  d.sym = f.qam > 0 ? reinterpret_cast<uint8_t*>(base + L.sym) : nullptr;
+  frame_scalars(f, S->opts, r->tiles, r->geo, &d);
+}
+
+void set_failed(otfs_server* S, const std::string& msg) {
+  std::lock_guard<std::mutex> g(S->mu);
+  S->failed = true;
+  S->fail_msg = msg;
+  S->cv.notify_all();
+}
+
+// ---- GPU executor steps (scheduler thread) ----------------------------------------------
+bool gpu_admit(otfs_server* S, Request* r) {
+  std::vector<double2> r64, w64;
+  std::vector<int2> paths;
+  build_frame_dev(S, r, r64, w64, paths);
+  std::vector<float2> r32(r64.size()), w32(w64.size());
+  for (size_t i = 0; i < r64.size(); ++i) r32[i] = make_float2((float)r64[i].x, (float)r64[i].y);
+  for (size_t i = 0; i < w64.size(); ++i) w32[i] = make_float2((float)w64[i].x, (float)w64[i].y);
+  FrameState st{};
+  st.status = OTFS_FRAME_RUNNING;
+  char* base = S->pool + S->slot_base + r->slot_off;
+  hipError_t e = hipSuccess;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes)
+      e = hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, S->s);
+  };
+  up(r->L.y, r->y.data(), r->y.size() * sizeof(float2));
+  up(r->L.rtab, r32.data(), r32.size() * sizeof(float2));
+  up(r->L.wtab, w32.data(), w32.size() * sizeof(float2));
+  if (S->opts.refresh_every > 0) {
+    up(r->L.rtab64, r64.data(), r64.size() * sizeof(double2));
+    up(r->L.wtab64, w64.data(), w64.size() * sizeof(double2));
+  }
+  up(r->L.paths, paths.data(), paths.size() * sizeof(int2));
+  up(r->L.st, &st, sizeof st);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->s);   // host sources go out of scope
+  if (e != hipSuccess) {
+    set_failed(S, std::string("admission copy: ") + hipGetErrorString(e));
+    return false;
+  }
+  return true;
+}
+
+bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame_stats>& out) {
+  const int n = (int)act.size();
+  std::vector<FrameDev> fd(n);
+  std::vector<HostFrame> frames(n);
+  std::vector<WorkItem> items;
+  std::vector<int> tile_base(n), tiles(n);
+  otfs_frame_stats* dstats = reinterpret_cast<otfs_frame_stats*>(S->pool + S->C.stats);
+  for (int i = 0; i < n; ++i) {
+    Request* r = act[i];
+    fd[i] = r->dev;
+    fd[i].stats = dstats + i;
+    fd[i].index = i;
+    frames[i] = r->hf;
+    tile_base[i] = (int)items.size();
+    tiles[i] = r->tiles;
+    for (WorkItem w : r->items) {
+      w.frame = i;
+      items.push_back(w);
+    }
+  }
+  if ((int)items.size() > kMaxItems) {
+    set_failed(S, "too many tiles in one step");
+    return false;
+  }
+  std::vector<int32_t> qitems;
+  std::vector<int2> qrange;
+  int per = 0;
+  bool xcd = false;
+  int ngroups = 1, grid = 0;
+  const int cap = S->bpc * S->cus;
+  if (S->xcd.round_robin && !(S->opts.flags & OTFS_AGENT_BARRIER) && cap >= S->xcd.nxcd &&
+      make_queues(frames, tile_base, tiles, S->xcd.nxcd, cap / S->xcd.nxcd, qitems, qrange, &per)) {
+    xcd = true;
+    ngroups = S->xcd.nxcd;
+    grid = per * ngroups;
+  } else if (make_queues(frames, tile_base, tiles, 1, cap, qitems, qrange, &per)) {
+    grid = per;
+  } else {
+    set_failed(S, "a frame needs more cooperating workgroups than fit");
+    return false;
+  }
+  char* P = S->pool;
+  const CtrlLayout& C = S->C;
+  hipError_t e = hipSuccess;
+  auto up = [&](size_t off, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(P + off, src, bytes, hipMemcpyHostToDevice, S->s);
+  };
+  up(C.frames, fd.data(), fd.size() * sizeof(FrameDev));
+  up(C.items, items.data(), items.size() * sizeof(WorkItem));
+  up(C.qitems, qitems.data(), qitems.size() * sizeof(int32_t));
+  up(C.qrange, qrange.data(), qrange.size() * sizeof(int2));
+  const FrameDev* dframes = reinterpret_cast<const FrameDev*>(P + C.frames);
+  unsigned* qhead = reinterpret_cast<unsigned*>(P + C.qhead);
+  unsigned* abort_flag = reinterpret_cast<unsigned*>(P + C.abort);
+  if (e == hipSuccess) e = launch_step_reset(dframes, n, abort_flag, qhead, ngroups, S->s);
+  Bases B{nullptr, nullptr, nullptr, nullptr};
+  if (e == hipSuccess)
+    e = launch_cg_fused(false, S->opts.refresh_every > 0, dframes,
+                        reinterpret_cast<const WorkItem*>(P + C.items),
+                        reinterpret_cast<const int32_t*>(P + C.qitems),
+                        reinterpret_cast<const int2*>(P + C.qrange), qhead, ngroups, grid,
+                        S->step_iters, B, xcd, abort_flag, S->lds_bytes, S->s);
+  out.resize(n);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out.data(), dstats, n * sizeof(otfs_frame_stats), hipMemcpyDeviceToHost, S->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->s);
+  if (e != hipSuccess) {
+    set_failed(S, std::string("serving step: ") + hipGetErrorString(e));
+    return false;
+  }
+  return true;
+}
+
+bool gpu_fetch(otfs_server* S, Request* r) {
+  const size_t E = (size_t)r->hf.M * r->hf.N;
+  r->xhat.resize(E);
+  char* base = S->pool + S->slot_base + r->slot_off;
+  hipError_t e = hipMemcpyAsync(r->xhat.data(), base + r->L.x, E * sizeof(float2),
+                                hipMemcpyDeviceToHost, S->s);
+  if (r->hf.qam > 0) {
+    r->sym.resize(E);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(r->sym.data(), base + r->L.sym, E, hipMemcpyDeviceToHost, S->s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(S->s);
+  if (e != hipSuccess) {
+    set_failed(S, std::string("result copy: ") + hipGetErrorString(e));
+    return false;
+  }
+  return true;
+}
+
+// ---- scheduler ---------------------------------------------------------------------------
+// Device set-up of the scheduler thread: stream, XCD layout, resident workgroups.
+bool scheduler_init(otfs_server* S) {
+  if (S->dry) {
+    S->cap = kDryRunCap;
+    return true;
+  }
+  hipError_t e = hipSetDevice(S->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    set_failed(S, std::string("server stream: ") + hipGetErrorString(e));
+    return false;
+  }
+  if (probe_xcds(S->device, S->pool + S->C.probe, S->s, &S->xcd) != OTFS_OK) {
+    set_failed(S, std::string("XCC probe: ") + otfs_last_error());
+    return false;
+  }
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess && v > 0)
+    S->cus = v;
+  S->lds_bytes = kDefaultStageBytes;
+  S->bpc = std::max(1, fused_blocks_per_cu(false, S->opts.refresh_every > 0, S->lds_bytes));
+  S->cap = S->bpc * S->cus;
+  return true;
+}
+
+void scheduler(otfs_server* S) {
+  const bool ok = scheduler_init(S);
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->ready = true;
+  }
+  S->cv.notify_all();
+  if (!ok) return;
+  std::vector<otfs_frame_stats> st;
+  for (;;) {
+    std::vector<Request*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || S->failed || !S->queue.empty() || !S->active.empty(); });
+      if (S->stop || S->failed) return;
+      // admission: arrival order, while the head fits
+      while (!S->queue.empty() && (int)S->active.size() + (int)admitted.size() < kMaxActive) {
+        Request* r = S->queue.front();
+        if (S->active_tiles + r->tiles > kMaxItems) break;
+        size_t off = 0;
+        if (!S->alloc.alloc(r->L.total, &off)) break;
+        r->slot_off = off;
+        r->state = 1;
+        S->active_tiles += r->tiles;
+        S->queue.pop_front();
+        admitted.push_back(r);
+      }
+      S->peak = std::max<uint64_t>(S->peak, S->alloc.used());
+    }
+    for (Request* r : admitted) {
+      if (!S->dry && !gpu_admit(S, r)) return;
+    }
+    std::vector<Request*> act;
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      for (Request* r : admitted) S->active.push_back(r);
+      act = S->active;
+    }
+    if (act.empty()) continue;
+    st.clear();
+    if (S->dry) {
+      // dry run: every frame finishes after ceil(max_iters / step_iters) steps
+      st.resize(act.size());
+      for (size_t i = 0; i < act.size(); ++i) {
+        Request* r = act[i];
+        r->stats.iters = std::min(S->opts.max_iters, r->stats.iters + S->step_iters);
+        st[i] = otfs_frame_stats{r->stats.iters, 0.f,
+                                 r->stats.iters >= S->opts.max_iters ? OTFS_FRAME_DRYRUN
+                                                                     : OTFS_FRAME_RUNNING,
+                                 r->tiles};
+      }
+    } else if (!gpu_step(S, act, st)) {
+      return;
+    }
+    std::vector<Request*> done;
+    for (size_t i = 0; i < act.size(); ++i)
+      if (st[i].status != OTFS_FRAME_RUNNING) {
+        act[i]->stats = st[i];
+        done.push_back(act[i]);
+      }
+    for (Request* r : done) {
+      if (S->dry) {
+        const size_t E = (size_t)r->hf.M * r->hf.N;
+        r->xhat.assign(E, make_float2(0.f, 0.f));
+        if (r->hf.qam > 0) r->sym.assign(E, 0);
+      } else if (!gpu_fetch(S, r)) {
+        return;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      const auto now = Clock::now();
+      for (Request* r : done) {
+        r->t_done = now;
+        r->state = 2;
+        S->alloc.release(r->slot_off, r->L.total);
+        S->active_tiles -= r->tiles;
+        S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+        ++S->completed;
+      }
+      ++S->steps;
+    }
+    S->cv.notify_all();
+  }
+}
+
+}  // namespace
+}  // namespace otfs
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+extern "C" otfs_status otfs_server_create(int device, void* pool_dev, size_t pool_bytes,
+                                          const otfs_cg_opts* opts, int32_t step_iters,
                                           otfs_server_t** out) {
-  if (out) *out = nullptr;
-  return fail(OTFS_E_UNSUPPORTED, "serving is not built yet");
+  if (!out) return fail(OTFS_E_INVAL, "out must be non-null");
+  *out = nullptr;
+  if (device < -1) return fail(OTFS_E_INVAL, "device must be >= 0, or -1 for a dry run");
+  if (step_iters < 1) return fail(OTFS_E_INVAL, "step_iters must be >= 1");
+  otfs_cg_opts o{};
+  otfs_status st = validate_opts(opts, &o);
+  if (st != OTFS_OK) return st;
+  if (o.flags & (OTFS_D_STORED_BF16 | OTFS_Y_BF16))
+    return fail(OTFS_E_UNSUPPORTED, "the bf16 flags are not supported by the server");
+  if (device >= 0) {
+    if (!pool_dev) return fail(OTFS_E_INVAL, "pool_dev is null");
+    if ((reinterpret_cast<uintptr_t>(pool_dev) & 255u) != 0)
+      return fail(OTFS_E_INVAL, "pool_dev must be 256-byte aligned");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev)
+      return fail(OTFS_E_INVAL, "no device %d", device);
+  }
+  auto S = std::make_unique<otfs_server>();
+  S->device = device;
+  S->dry = device < 0;
+  S->pool = static_cast<char*>(pool_dev);
+  S->pool_bytes = pool_bytes;
+  S->opts = o;
+  S->step_iters = step_iters;
+  S->C = ctrl_layout();
+  S->slot_base = S->C.total;
+  if (pool_bytes <= S->slot_base)
+    return fail(OTFS_E_BUDGET, "pool of %zu bytes is smaller than the %zu-byte control region",
+                pool_bytes, S->slot_base);
+  S->alloc.reset(pool_bytes - S->slot_base);
+  otfs_server* raw = S.release();
+  try {
+    raw->th = std::thread(scheduler, raw);
+  } catch (...) {
+    delete raw;
+    return fail(OTFS_E_NOMEM, "could not start the scheduler thread");
+  }
+  std::string err;
+  {
+    std::unique_lock<std::mutex> lk(raw->mu);
+    raw->cv.wait(lk, [&] { return raw->ready; });
+    if (raw->failed) err = raw->fail_msg;
+  }
+  if (!err.empty()) {
+    otfs_server_free(raw);
+    return fail(OTFS_E_DEVICE, "server start: %s", err.c_str());
+  }
+  *out = raw;
+  return OTFS_OK;
 }
-extern "C" otfs_status otfs_submit(otfs_server_t*, const otfs_frame_desc*, const void*, uint64_t*) {
-  return fail(OTFS_E_UNSUPPORTED, "serving is not built yet");
+
+extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* frame,
+                                   const void* y_host, uint64_t* ticket) {
+  if (!S || !frame || !y_host || !ticket) return fail(OTFS_E_INVAL, "null argument");
+  auto r = std::make_unique<Request>();
+  otfs_status st = validate_frame(*frame, 0, &r->hf);
+  if (st != OTFS_OK) return st;
+  const size_t E = (size_t)frame->M * frame->N;
+  std::vector<WorkItem> items;
+  std::vector<int> tb, tl;
+  make_tiles(std::vector<HostFrame>{r->hf}, kServeTileElems, items, tb, tl);
+  r->tiles = tl[0];
+  r->items = items;
+  int band = 1;
+  for (const WorkItem& w : items) band = std::max(band, w.l_end - w.l_begin);
+  stage_geometry(r->hf, band, kDefaultStageBytes / (int)sizeof(float2), &r->geo);
+  if (r->tiles > S->cap || r->tiles > kMaxItems)
+    return fail(OTFS_E_UNSUPPORTED, "frame needs %d cooperating workgroups, %d fit", r->tiles,
+                std::min(S->cap, kMaxItems));
+  r->L = slot_layout(r->hf, r->tiles, S->opts.refresh_every > 0);
+  if (!frame_fits_ever(S, r->L))
+    return fail(OTFS_E_BUDGET, "frame state needs %zu bytes, the pool has %zu for frames",
+                r->L.total, S->pool_bytes - S->slot_base);
+  r->y.resize(E);
+  std::memcpy(r->y.data(), y_host, E * sizeof(float2));
+  r->t_submit = Clock::now();
+  std::lock_guard<std::mutex> g(S->mu);
+  if (S->failed) return fail(OTFS_E_DEVICE, "server failed: %s", S->fail_msg.c_str());
+  r->ticket = S->next_ticket++;
+  *ticket = r->ticket;
+  Request* raw = r.get();
+  S->reqs.emplace(raw->ticket, std::move(r));
+  S->queue.push_back(raw);
+  ++S->submitted;
+  S->cv.notify_all();
+  return OTFS_OK;
 }
-extern "C" otfs_status otfs_poll(otfs_server_t*, uint64_t, void*, uint8_t*, otfs_frame_stats*,
-                                 uint64_t*) {
-  return fail(OTFS_E_UNSUPPORTED, "serving is not built yet");
+
+extern "C" otfs_status otfs_server_frame_bytes(otfs_server_t* S, const otfs_frame_desc* frame,
+                                               size_t* frame_bytes, size_t* control_bytes) {
+  if (!S || !frame) return fail(OTFS_E_INVAL, "null argument");
+  HostFrame hf;
+  otfs_status st = validate_frame(*frame, 0, &hf);
+  if (st != OTFS_OK) return st;
+  std::vector<WorkItem> items;
+  std::vector<int> tb, tl;
+  make_tiles(std::vector<HostFrame>{hf}, kServeTileElems, items, tb, tl);
+  if (frame_bytes) *frame_bytes = slot_layout(hf, tl[0], S->opts.refresh_every > 0).total;
+  if (control_bytes) *control_bytes = S->slot_base;
+  return OTFS_OK;
 }
-extern "C" otfs_status otfs_server_stats(otfs_server_t*, otfs_server_stats_t*) {
-  return fail(OTFS_E_UNSUPPORTED, "serving is not built yet");
+
+extern "C" otfs_status otfs_poll(otfs_server_t* S, uint64_t ticket, void* xhat_host,
+                                 uint8_t* sym_host, otfs_frame_stats* stats,
+                                 uint64_t* latency_ns) {
+  if (!S) return fail(OTFS_E_INVAL, "server is null");
+  std::unique_ptr<Request> r;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(OTFS_E_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    if (it->second->state != 2) {
+      if (S->failed) return fail(OTFS_E_DEVICE, "server failed: %s", S->fail_msg.c_str());
+      return OTFS_E_AGAIN;
+    }
+    r = std::move(it->second);
+    S->reqs.erase(it);
+  }
+  if (xhat_host) std::memcpy(xhat_host, r->xhat.data(), r->xhat.size() * sizeof(float2));
+  if (sym_host && !r->sym.empty()) std::memcpy(sym_host, r->sym.data(), r->sym.size());
+  if (stats) *stats = r->stats;
+  if (latency_ns)
+    *latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
+  return OTFS_OK;
 }
-extern "C" otfs_status otfs_server_free(otfs_server_t*) { return OTFS_OK; }
+
+extern "C" otfs_status otfs_server_stats(otfs_server_t* S, otfs_server_stats_t* out) {
+  if (!S || !out) return fail(OTFS_E_INVAL, "null argument");
+  std::lock_guard<std::mutex> g(S->mu);
+  out->submitted = S->submitted;
+  out->completed = S->completed;
+  out->steps = S->steps;
+  out->queued = S->queue.size();
+  out->active = S->active.size();
+  out->pool_bytes_in_use = S->alloc.used();
+  out->pool_bytes_peak = S->peak;
+  if (S->failed) return fail(OTFS_E_DEVICE, "server failed: %s", S->fail_msg.c_str());
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_server_free(otfs_server_t* S) {
+  if (!S) return OTFS_OK;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->th.joinable()) S->th.join();
+  if (S->s) {
+    (void)hipStreamSynchronize(S->s);
+    (void)hipStreamDestroy(S->s);
+  }
+  delete S;
+  return OTFS_OK;
+}

@@ -59,12 +59,14 @@ def _edge_specs(rng):
     return out
 
 
-@pytest.mark.parametrize("tile_elems", [0, 64, 1024])
-def test_apply_parity_edge_batch(otfs, tile_elems):
+@pytest.mark.parametrize("tile_elems,stage", [(0, None), (64, None), (1024, None), (0, 0),
+                                              (1024, 16384), (64, 65536)])
+def test_apply_parity_edge_batch(otfs, tile_elems, stage):
     rng = np.random.default_rng(7 + tile_elems)
     specs = _edge_specs(rng)
-    say("apply parity", "tile_elems", tile_elems, [(s.M, s.N, s.P) for s in specs])
-    plan = otfs.Plan(specs, tile_elems=tile_elems)
+    say("apply parity", "tile_elems", tile_elems, "stage", stage, [(s.M, s.N, s.P) for s in specs])
+    plan = otfs.Plan(specs, tile_elems=tile_elems, stage_bytes=stage)
+    say("  lds_bytes", plan.info().lds_bytes)
     E = plan.total_elems
     x = _rand_c(rng, E)
     y = _rand_c(rng, E)
@@ -142,17 +144,17 @@ def test_cg_single_64x16_config(otfs):
         _cg_check(_run(otfs, plan, y, form), frames, ops, y, NMSE_TOL, form)
 
 
-@pytest.mark.parametrize("tile_elems,max_grid,agent", [(0, 0, 0), (700, 0, 0), (700, 8, 1),
-                                                       (700, 64, 0), (2048, 3, 1),
-                                                       (0, 0, 1), (350, 0, 0), (200, 0, 0),
-                                                       (200, 0, 1)])
-def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent):
+@pytest.mark.parametrize("tile_elems,max_grid,agent,stage", [
+    (0, 0, 0, None), (700, 0, 0, None), (700, 8, 1, None), (700, 64, 0, None),
+    (2048, 3, 1, None), (0, 0, 1, None), (350, 0, 0, None), (200, 0, 0, None),
+    (200, 0, 1, None), (0, 0, 0, 0), (700, 0, 0, 0), (700, 0, 0, 16384)])
+def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent, stage):
     frames = _mixed_frames(11, 9, [(128, 32), (64, 16), (100, 30), (96, 8), (256, 16)],
                            (1, 9), 12, 4)
     ops, xs, y = oracle_batch(frames)
-    say("cg ragged", tile_elems, max_grid, "agent" if agent else "xcd")
+    say("cg ragged", tile_elems, max_grid, "agent" if agent else "xcd", "stage", stage)
     plan = otfs.Plan([f.spec for f in frames], tile_elems=tile_elems, max_grid=max_grid,
-                     flags=otfs.AGENT_BARRIER if agent else 0)
+                     flags=otfs.AGENT_BARRIER if agent else 0, stage_bytes=stage)
     inf = plan.info()
     say("  groups", inf.groups, "xcd_local", inf.xcd_local, "grid", inf.grid)
     if agent:
