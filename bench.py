@@ -99,6 +99,59 @@ def load_traffic(workload, launch_bytes):
     return t.get("traffic_bytes_per_launch")
 
 
+def serving_leg(otfs, W, workload, torch, step_iters=5, seed=1004):
+    """Frames of `workload` offered to the server: first all at once (throughput), then as
+    a Poisson stream at half that rate (latency from submit to completion)."""
+    import numpy as np
+    frames = list(W.iter_frames(workload))
+    specs = [f.spec for f in frames]
+    sp0 = specs[0]
+    # received frames, synthesised on the GPU and handed to the server as host buffers
+    plan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol)
+    offs = otfs.frame_offsets(specs)
+    dev = torch.device("cuda")
+    sym = torch.from_numpy(np.concatenate([f.sym for f in frames])).to(dev)
+    x = torch.empty(plan.total_elems, dtype=torch.complex64, device=dev)
+    for i, f in enumerate(frames):
+        x[offs[i]:offs[i + 1]] = qam_points_torch(torch, sym[offs[i]:offs[i + 1]], f.spec.qam)
+    noise = torch.from_numpy(np.concatenate([f.noise for f in frames]).astype(np.complex64))
+    y = (plan.apply_H(x).cpu() + noise).numpy()
+    del plan, x, sym
+    ys = [y[offs[i]:offs[i + 1]] for i in range(len(specs))]
+    total = float(offs[-1])
+
+    def run(srv, arrivals):
+        t0 = time.perf_counter()
+        tickets = []
+        for i, (sp, yy) in enumerate(zip(specs, ys)):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(sp, yy))
+        lat = [srv.wait(t, sp, timeout=120.0)[3] for t, sp in zip(tickets, specs)]
+        return time.perf_counter() - t0, np.array(lat) * 1e3
+
+    pool = 8 << 30
+    with otfs.Server(pool, max_iters=sp0.max_iters, rel_tol=sp0.tol,
+                     step_iters=step_iters) as srv:
+        run(srv, np.zeros(len(specs)))                       # warm-up
+        wall, lat_burst = run(srv, np.zeros(len(specs)))
+        rate = len(specs) / wall
+        gaps = np.random.default_rng(seed).exponential(2.0 / rate, len(specs))
+        wall_p, lat_p = run(srv, np.cumsum(gaps) - gaps[0])
+        st = srv.stats()
+    return {"workload": workload, "frames": len(specs), "step_iters": step_iters,
+            "pool_bytes": pool, "pool_bytes_peak": int(st.pool_bytes_peak),
+            "burst": {"value": total / wall, "unit": "symbols/s", "frames_per_s": rate,
+                      "latency_ms_p50": float(np.percentile(lat_burst, 50)),
+                      "latency_ms_p99": float(np.percentile(lat_burst, 99))},
+            "poisson_half_rate": {"offered_frames_per_s": rate / 2,
+                                  "value": total / wall_p, "unit": "symbols/s",
+                                  "latency_ms_p50": float(np.percentile(lat_p, 50)),
+                                  "latency_ms_p99": float(np.percentile(lat_p, 99))},
+            "note": "host buffers in and out (submit copies y, poll copies x_hat)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-frames", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serving-workload", default="serving_uneven")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (reference "
                          "for hardware byte counters)")
@@ -224,6 +279,11 @@ def main():
         torch.cuda.synchronize()
         tp = time.perf_counter() - t1
         out["plain_form"] = {"value": E / tp, "unit": "symbols/s", "ms_per_step": tp * 1e3}
+
+    if not args.no_serving:
+        del plan, y, xhat, dec, stats, x, noise, sym
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(otfs, W, args.serving_workload, torch)
 
     if cpu is not None:
         out["cpu_baseline"] = cpu

@@ -158,7 +158,9 @@ typedef struct {
   int32_t tile_elems;       /* target elements per workgroup tile                           */
   int32_t groups;           /* work-queue groups of the fused launch (XCDs, or 1)           */
   int32_t xcd_local;        /* 1: frames stay on one XCD (see OTFS_AGENT_BARRIER)           */
-  int32_t lds_bytes;        /* LDS per workgroup for staged gather windows (0: none staged) */
+  int32_t lds_bytes;        /* dynamic LDS per workgroup of the fused launch (0: none)       */
+  int32_t staged_frames;    /* frames whose gathers are staged through LDS windows          */
+  int32_t resident_frames;  /* one-workgroup frames solved with all CG vectors in LDS       */
 } otfs_plan_info_t;
 otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
 
@@ -167,11 +169,14 @@ otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
  * the next otfs_plan_bind.  Used by the autotuner. */
 otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elems, int32_t max_grid);
 
-/* LDS budget per workgroup for staging the gather windows of H and H^H (Eqs. sparse_mvm,
- * sparse_herm_mvm): a workgroup copies the source rows and columns its block of outputs
- * can reach into LDS, then does every path's gather from there.  Frames whose smallest
- * window exceeds the budget gather straight from memory.  0 disables staging; at most
- * 65536.  Default 40 KiB.  Takes effect at the next otfs_plan_bind. */
+/* LDS budget per workgroup of the fused kernel (bytes, at most 65536, default 40 KiB;
+ * takes effect at the next otfs_plan_bind).  A frame of one tile whose five CG vectors
+ * (5 * M*N * 8 bytes) fit is solved with the vectors resident in LDS (not with the bf16
+ * stored D or the refresh).  Other frames stage the gather windows of H and H^H
+ * (Eqs. sparse_mvm, sparse_herm_mvm): a workgroup copies the source rows and columns its
+ * block of outputs can reach into LDS, then does every path's gather from there; frames
+ * whose smallest window exceeds the budget gather straight from memory.  0 turns both
+ * off. */
 otfs_status otfs_plan_set_staging(otfs_plan_t* plan, int32_t lds_bytes);
 
 /* ------------------------------------------------------------------------------------ */

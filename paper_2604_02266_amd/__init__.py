@@ -62,7 +62,8 @@ class PlanInfo(ctypes.Structure):
                 ("grid", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("max_paths", ctypes.c_int32), ("tile_elems", ctypes.c_int32),
                 ("groups", ctypes.c_int32), ("xcd_local", ctypes.c_int32),
-                ("lds_bytes", ctypes.c_int32)]
+                ("lds_bytes", ctypes.c_int32), ("staged_frames", ctypes.c_int32),
+                ("resident_frames", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):

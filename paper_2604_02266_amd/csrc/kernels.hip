@@ -744,6 +744,145 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   if (wi.tile == 0 && threadIdx.x == 0) *F.st = s;
 }
 
+// ---------------------------------------------------------------------------------------
+// A small frame handled by one workgroup with x, c, p, t and a resident in LDS for the
+// whole solve: y is read once (b = H^H y), x_hat and the decisions are written once, and
+// every pass in between runs out of LDS with no per-frame barrier.  Same schedule and
+// arithmetic as cg_item for one tile (the deferred updates are applied in place before
+// the gathers, all of which are then of the finished p').  When a serving step ends
+// before the frame does, x, c and p are saved to the frame's vectors (p in p0) and
+// reloaded by the next launch.
+// ---------------------------------------------------------------------------------------
+__device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, float* red,
+                                 float2* lds) {
+  const FrameVecs V = frame_vecs(F, B);
+  FrameState s = *F.st;
+  if (s.status != OTFS_FRAME_RUNNING) return;
+  const int N = F.N;
+  const int E = F.M * F.N;
+  float2* xs = lds;
+  float2* cs = lds + E;
+  float2* ps = lds + 2 * E;
+  float2* ts = lds + 3 * E;
+  float2* as = lds + 4 * E;
+  const float lam = F.lam;
+  const bool dec = V.sym != nullptr && F.qside > 0;
+  auto finish = [&](bool xpending, int status) {
+    for (int q = threadIdx.x; q < E; q += kBlock) {
+      float2 xv = xs[q];
+      if (xpending) xv = axpyf(s.alpha, ps[q], xv);
+      V.x[q] = xv;
+      if (dec) V.sym[q] = decide(xv, F.qscale, F.qside);
+    }
+    if (threadIdx.x == 0) {
+      if (V.stats) {
+        otfs_frame_stats st{s.iter, s.rel, status, 1};
+        *V.stats = st;
+      }
+      FrameState o = s;
+      o.status = status;
+      o.pending = 0;
+      *F.st = o;
+    }
+  };
+
+  if (!s.init) {
+    // b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line)
+    float acc = 0.f;
+    band_apply<kRows, kPaths, true, false>(
+        F, 0, N, [&](int i) { return load_y(V.y, i, V.ybf16); },
+        [&](int q, float2 v) {
+          cs[q] = v;
+          ps[q] = v;
+          xs[q] = make_float2(0.f, 0.f);
+          acc = fmaf(v.x, v.x, acc);
+          acc = fmaf(v.y, v.y, acc);
+        });
+    const float cn0 = block_sum(acc, red);
+    s.init = 1;
+    s.iter = 0;
+    s.pbuf = 0;
+    s.pending = 0;
+    s.cn = cn0;
+    s.cn0 = cn0;
+    s.alpha = 0.f;
+    s.beta = 0.f;
+    s.rel = cn0 > 0.f ? 1.f : 0.f;
+    if (!(cn0 > 0.f)) return finish(false, cn0 == 0.f ? OTFS_FRAME_CONVERGED : OTFS_FRAME_NONFINITE);
+  } else {
+    for (int q = threadIdx.x; q < E; q += kBlock) {
+      xs[q] = V.x[q];
+      cs[q] = F.c[q];
+      ps[q] = F.p0[q];
+    }
+    __syncthreads();
+  }
+
+  for (int step = 0; step < budget; ++step) {
+    const int xi = s.iter + 1;
+    const bool xp = (s.pending & 1) != 0;
+    const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
+    // A: deferred updates in place, then t = H p'
+    for (int q = threadIdx.x; q < E; q += kBlock) {
+      const float2 po = ps[q];
+      if (xp) xs[q] = axpyf(al, po, xs[q]);
+      ps[q] = axpyf(be, po, cs[q]);
+    }
+    __syncthreads();
+    band_apply<kRows, kPaths, false, false>(
+        F, 0, N, [&](int i) { return ps[i]; }, [&](int q, float2 v) { ts[q] = v; });
+    __syncthreads();
+    // B: a = H^H t + lam p', Re(p'^H a)
+    float acc = 0.f;
+    band_apply<kRows, kPaths, true, false>(
+        F, 0, N, [&](int i) { return ts[i]; },
+        [&](int q, float2 v) {
+          const float2 p = ps[q];
+          const float2 a = axpyf(lam, p, v);
+          as[q] = a;
+          acc = fmaf(p.x, a.x, acc);
+          acc = fmaf(p.y, a.y, acc);
+        });
+    const float den = block_sum(acc, red);
+    s.pending = 0;
+    const float alpha = s.cn / den;
+    if (!(den > 0.f) || !isfinite(alpha)) {
+      const int st = (isfinite(den) && isfinite(s.cn)) ? OTFS_FRAME_BREAKDOWN
+                                                        : OTFS_FRAME_NONFINITE;
+      return finish(false, st);
+    }
+    // C: c -= alpha a, ||c||^2
+    acc = 0.f;
+#pragma unroll 4
+    for (int q = threadIdx.x; q < E; q += kBlock) {
+      const float2 c = axpyf(-alpha, as[q], cs[q]);
+      cs[q] = c;
+      acc = fmaf(c.x, c.x, acc);
+      acc = fmaf(c.y, c.y, acc);
+    }
+    const float cn_new = block_sum(acc, red);
+    s.iter = xi;
+    s.alpha = alpha;
+    s.rel = sqrtf(cn_new / s.cn0);
+    if (!isfinite(cn_new)) return finish(true, OTFS_FRAME_NONFINITE);
+    if (F.tol > 0.f && s.rel <= F.tol) return finish(true, OTFS_FRAME_CONVERGED);
+    if (xi >= F.max_iters) return finish(true, OTFS_FRAME_CAPPED);
+    s.beta = cn_new / s.cn;
+    s.cn = cn_new;
+    s.pending = 3;
+  }
+  // iteration budget of this launch used up: save the vectors and the state
+  for (int q = threadIdx.x; q < E; q += kBlock) {
+    V.x[q] = xs[q];
+    F.c[q] = cs[q];
+    F.p0[q] = ps[q];
+  }
+  if (threadIdx.x == 0) {
+    s.pbuf = 0;
+    *F.st = s;
+  }
+}
+
 // XCC (XCD) this wave runs on, from the hardware register XCC_ID, bits [3:0].
 __device__ __forceinline__ int xcc_id() {
   return (int)(__builtin_amdgcn_s_getreg((15 << 11) | (0 << 6) | 20) & 0xfu);
@@ -788,7 +927,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict_
     __syncthreads();
     if (it < 0) break;
     const WorkItem wi = items[it];
-    cg_item<STORED, REFRESH>(frames[wi.frame], wi, budget, B, L, red, redd, &sflag, stage_lds);
+    const FrameDev& F = frames[wi.frame];
+    if (!STORED && !REFRESH && F.resident)
+      cg_item_resident(F, budget, B, red, stage_lds);
+    else
+      cg_item<STORED, REFRESH>(F, wi, budget, B, L, red, redd, &sflag, stage_lds);
     __syncthreads();
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

@@ -67,6 +67,9 @@ struct FrameDev {
   // sub-band of one staged block, and the delay / Doppler shift ranges of the paths
   int32_t skc, ssb;
   int32_t tau_lo, tau_hi, nu_lo, nu_hi;
+  // 1: a one-workgroup frame whose five CG vectors (x, c, p, t, a) live in LDS for the
+  // whole solve (y read once, x written once)
+  int32_t resident;
 };
 
 // One workgroup's share of one frame: Doppler rows [l_begin, l_end), all delay columns.

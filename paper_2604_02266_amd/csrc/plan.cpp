@@ -131,6 +131,22 @@ void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const 
   d->tau_hi = geo.tau_hi;
   d->nu_lo = geo.nu_lo;
   d->nu_hi = geo.nu_hi;
+  d->resident = geo.resident;
+}
+
+int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opts& o,
+                 int budget_bytes, FrameDev* geo) {
+  std::memset(geo, 0, sizeof(FrameDev));
+  const int64_t E = (int64_t)f.M * f.N;
+  const bool stored = (o.flags & OTFS_D_STORED_BF16) != 0;
+  if (tiles == 1 && !stored && o.refresh_every == 0 &&
+      E * kResidentVecs * (int64_t)sizeof(float2) <= budget_bytes) {
+    stage_geometry(f, band_rows, 0, geo);   // shift ranges only; no staging
+    geo->resident = 1;
+    return (int)(E * kResidentVecs * (int64_t)sizeof(float2));
+  }
+  return stage_geometry(f, band_rows, budget_bytes / (int)sizeof(float2), geo) *
+         (int)sizeof(float2);
 }
 
 // W[l] = e^{j 2 pi l / N}
@@ -417,6 +433,12 @@ extern "C" otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t*
   info->groups = plan->ngroups;
   info->xcd_local = plan->xcd_local ? 1 : 0;
   info->lds_bytes = plan->lds_bytes;
+  info->staged_frames = 0;
+  info->resident_frames = 0;
+  for (const FrameDev& d : plan->h_frames) {
+    info->staged_frames += d.skc > 0 ? 1 : 0;
+    info->resident_frames += d.resident ? 1 : 0;
+  }
   return OTFS_OK;
 }
 
@@ -458,20 +480,20 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   plan->device = dev;
   plan->drop_graph();
 
-  // staged-gather geometry per frame (decides the dynamic LDS of the launches)
+  // LDS use per frame: resident vectors or staged-gather windows (decides the dynamic LDS
+  // of the launches)
   std::vector<FrameDev> geo(plan->frames.size());
-  int max_win = 0;
+  int max_lds = 0;
   for (size_t f = 0; f < plan->frames.size(); ++f) {
     int band = 1;
     for (int t = 0; t < plan->tiles[f]; ++t) {
       const WorkItem& w = plan->items[plan->tile_base[f] + t];
       band = std::max(band, w.l_end - w.l_begin);
     }
-    std::memset(&geo[f], 0, sizeof(FrameDev));
-    max_win = std::max(max_win, stage_geometry(plan->frames[f], band,
-                                               plan->stage_bytes / (int)sizeof(float2), &geo[f]));
+    max_lds = std::max(max_lds, lds_geometry(plan->frames[f], plan->tiles[f], band, plan->opts,
+                                             plan->stage_bytes, &geo[f]));
   }
-  plan->lds_bytes = max_win * (int)sizeof(float2);
+  plan->lds_bytes = max_lds;
 
   // work queues of the fused kernel (need the occupancy and XCD layout of this device)
   const bool stored_mode = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;

@@ -69,6 +69,12 @@ otfs_status probe_xcds(int device, void* scratch_dev, hipStream_t s, XcdInfo* ou
 // Staged-gather geometry of one frame whose widest tile has band_rows rows: fills
 // skc/ssb (0 = direct gathers) and the shift ranges; returns the window size in elements.
 int stage_geometry(const HostFrame& f, int band_rows, int budget_elems, FrameDev* d);
+// LDS use of one frame within budget_bytes: the resident form for a one-tile frame whose
+// vectors fit (no stored D, no refresh), else staged windows, else none.  Fills the
+// geometry fields of *geo (resident, skc, ssb, shift ranges); returns the bytes it needs.
+constexpr int kResidentVecs = 5;
+int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opts& o,
+                 int budget_bytes, FrameDev* geo);
 constexpr int kProbeBlocks = 1024;
 
 }  // namespace otfs

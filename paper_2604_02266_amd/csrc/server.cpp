@@ -561,7 +561,7 @@ extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* fram
   r->items = items;
   int band = 1;
   for (const WorkItem& w : items) band = std::max(band, w.l_end - w.l_begin);
-  stage_geometry(r->hf, band, kDefaultStageBytes / (int)sizeof(float2), &r->geo);
+  lds_geometry(r->hf, r->tiles, band, S->opts, kDefaultStageBytes, &r->geo);
   if (r->tiles > S->cap || r->tiles > kMaxItems)
     return fail(OTFS_E_UNSUPPORTED, "frame needs %d cooperating workgroups, %d fit", r->tiles,
                 std::min(S->cap, kMaxItems));

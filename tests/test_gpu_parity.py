@@ -162,6 +162,27 @@ def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent, stage):
     _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
 
 
+def test_cg_resident_small_frames(otfs):
+    # one-tile frames whose vectors fit in LDS run the resident form; with the LDS budget
+    # set to zero the same frames run the memory-resident form
+    frames = _mixed_frames(21, 8, [(64, 16), (32, 32), (37, 11), (8, 4), (5, 3), (16, 64),
+                                   (1, 7), (100, 10)], (1, 6), 12, 4)
+    ops, xs, y = oracle_batch(frames)
+    say("cg resident small frames", [(f.spec.M, f.spec.N, f.spec.P) for f in frames])
+    res = otfs.Plan([f.spec for f in frames])
+    assert res.info().resident_frames == len(frames)
+    out_res = _run(otfs, res, y)
+    _cg_check(out_res, frames, ops, y, NMSE_TOL, "resident")
+    say("cg small frames without LDS")
+    mem = otfs.Plan([f.spec for f in frames], stage_bytes=0)
+    assert mem.info().resident_frames == 0 and mem.info().lds_bytes == 0
+    out_mem = _run(otfs, mem, y)
+    _cg_check(out_mem, frames, ops, y, NMSE_TOL, "memory")
+    assert np.array_equal(out_res[2]["iters"], out_mem[2]["iters"])
+    for a, b in zip(split(out_res[0], frames), split(out_mem[0], frames)):
+        assert O.nmse(a, b) <= 1e-10
+
+
 def test_cg_fresh_plans_reusing_memory(otfs):
     # Regression: each new plan gets memory that earlier plans (other frame-to-XCD
     # assignments) used; stale cache lines must not leak into the solve.
