@@ -69,6 +69,108 @@ __device__ __forceinline__ float2 axpyf(float s, float2 p, float2 c) {
 }
 
 // ---------------------------------------------------------------------------------------
+// memory views
+// ---------------------------------------------------------------------------------------
+// Pointers kept in frame descriptors are generic; these casts tell the compiler which
+// memory they address, so that accesses become global (not flat) instructions, and
+// wave-uniform table reads through a constant view become scalar loads.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+using kptr = __attribute__((address_space(4))) T*;
+template <class T>
+using lptr = __attribute__((address_space(3))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+typedef unsigned long long u64;
+// 8-byte pairs (complex64, int pairs) are moved as 64-bit words through these views.
+struct GPairs {   // global table
+  gptr<const u64> p;
+  __device__ __forceinline__ float2 f(int64_t i) const { return __builtin_bit_cast(float2, p[i]); }
+};
+struct KPairs {   // wave-uniform table: scalar loads
+  kptr<const u64> p;
+  __device__ __forceinline__ float2 f(int i) const { return __builtin_bit_cast(float2, p[i]); }
+  __device__ __forceinline__ int2 i2(int i) const { return __builtin_bit_cast(int2, p[i]); }
+};
+struct LdsC {     // complex64 array in LDS
+  lptr<u64> p;
+  __device__ __forceinline__ float2 ld(int i) const { return __builtin_bit_cast(float2, p[i]); }
+  __device__ __forceinline__ void st(int i, float2 v) const { p[i] = __builtin_bit_cast(u64, v); }
+  __device__ __forceinline__ LdsC operator+(int o) const { return LdsC{p + o}; }
+};
+__device__ __forceinline__ GPairs gpairs(const void* t) { return GPairs{(gptr<const u64>)t}; }
+__device__ __forceinline__ KPairs kpairs(const void* t) { return KPairs{(kptr<const u64>)t}; }
+__device__ __forceinline__ LdsC lds_c(void* t) { return LdsC{(lptr<u64>)t}; }
+
+// A vector of `bytes` bytes read through a buffer resource: the base stays in SGPRs and
+// each read takes one 32-bit byte offset (frames hold at most 2^28 elements, so every
+// offset fits).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int64_t bytes) {
+  const uint32_t n = bytes > 0xffffffffLL ? 0xffffffffu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, 0x00020000);
+}
+
+// Source views of a band application: load(i) issues the reads of element i, value(raw)
+// forms the element from them.
+struct SrcBuf {   // complex64 vector
+  __amdgpu_buffer_rsrc_t r;
+  using Raw = float2;
+  __device__ __forceinline__ Raw load(uint32_t i) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+  }
+  __device__ __forceinline__ float2 value(Raw v) const { return v; }
+};
+struct SrcBf16 {  // complex stored as a bf16 pair per element
+  __amdgpu_buffer_rsrc_t r;
+  using Raw = uint32_t;
+  __device__ __forceinline__ Raw load(uint32_t i) const {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0);
+  }
+  __device__ __forceinline__ float2 value(Raw v) const { return bf16x2_to_f2(v); }
+};
+struct SrcDir {   // the new direction c + beta p, formed from c and the old p
+  __amdgpu_buffer_rsrc_t c, p;
+  float beta;
+  struct Raw {
+    float2 c, p;
+  };
+  __device__ __forceinline__ Raw load(uint32_t i) const {
+    return Raw{__builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(c, i * 8u, 0, 0)),
+               __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(p, i * 8u, 0, 0))};
+  }
+  __device__ __forceinline__ float2 value(const Raw& v) const { return axpyf(beta, v.p, v.c); }
+};
+struct SrcLds {   // complex64 vector in LDS
+  LdsC v;
+  using Raw = float2;
+  __device__ __forceinline__ Raw load(uint32_t i) const { return v.ld((int)i); }
+  __device__ __forceinline__ float2 value(Raw x) const { return x; }
+};
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+// A complex64 vector read and written element-wise through a buffer resource (one 32-bit
+// offset per element, shared by every vector accessed at that element).
+struct CVec {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ float2 ld(uint32_t i) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+  }
+  __device__ __forceinline__ void st(uint32_t i, float2 v) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, 0, 0);
+  }
+};
+__device__ __forceinline__ CVec cvec(const float2* p, int64_t n) { return CVec{buf_rsrc(p, n * 8)}; }
+__device__ __forceinline__ SrcBuf src_vec(const float2* p, int64_t n) {
+  return SrcBuf{buf_rsrc(p, n * 8)};
+}
+__device__ __forceinline__ SrcDir src_dir(const float2* c, const float2* p, float beta,
+                                          int64_t n) {
+  return SrcDir{buf_rsrc(c, n * 8), buf_rsrc(p, n * 8), beta};
+}
+
+// ---------------------------------------------------------------------------------------
 // reductions: wave64 butterfly, then the waves of the block in a fixed order
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ float wave_sum(float v) {
@@ -201,12 +303,20 @@ __device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
 // contiguous run of a source row across the wave, and the coefficient of the column is
 // loaded once per (chunk, path).  Nothing is sized by P, so one kernel serves every P.
 //
-// src(i) returns element i (frame-local index) of the vector being multiplied;
-// sink(q, v) receives output element q.  Threads without a column return early; callers
-// put block-wide work after the call.
+// src is a source view (see SrcBuf): src.load(i) issues the reads of element i (frame-local
+// index) of the vector being multiplied and src.value(raw) forms the element; every read
+// of a chunk is issued before the first value is formed, and no read sits under a
+// branch, so the R*U gathers of a chunk are in flight together.  Rows past the end of the
+// band repeat the band's last row and are not stored.  sink(q, v) receives output element
+// q.  Threads without a column return early; callers put block-wide work after the call.
+//
+// Wrap factor.  W[l0]^n with l0 the source row: for H, l0 = <l - nu>_N and
+// W[l0] = W[l] conj(W[nu]), so the path part conj(W[nu])^n is folded into the column's
+// coefficient and only W[l]^n (one table read per row of the chunk) varies along the
+// band; for H^H the factor is W[l]^w of the output row itself.
 // ---------------------------------------------------------------------------------------
 #ifndef OTFS_ROWS
-#define OTFS_ROWS 4
+#define OTFS_ROWS 2
 #endif
 #ifndef OTFS_PATHS
 #define OTFS_PATHS 2
@@ -214,9 +324,18 @@ __device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
 constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
 constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
 constexpr int kRows64 = 4;   // rows per thread chunk in the FP64 refresh gathers
+#ifndef OTFS_RES_ROWS
+#define OTFS_RES_ROWS 2
+#endif
+#ifndef OTFS_RES_PATHS
+#define OTFS_RES_PATHS 1
+#endif
+constexpr int kResRows = OTFS_RES_ROWS;    // rows per chunk of the LDS-resident gathers
+constexpr int kResPaths = OTFS_RES_PATHS;  // paths per step of the LDS-resident gathers
 
 template <int R, int U, bool ADJ, bool STORED, class Src, class Sink>
-__device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Src src, Sink sink) {
+__device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
+                                           Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
   const int TY = kBlock / TX;
@@ -224,72 +343,74 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Sr
   if (ty >= TY) return;
   const int64_t E = (int64_t)M * N;
   const int nrows = le - lb - ty > 0 ? (le - lb - ty + TY - 1) / TY : 0;
-  const int2* __restrict__ paths = F.paths;
-  const float2* __restrict__ rtab = F.rtab;
-  const float2* __restrict__ wtab = F.wtab;
+  const KPairs paths = kpairs(F.paths);
+  const KPairs wtab_s = kpairs(F.wtab);
+  const GPairs rtab = gpairs(F.rtab);
+  const GPairs wtab = gpairs(F.wtab);
+  const gptr<const uint32_t> dtab = glb(F.dtab);
   for (int k = tx; k < M; k += TX) {
     for (int r0 = 0; r0 < nrows; r0 += R) {
+      int l[R];
+      float2 wl[R];
       float2 acc[R];
 #pragma unroll
-      for (int i = 0; i < R; ++i) acc[i] = make_float2(0.f, 0.f);
+      for (int i = 0; i < R; ++i) {
+        l[i] = lb + ty + min(r0 + i, nrows - 1) * TY;
+        if (!STORED) wl[i] = wtab.f(l[i]);
+        acc[i] = make_float2(0.f, 0.f);
+      }
       // NP paths at once: all NP*R gathers are issued before any is consumed
       auto step = [&](auto npc, int p0) {
         constexpr int NP = decltype(npc)::value;
         int kk[NP], nw[NP], nuv[NP];
-        float2 cf[NP];
+        float2 cf[NP], cw[NP];
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
-          const int2 tn = paths[p0 + u];
+          const int2 tn = paths.i2(p0 + u);
           const int K = ADJ ? k + tn.x : k - tn.x;   // H: <k - tau>_M; H^H: <k + tau>_M
           nw[u] = K < 0 ? -1 : (K >= M ? 1 : 0);     // wrap count
           kk[u] = K - nw[u] * M;
           nuv[u] = tn.y;
           if (!STORED) {
-            const float2 r = rtab[(p0 + u) * M + (ADJ ? kk[u] : k)];
+            const float2 r = rtab.f((p0 + u) * M + (ADJ ? kk[u] : k));
             cf[u] = ADJ ? make_float2(r.x, -r.y) : r;
+            if (ADJ) {
+              cw[u] = cf[u];
+            } else {
+              const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
+              cw[u] = cmulf(cf[u], make_float2(wn.x, nw[u] > 0 ? -wn.y : wn.y));
+            }
           }
         }
-        float2 v[NP][R];
-        float2 d[NP][R];
+        typename Src::Raw v[NP][R];
+        uint32_t d[NP][R];
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
 #pragma unroll
           for (int i = 0; i < R; ++i) {
-            if (r0 + i < nrows) {
-              const int l = lb + ty + (r0 + i) * TY;
-              int ls = ADJ ? l + nuv[u] : l - nuv[u];
-              ls += ls < 0 ? N : 0;
-              ls -= ls >= N ? N : 0;
-              const int qs = ls * M + kk[u];
-              v[u][i] = src(qs);
-              if (STORED)
-                d[u][i] = bf16x2_to_f2(
-                    F.dtab[(int64_t)(p0 + u) * E + (ADJ ? (int64_t)qs : (int64_t)l * M + k)]);
-            }
+            int ls = ADJ ? l[i] + nuv[u] : l[i] - nuv[u];
+            ls += ls < 0 ? N : 0;
+            ls -= ls >= N ? N : 0;
+            const int qs = ls * M + kk[u];
+            v[u][i] = src.load((uint32_t)qs);
+            if (STORED)
+              d[u][i] = dtab[(int64_t)(p0 + u) * E + (ADJ ? (int64_t)qs : (int64_t)l[i] * M + k)];
           }
         }
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
 #pragma unroll
           for (int i = 0; i < R; ++i) {
-            if (r0 + i < nrows) {
-              float2 c;
-              if (STORED) {
-                c = ADJ ? make_float2(d[u][i].x, -d[u][i].y) : d[u][i];
-              } else {
-                c = cf[u];
-                if (nw[u] != 0) {   // H: W[source row]^n;  H^H: W[own row]^w
-                  const int l = lb + ty + (r0 + i) * TY;
-                  int ls = l - nuv[u];
-                  ls += ls < 0 ? N : 0;
-                  ls -= ls >= N ? N : 0;
-                  float2 w = wtab[ADJ ? l : ls];
-                  if (nw[u] < 0) w.y = -w.y;
-                  c = cmulf(c, w);
-                }
-              }
-              cmacf(acc[i], c, v[u][i]);
+            float2 c;
+            if (STORED) {
+              const float2 dd = bf16x2_to_f2(d[u][i]);
+              c = ADJ ? make_float2(dd.x, -dd.y) : dd;
+            } else {
+              const float2 w = make_float2(wl[i].x, nw[u] > 0 ? wl[i].y : -wl[i].y);
+              const float2 cr = cmulf(cw[u], w);
+              c = nw[u] != 0 ? cr : cf[u];
             }
+            cmacf(acc[i], c, src.value(v[u][i]));
           }
         }
       };
@@ -298,7 +419,7 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Sr
       for (; p < P; ++p) step(std::integral_constant<int, 1>{}, p);
 #pragma unroll
       for (int i = 0; i < R; ++i)
-        if (r0 + i < nrows) sink((lb + ty + (r0 + i) * TY) * M + k, acc[i]);
+        if (r0 + i < nrows) sink(l[i] * M + k, acc[i]);
     }
   }
 }
@@ -310,14 +431,17 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, Sr
 // workgroup first copies into LDS every source element its outputs can reach -- the rows
 // shifted by [nu_lo, nu_hi] and the columns shifted by [tau_lo, tau_hi] (whole rows when
 // skc = M, all N rows when the row window wraps the frame) -- with coalesced loads issued
-// in batches, then runs every path's gather from LDS.  The staged value is stage(i) of
-// the source element, computed once per element (phase A stages c + beta p).
+// in batches, then runs every path's gather from LDS.  The staged value of a source
+// element is formed once (phase A stages c + beta p).
 // ---------------------------------------------------------------------------------------
-constexpr int kStageBatch = 8;   // staging loads in flight per thread
+#ifndef OTFS_STAGE_BATCH
+#define OTFS_STAGE_BATCH 2
+#endif
+constexpr int kStageBatch = OTFS_STAGE_BATCH;   // staging loads in flight per thread
 
-template <bool ADJ, class Stage, class Sink>
-__device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, float2* lds,
-                                             Stage stage, Sink sink) {
+template <bool ADJ, class Src, class Sink>
+__device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, float2* lds_gen,
+                                             const Src& src, Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int KC = F.skc, SB = F.ssb;
   const int dtau = F.tau_hi - F.tau_lo, dnu = F.nu_hi - F.nu_lo;
@@ -326,9 +450,11 @@ __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, 
   const int TYc = kBlock / TXc;
   const int tx = threadIdx.x % TXc, ty = threadIdx.x / TXc;
   const bool active = ty < TYc;
-  const int2* __restrict__ paths = F.paths;
-  const float2* __restrict__ rtab = F.rtab;
-  const float2* __restrict__ wtab = F.wtab;
+  const LdsC lds = lds_c(lds_gen);
+  const KPairs paths = kpairs(F.paths);
+  const KPairs wtab_s = kpairs(F.wtab);
+  const GPairs rtab = gpairs(F.rtab);
+  const GPairs wtab = gpairs(F.wtab);
   for (int sb0 = lb; sb0 < le; sb0 += SB) {
     const int sbn = min(SB, le - sb0);
     const bool full_rows = sbn + dnu >= N;
@@ -342,71 +468,69 @@ __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, 
       const float inv_wc = 1.0f / (float)WC;
       __syncthreads();                         // the previous block's readers are done
       for (int e0 = 0; e0 < nwin; e0 += kBlock * kStageBatch) {
-        float2 v[kStageBatch];
-        int at[kStageBatch];
+        // window elements past the end re-read the last one and are not stored
+        typename Src::Raw v[kStageBatch];
+#pragma unroll
+        for (int j = 0; j < kStageBatch; ++j) {
+          const int e = min(e0 + j * kBlock + (int)threadIdx.x, nwin - 1);
+          int r = (int)((float)e * inv_wc);
+          int c = e - r * WC;
+          if (c < 0) { --r; c += WC; }
+          if (c >= WC) { ++r; c -= WC; }
+          int sr = row0 + r;
+          sr += sr < 0 ? N : 0;
+          sr -= sr >= N ? N : 0;
+          int sc = col0 + c;
+          sc += sc < 0 ? M : 0;
+          sc -= sc >= M ? M : 0;
+          v[j] = src.load((uint32_t)(sr * M + sc));
+        }
 #pragma unroll
         for (int j = 0; j < kStageBatch; ++j) {
           const int e = e0 + j * kBlock + (int)threadIdx.x;
-          at[j] = -1;
-          if (e < nwin) {
-            int r = (int)((float)e * inv_wc);
-            int c = e - r * WC;
-            if (c < 0) { --r; c += WC; }
-            if (c >= WC) { ++r; c -= WC; }
-            int sr = row0 + r;
-            sr += sr < 0 ? N : 0;
-            sr -= sr >= N ? N : 0;
-            int sc = col0 + c;
-            sc += sc < 0 ? M : 0;
-            sc -= sc >= M ? M : 0;
-            v[j] = stage(sr * M + sc);
-            at[j] = e;
-          }
+          if (e < nwin) lds.st(e, src.value(v[j]));
         }
-#pragma unroll
-        for (int j = 0; j < kStageBatch; ++j)
-          if (at[j] >= 0) lds[at[j]] = v[j];
       }
       __syncthreads();
       if (!active) continue;
+      // the wrap factor W[l]^n of each row (see band_apply), read once per block row
+      float2 wl[kStageRows];
+#pragma unroll
+      for (int i = 0; i < kStageRows; ++i) wl[i] = wtab.f(sb0 + min(ty + i * TYc, sbn - 1));
       for (int cc = tx; cc < kcn; cc += TXc) {
         const int k = k0 + cc;
         float2 acc[kStageRows];
 #pragma unroll
         for (int i = 0; i < kStageRows; ++i) acc[i] = make_float2(0.f, 0.f);
         for (int p = 0; p < P; ++p) {
-          const int2 tn = paths[p];
+          const int2 tn = paths.i2(p);
           const int K = ADJ ? k + tn.x : k - tn.x;
           const int n = K < 0 ? -1 : (K >= M ? 1 : 0);
           const int kk = K - n * M;
-          const float2 r = rtab[p * M + (ADJ ? kk : k)];
+          const float2 r = rtab.f(p * M + (ADJ ? kk : k));
           const float2 cf = ADJ ? make_float2(r.x, -r.y) : r;
+          float2 cw = cf;
+          if (!ADJ) {
+            const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
+            cw = cmulf(cf, make_float2(wn.x, n > 0 ? -wn.y : wn.y));
+          }
           const int lc = full_cols ? kk : (ADJ ? cc + (tn.x - F.tau_lo) : cc + (F.tau_hi - tn.x));
 #pragma unroll
           for (int i = 0; i < kStageRows; ++i) {
-            const int rr = ty + i * TYc;
-            if (rr < sbn) {
-              const int l = sb0 + rr;
-              int lr;
-              if (full_rows) {
-                lr = ADJ ? l + tn.y : l - tn.y;
-                lr += lr < 0 ? N : 0;
-                lr -= lr >= N ? N : 0;
-              } else {
-                lr = ADJ ? rr + (tn.y - F.nu_lo) : rr + (F.nu_hi - tn.y);
-              }
-              const float2 val = lds[lr * WC + lc];
-              float2 c = cf;
-              if (n != 0) {   // H: W[source row]^n;  H^H: W[own row]^w
-                int ls = l - tn.y;
-                ls += ls < 0 ? N : 0;
-                ls -= ls >= N ? N : 0;
-                float2 w = wtab[ADJ ? l : ls];
-                if (n < 0) w.y = -w.y;
-                c = cmulf(c, w);
-              }
-              cmacf(acc[i], c, val);
+            const int rr = min(ty + i * TYc, sbn - 1);
+            const int l = sb0 + rr;
+            int lr;
+            if (full_rows) {
+              lr = ADJ ? l + tn.y : l - tn.y;
+              lr += lr < 0 ? N : 0;
+              lr -= lr >= N ? N : 0;
+            } else {
+              lr = ADJ ? rr + (tn.y - F.nu_lo) : rr + (F.nu_hi - tn.y);
             }
+            const float2 val = lds.ld(lr * WC + lc);
+            const float2 w = make_float2(wl[i].x, n > 0 ? wl[i].y : -wl[i].y);
+            const float2 cr = cmulf(cw, w);
+            cmacf(acc[i], n != 0 ? cr : cf, val);
           }
         }
 #pragma unroll
@@ -423,7 +547,7 @@ __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, 
 // gathered straight from memory otherwise.
 template <bool ADJ, bool STORED, class Src, class Sink>
 __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, float2* lds,
-                                           Src src, Sink sink) {
+                                           const Src& src, Sink sink) {
   if (!STORED && F.skc > 0 && lds != nullptr)
     staged_apply<ADJ>(F, lb, le, lds, src, sink);
   else
@@ -575,10 +699,9 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   const int lb = wi.l_begin, le = wi.l_end;
   const int64_t q0 = (int64_t)lb * M, q1 = (int64_t)le * M;
   const float lam = F.lam;
-  float2* cvec = F.c;
-  float2* tvec = F.t;
-  float2* avec = F.a;
-  float2* xvec = V.x;
+  const int64_t E = (int64_t)M * F.N;
+  const uint32_t u0 = (uint32_t)q0, u1 = (uint32_t)q1;
+  const CVec cv = cvec(F.c, E), tv = cvec(F.t, E), av = cvec(F.a, E), xv = cvec(V.x, E);
   unsigned nbar = 0;
   auto bar = [&]() -> bool {
     if (T == 1) {
@@ -603,15 +726,18 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line) ----
   if (!s.init) {
     float acc = 0.f;
-    apply_band<true, STORED>(
-        F, lb, le, lds, [&](int i) { return load_y(V.y, i, V.ybf16); },
-        [&](int q, float2 v) {
-          cvec[q] = v;
-          F.p0[q] = v;
-          xvec[q] = make_float2(0.f, 0.f);
-          acc = fmaf(v.x, v.x, acc);
-          acc = fmaf(v.y, v.y, acc);
-        });
+    const CVec p0 = cvec(F.p0, E);
+    auto sink = [&](int q, float2 v) {
+      cv.st((uint32_t)q, v);
+      p0.st((uint32_t)q, v);
+      xv.st((uint32_t)q, make_float2(0.f, 0.f));
+      acc = fmaf(v.x, v.x, acc);
+      acc = fmaf(v.y, v.y, acc);
+    };
+    if (V.ybf16)
+      apply_band<true, STORED>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, sink);
+    else
+      apply_band<true, STORED>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, sink);
     const float bs = block_sum(acc, red);
     if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
     if (!bar()) return fail_timeout();
@@ -633,20 +759,22 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
 
   for (int step = 0; step < budget; ++step) {
     const int xi = s.iter + 1;
-    float2* pold = s.pbuf ? F.p1 : F.p0;
-    float2* pnew = s.pbuf ? F.p0 : F.p1;
+    float2* const pold_g = s.pbuf ? F.p1 : F.p0;
+    float2* const pnew_g = s.pbuf ? F.p0 : F.p1;
+    const CVec pov = cvec(pold_g, E), pnv = cvec(pnew_g, E);
     // iteration 1 has no pending update: beta = 0 gives p_new = c = b exactly
     const bool xp = (s.pending & 1) != 0;
     const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
 
     // ---- A: deferred updates of the band, t = H p ----
     apply_band<false, STORED>(
-        F, lb, le, lds, [&](int i) { return axpyf(be, pold[i], cvec[i]); },
+        F, lb, le, lds, SrcDir{cv.r, pov.r, be},
         [&](int q, float2 v) {
-          tvec[q] = v;
-          const float2 po = pold[q];
-          pnew[q] = axpyf(be, po, cvec[q]);
-          if (xp) xvec[q] = axpyf(al, po, xvec[q]);
+          const uint32_t u = (uint32_t)q;
+          tv.st(u, v);
+          const float2 po = pov.ld(u);
+          pnv.st(u, axpyf(be, po, cv.ld(u)));
+          if (xp) xv.st(u, axpyf(al, po, xv.ld(u)));
         });
     if (!bar()) return fail_timeout();
 
@@ -654,11 +782,11 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     {
       float acc = 0.f;
       apply_band<true, STORED>(
-          F, lb, le, lds, [&](int i) { return tvec[i]; },
+          F, lb, le, lds, SrcBuf{tv.r},
           [&](int q, float2 v) {
-            const float2 p = pnew[q];
+            const float2 p = pnv.ld((uint32_t)q);
             const float2 a = axpyf(lam, p, v);
-            avec[q] = a;
+            av.st((uint32_t)q, a);
             acc = fmaf(p.x, a.x, acc);
             acc = fmaf(p.y, a.y, acc);
           });
@@ -674,16 +802,16 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     if (!(den > 0.f) || !isfinite(alpha)) {          // x already holds x_{xi-1}
       const int st = (isfinite(den) && isfinite(s.cn)) ? OTFS_FRAME_BREAKDOWN
                                                         : OTFS_FRAME_NONFINITE;
-      return finish_tile(F, wi, V, s, pnew, false, st);
+      return finish_tile(F, wi, V, s, pnew_g, false, st);
     }
 
     // ---- C: c -= alpha a, partial ||c||^2 ----
     {
       float acc = 0.f;
 #pragma unroll 4
-      for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
-        const float2 c = axpyf(-alpha, avec[q], cvec[q]);
-        cvec[q] = c;
+      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock) {
+        const float2 c = axpyf(-alpha, av.ld(u), cv.ld(u));
+        cv.st(u, c);
         acc = fmaf(c.x, c.x, acc);
         acc = fmaf(c.y, c.y, acc);
       }
@@ -703,8 +831,8 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       band_apply64<kRows64, false>(
           F, lb, le,
           [&](int i) {
-            const float2 xv = axpyf(alpha, pnew[i], xvec[i]);
-            return make_double2((double)xv.x, (double)xv.y);
+            const float2 xe = axpyf(alpha, pnv.ld((uint32_t)i), xv.ld((uint32_t)i));
+            return make_double2((double)xe.x, (double)xe.y);
           },
           [&](int q, double2 v) {
             const float2 yv = load_y(V.y, q, V.ybf16);
@@ -716,11 +844,11 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       band_apply64<kRows64, true>(
           F, lb, le, [&](int i) { return F.u[i]; },
           [&](int q, double2 v) {
-            const float2 xn = axpyf(alpha, pnew[q], xvec[q]);
-            xvec[q] = xn;
+            const float2 xn = axpyf(alpha, pnv.ld((uint32_t)q), xv.ld((uint32_t)q));
+            xv.st((uint32_t)q, xn);
             const float2 cf = make_float2((float)(v.x - (double)lam * (double)xn.x),
                                           (float)(v.y - (double)lam * (double)xn.y));
-            cvec[q] = cf;
+            cv.st((uint32_t)q, cf);
             acc = fma((double)cf.x, (double)cf.x, acc);
             acc = fma((double)cf.y, (double)cf.y, acc);
           });
@@ -732,10 +860,10 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     }
 
     s.rel = sqrtf(cn_new / s.cn0);
-    if (!isfinite(cn_new)) return finish_tile(F, wi, V, s, pnew, xpend, OTFS_FRAME_NONFINITE);
+    if (!isfinite(cn_new)) return finish_tile(F, wi, V, s, pnew_g, xpend, OTFS_FRAME_NONFINITE);
     if (F.tol > 0.f && s.rel <= F.tol)
-      return finish_tile(F, wi, V, s, pnew, xpend, OTFS_FRAME_CONVERGED);
-    if (xi >= F.max_iters) return finish_tile(F, wi, V, s, pnew, xpend, OTFS_FRAME_CAPPED);
+      return finish_tile(F, wi, V, s, pnew_g, xpend, OTFS_FRAME_CONVERGED);
+    if (xi >= F.max_iters) return finish_tile(F, wi, V, s, pnew_g, xpend, OTFS_FRAME_CAPPED);
     s.beta = cn_new / s.cn;
     s.cn = cn_new;
     s.pending = (xpend ? 1 : 0) | 2;
@@ -760,17 +888,17 @@ __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, 
   if (s.status != OTFS_FRAME_RUNNING) return;
   const int N = F.N;
   const int E = F.M * F.N;
-  float2* xs = lds;
-  float2* cs = lds + E;
-  float2* ps = lds + 2 * E;
-  float2* ts = lds + 3 * E;
-  float2* as = lds + 4 * E;
+  const LdsC xs = lds_c(lds);
+  const LdsC cs = xs + E;
+  const LdsC ps = xs + 2 * E;
+  const LdsC ts = xs + 3 * E;
+  const LdsC as = xs + 4 * E;
   const float lam = F.lam;
   const bool dec = V.sym != nullptr && F.qside > 0;
   auto finish = [&](bool xpending, int status) {
     for (int q = threadIdx.x; q < E; q += kBlock) {
-      float2 xv = xs[q];
-      if (xpending) xv = axpyf(s.alpha, ps[q], xv);
+      float2 xv = xs.ld(q);
+      if (xpending) xv = axpyf(s.alpha, ps.ld(q), xv);
       V.x[q] = xv;
       if (dec) V.sym[q] = decide(xv, F.qscale, F.qside);
     }
@@ -789,15 +917,17 @@ __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, 
   if (!s.init) {
     // b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line)
     float acc = 0.f;
-    band_apply<kRows, kPaths, true, false>(
-        F, 0, N, [&](int i) { return load_y(V.y, i, V.ybf16); },
-        [&](int q, float2 v) {
-          cs[q] = v;
-          ps[q] = v;
-          xs[q] = make_float2(0.f, 0.f);
-          acc = fmaf(v.x, v.x, acc);
-          acc = fmaf(v.y, v.y, acc);
-        });
+    auto sink = [&](int q, float2 v) {
+      cs.st(q, v);
+      ps.st(q, v);
+      xs.st(q, make_float2(0.f, 0.f));
+      acc = fmaf(v.x, v.x, acc);
+      acc = fmaf(v.y, v.y, acc);
+    };
+    if (V.ybf16)
+      band_apply<kResRows, kResPaths, true, false>(F, 0, N, SrcBf16{buf_rsrc(V.y, (int64_t)E * 4)}, sink);
+    else
+      band_apply<kResRows, kResPaths, true, false>(F, 0, N, SrcBuf{buf_rsrc(V.y, (int64_t)E * 8)}, sink);
     const float cn0 = block_sum(acc, red);
     s.init = 1;
     s.iter = 0;
@@ -811,9 +941,9 @@ __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, 
     if (!(cn0 > 0.f)) return finish(false, cn0 == 0.f ? OTFS_FRAME_CONVERGED : OTFS_FRAME_NONFINITE);
   } else {
     for (int q = threadIdx.x; q < E; q += kBlock) {
-      xs[q] = V.x[q];
-      cs[q] = F.c[q];
-      ps[q] = F.p0[q];
+      xs.st(q, V.x[q]);
+      cs.st(q, F.c[q]);
+      ps.st(q, F.p0[q]);
     }
     __syncthreads();
   }
@@ -824,22 +954,22 @@ __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, 
     const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
     // A: deferred updates in place, then t = H p'
     for (int q = threadIdx.x; q < E; q += kBlock) {
-      const float2 po = ps[q];
-      if (xp) xs[q] = axpyf(al, po, xs[q]);
-      ps[q] = axpyf(be, po, cs[q]);
+      const float2 po = ps.ld(q);
+      if (xp) xs.st(q, axpyf(al, po, xs.ld(q)));
+      ps.st(q, axpyf(be, po, cs.ld(q)));
     }
     __syncthreads();
-    band_apply<kRows, kPaths, false, false>(
-        F, 0, N, [&](int i) { return ps[i]; }, [&](int q, float2 v) { ts[q] = v; });
+    band_apply<kResRows, kResPaths, false, false>(
+        F, 0, N, SrcLds{ps}, [&](int q, float2 v) { ts.st(q, v); });
     __syncthreads();
     // B: a = H^H t + lam p', Re(p'^H a)
     float acc = 0.f;
-    band_apply<kRows, kPaths, true, false>(
-        F, 0, N, [&](int i) { return ts[i]; },
+    band_apply<kResRows, kResPaths, true, false>(
+        F, 0, N, SrcLds{ts},
         [&](int q, float2 v) {
-          const float2 p = ps[q];
+          const float2 p = ps.ld(q);
           const float2 a = axpyf(lam, p, v);
-          as[q] = a;
+          as.st(q, a);
           acc = fmaf(p.x, a.x, acc);
           acc = fmaf(p.y, a.y, acc);
         });
@@ -855,8 +985,8 @@ __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, 
     acc = 0.f;
 #pragma unroll 4
     for (int q = threadIdx.x; q < E; q += kBlock) {
-      const float2 c = axpyf(-alpha, as[q], cs[q]);
-      cs[q] = c;
+      const float2 c = axpyf(-alpha, as.ld(q), cs.ld(q));
+      cs.st(q, c);
       acc = fmaf(c.x, c.x, acc);
       acc = fmaf(c.y, c.y, acc);
     }
@@ -873,9 +1003,9 @@ __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, 
   }
   // iteration budget of this launch used up: save the vectors and the state
   for (int q = threadIdx.x; q < E; q += kBlock) {
-    V.x[q] = xs[q];
-    F.c[q] = cs[q];
-    F.p0[q] = ps[q];
+    V.x[q] = xs.ld(q);
+    F.c[q] = cs.ld(q);
+    F.p0[q] = ps.ld(q);
   }
   if (threadIdx.x == 0) {
     s.pbuf = 0;
@@ -923,7 +1053,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict_
       s_item = (int)j < r.y - r.x ? qitems[r.x + (int)j] : -1;
     }
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: descriptors in SGPRs
     __syncthreads();
     if (it < 0) break;
     const WorkItem wi = items[it];
@@ -952,11 +1082,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ f
   const WorkItem wi = items[blockIdx.x];
   const FrameDev& F = frames[wi.frame];
   extern __shared__ float2 stage_lds[];
-  const float2* __restrict__ src = in + F.off;
-  float2* __restrict__ dst = out + F.off;
-  apply_band<ADJ, STORED>(
-      F, wi.l_begin, wi.l_end, stage_lds, [&](int i) { return src[i]; },
-      [&](int q, float2 v) { dst[q] = v; });
+  const int64_t E = (int64_t)F.M * F.N;
+  const CVec dst = cvec(out + F.off, E);
+  apply_band<ADJ, STORED>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
+                          [&](int q, float2 v) { dst.st((uint32_t)q, v); });
 }
 
 __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsigned* abort_flag,
@@ -1035,15 +1164,20 @@ __global__ __launch_bounds__(kBlock) void k_plain_init(const FrameDev* __restric
   const FrameDev& F = frames[f];
   const FrameVecs V = frame_vecs(F, B);
   float acc = 0.f;
-  band_apply<kRows, kPaths, true, false>(
-      F, wi.l_begin, wi.l_end, [&](int i) { return load_y(V.y, i, V.ybf16); },
-      [&](int q, float2 v) {
-        F.c[q] = v;
-        F.p0[q] = v;
-        V.x[q] = make_float2(0.f, 0.f);
-        acc = fmaf(v.x, v.x, acc);
-        acc = fmaf(v.y, v.y, acc);
-      });
+  const int64_t E = (int64_t)F.M * F.N;
+  auto sink = [&](int q, float2 v) {
+    F.c[q] = v;
+    F.p0[q] = v;
+    V.x[q] = make_float2(0.f, 0.f);
+    acc = fmaf(v.x, v.x, acc);
+    acc = fmaf(v.y, v.y, acc);
+  };
+  if (V.ybf16)
+    band_apply<kRows, kPaths, true, false>(F, wi.l_begin, wi.l_end,
+                                           SrcBf16{buf_rsrc(V.y, E * 4)}, sink);
+  else
+    band_apply<kRows, kPaths, true, false>(F, wi.l_begin, wi.l_end,
+                                           SrcBuf{buf_rsrc(V.y, E * 8)}, sink);
   const float bs = block_sum(acc, red);
   if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
 }
@@ -1069,7 +1203,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_H(const FrameDev* __restrict__
   if (F.st->status != OTFS_FRAME_RUNNING) return;
   const WorkItem wi = items[blockIdx.x];
   band_apply<kRows, kPaths, false, false>(
-      F, wi.l_begin, wi.l_end, [&](int i) { return F.p0[i]; },
+      F, wi.l_begin, wi.l_end, src_vec(F.p0, (int64_t)F.M * F.N),
       [&](int q, float2 v) { F.t[q] = v; });
 }
 
@@ -1082,7 +1216,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_HH(const FrameDev* __restrict_
   const float lam = F.lam;
   float acc = 0.f;
   band_apply<kRows, kPaths, true, false>(
-      F, wi.l_begin, wi.l_end, [&](int i) { return F.t[i]; },
+      F, wi.l_begin, wi.l_end, src_vec(F.t, (int64_t)F.M * F.N),
       [&](int q, float2 v) {
         const float2 p = F.p0[q];
         const float2 a = axpyf(lam, p, v);

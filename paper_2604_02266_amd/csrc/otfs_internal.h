@@ -91,7 +91,10 @@ struct Bases {
 
 // ---- launchers (kernels.hip) -----------------------------------------------------------
 constexpr int kMaxGroups = 16;   // work-queue groups (one per XCD in XCD-local mode)
-constexpr int kStageRows = 8;    // output rows per thread in one staged block
+#ifndef OTFS_STAGE_ROWS
+#define OTFS_STAGE_ROWS 4
+#endif
+constexpr int kStageRows = OTFS_STAGE_ROWS;   // output rows per thread in one staged block
 constexpr int kDefaultStageBytes = 40 * 1024;   // LDS per workgroup for staged windows
 
 // One workgroup per item.  in/out are batch-wide complex64 buffers (frame at base + off).

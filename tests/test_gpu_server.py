@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from helpers import check_decisions, say, to_dev
+from helpers import check_decisions, iters_close, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_server_matches_oracle_and_plan(otfs):
         nm = O.nmse(x, xr)
         assert nm <= NMSE_TOL, f"frame {i} ({sp.M}x{sp.N}): NMSE {nm:.3e}"
         assert st.status in (otfs.FRAME_CONVERGED, otfs.FRAME_CAPPED)
-        assert abs(st.iters - it_r) <= 1
+        assert iters_close(st.iters, it_r, rel_r > TOL * 1.5 and it_r == MAX_ITERS)
         assert lat > 0
         check_decisions(sym, x, xr, sp.qam)
     # the same frame through a plan with the server's tiling gives the same bits
