@@ -85,10 +85,12 @@ enum {
                                     needs a created stream, not the NULL stream             */
   OTFS_TIME_KERNEL = 1u << 3,    /* bracket the fused CG kernel with hipEvents on the caller's
                                     stream; read with otfs_plan_kernel_ms                    */
-  OTFS_AGENT_BARRIER = 1u << 4   /* fused kernel: one work queue and device-wide coherent
+  OTFS_AGENT_BARRIER = 1u << 4,  /* fused kernel: one work queue and device-wide coherent
                                     per-frame barriers, independent of workgroup placement
                                     (default: frames stay on one XCD, barriers coherent
                                     through that XCD's L2)                                   */
+  OTFS_NO_LDS_RESIDENT = 1u << 5 /* solve small one-tile frames with their vectors in memory
+                                    too (default: in LDS when 5*M*N*8 bytes fit 40 KiB)      */
 };
 
 /* CG options (Algorithm 1 with a per-frame stop test added in front of the direction
@@ -152,7 +154,7 @@ otfs_status otfs_plan_free(otfs_plan_t* plan);
 typedef struct {
   int32_t nframes;
   int64_t total_elems;
-  int32_t grid;             /* workgroups of the fused CG launch                            */
+  int32_t grid;             /* workgroups of the fused CG launches (summed over launches)   */
   int32_t block;            /* threads per workgroup                                        */
   int32_t max_paths;        /* largest P in the batch                                       */
   int32_t tile_elems;       /* target elements per workgroup tile                           */
@@ -161,6 +163,7 @@ typedef struct {
   int32_t lds_bytes;        /* dynamic LDS per workgroup of the fused launch (0: none)       */
   int32_t staged_frames;    /* frames whose gathers are staged through LDS windows          */
   int32_t resident_frames;  /* one-workgroup frames solved with all CG vectors in LDS       */
+  int32_t launches;         /* fused-kernel launches per solve: one per kind of frame        */
 } otfs_plan_info_t;
 otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
 
@@ -169,14 +172,14 @@ otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
  * the next otfs_plan_bind.  Used by the autotuner. */
 otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elems, int32_t max_grid);
 
-/* LDS budget per workgroup of the fused kernel (bytes, at most 65536, default 40 KiB;
- * takes effect at the next otfs_plan_bind).  A frame of one tile whose five CG vectors
- * (5 * M*N * 8 bytes) fit is solved with the vectors resident in LDS (not with the bf16
- * stored D or the refresh).  Other frames stage the gather windows of H and H^H
- * (Eqs. sparse_mvm, sparse_herm_mvm): a workgroup copies the source rows and columns its
- * block of outputs can reach into LDS, then does every path's gather from there; frames
- * whose smallest window exceeds the budget gather straight from memory.  0 turns both
- * off. */
+/* LDS budget per workgroup for staging the gather windows of H and H^H (Eqs. sparse_mvm,
+ * sparse_herm_mvm), in bytes, at most 65536; takes effect at the next otfs_plan_bind.  A
+ * staged frame's workgroup copies the source rows and columns a block of its outputs can
+ * reach (for c and the old p at once in the direction pass) straight from memory into
+ * LDS, then does every path's gather from there; frames whose smallest window pair
+ * exceeds the budget gather straight from memory.  Default 0 (off): on the measured
+ * workloads direct gathers were faster.  Small one-tile frames solved resident in LDS
+ * (see OTFS_NO_LDS_RESIDENT) do not depend on this budget. */
 otfs_status otfs_plan_set_staging(otfs_plan_t* plan, int32_t lds_bytes);
 
 /* ------------------------------------------------------------------------------------ */

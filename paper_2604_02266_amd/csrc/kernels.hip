@@ -114,34 +114,52 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int64_
 }
 
 // Source views of a band application: load(i) issues the reads of element i, value(raw)
-// forms the element from them.
+// forms the element from them.  A stageable view also names the kNV complex64 vectors it
+// reads (rsrc(j)) and forms the element from their values (combine); own(i, v) reads them
+// at element i.
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+}
 struct SrcBuf {   // complex64 vector
   __amdgpu_buffer_rsrc_t r;
+  static constexpr int kNV = 1;
+  static constexpr bool kStageable = true;
   using Raw = float2;
-  __device__ __forceinline__ Raw load(uint32_t i) const {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
-  }
+  __device__ __forceinline__ Raw load(uint32_t i) const { return buf_ld2(r, i); }
   __device__ __forceinline__ float2 value(Raw v) const { return v; }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int) const { return r; }
+  __device__ __forceinline__ float2 combine(const float2* v) const { return v[0]; }
+  __device__ __forceinline__ void own(uint32_t i, float2* v) const { v[0] = buf_ld2(r, i); }
 };
-struct SrcBf16 {  // complex stored as a bf16 pair per element
+struct SrcBf16 {  // complex stored as a bf16 pair per element (not staged)
   __amdgpu_buffer_rsrc_t r;
+  static constexpr int kNV = 1;
+  static constexpr bool kStageable = false;
   using Raw = uint32_t;
   __device__ __forceinline__ Raw load(uint32_t i) const {
     return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0);
   }
   __device__ __forceinline__ float2 value(Raw v) const { return bf16x2_to_f2(v); }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int) const { return r; }
+  __device__ __forceinline__ float2 combine(const float2* v) const { return v[0]; }
+  __device__ __forceinline__ void own(uint32_t i, float2* v) const { v[0] = value(load(i)); }
 };
 struct SrcDir {   // the new direction c + beta p, formed from c and the old p
   __amdgpu_buffer_rsrc_t c, p;
   float beta;
+  static constexpr int kNV = 2;
+  static constexpr bool kStageable = true;
   struct Raw {
     float2 c, p;
   };
-  __device__ __forceinline__ Raw load(uint32_t i) const {
-    return Raw{__builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(c, i * 8u, 0, 0)),
-               __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(p, i * 8u, 0, 0))};
-  }
+  __device__ __forceinline__ Raw load(uint32_t i) const { return Raw{buf_ld2(c, i), buf_ld2(p, i)}; }
   __device__ __forceinline__ float2 value(const Raw& v) const { return axpyf(beta, v.p, v.c); }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int j) const { return j == 0 ? c : p; }
+  __device__ __forceinline__ float2 combine(const float2* v) const { return axpyf(beta, v[1], v[0]); }
+  __device__ __forceinline__ void own(uint32_t i, float2* v) const {
+    v[0] = buf_ld2(c, i);
+    v[1] = buf_ld2(p, i);
+  }
 };
 struct SrcLds {   // complex64 vector in LDS
   LdsC v;
@@ -169,6 +187,65 @@ __device__ __forceinline__ SrcDir src_dir(const float2* c, const float2* p, floa
                                           int64_t n) {
   return SrcDir{buf_rsrc(c, n * 8), buf_rsrc(p, n * 8), beta};
 }
+
+// Output views of a band application (see apply_band).
+struct NoPre {};
+struct OutStore {   // out = v
+  CVec o;
+  static constexpr bool kOwn = false;
+  using Pre = NoPre;
+  __device__ __forceinline__ Pre pre(uint32_t) const { return Pre{}; }
+  __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre&, const float2*) const {
+    o.st(q, v);
+  }
+};
+struct OutInit {    // b = H^H y: c = p = b, x = 0, partial ||b||^2
+  CVec c, p, x;
+  float* acc;
+  static constexpr bool kOwn = false;
+  using Pre = NoPre;
+  __device__ __forceinline__ Pre pre(uint32_t) const { return Pre{}; }
+  __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre&, const float2*) const {
+    c.st(q, v);
+    p.st(q, v);
+    x.st(q, make_float2(0.f, 0.f));
+    *acc = fmaf(v.x, v.x, *acc);
+    *acc = fmaf(v.y, v.y, *acc);
+  }
+};
+struct OutA {       // t = H p', p_new = c + beta p_old, x += alpha p_old (deferred updates)
+  CVec t, pn, x;
+  float alpha, beta;
+  bool xp;
+  static constexpr bool kOwn = true;
+  struct Pre {
+    float2 x;
+  };
+  __device__ __forceinline__ Pre pre(uint32_t q) const {
+    return Pre{xp ? x.ld(q) : make_float2(0.f, 0.f)};
+  }
+  __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre& pr, const float2* own) const {
+    t.st(q, v);
+    pn.st(q, axpyf(beta, own[1], own[0]));
+    if (xp) x.st(q, axpyf(alpha, own[1], pr.x));
+  }
+};
+struct OutB {       // a = H^H t + lam p', partial Re(p'^H a)
+  CVec a, pn;
+  float lam;
+  float* acc;
+  static constexpr bool kOwn = false;
+  struct Pre {
+    float2 p;
+  };
+  __device__ __forceinline__ Pre pre(uint32_t q) const { return Pre{pn.ld(q)}; }
+  __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre& pr, const float2*) const {
+    const float2 av = axpyf(lam, pr.p, v);
+    a.st(q, av);
+    *acc = fmaf(pr.p.x, av.x, *acc);
+    *acc = fmaf(pr.p.y, av.y, *acc);
+  }
+};
 
 // ---------------------------------------------------------------------------------------
 // reductions: wave64 butterfly, then the waves of the block in a fixed order
@@ -324,6 +401,7 @@ __device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
 constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
 constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
 constexpr int kRows64 = 4;   // rows per thread chunk in the FP64 refresh gathers
+constexpr int kElemChunk = 8;   // elements per thread in flight in element-wise passes
 #ifndef OTFS_RES_ROWS
 #define OTFS_RES_ROWS 2
 #endif
@@ -333,9 +411,9 @@ constexpr int kRows64 = 4;   // rows per thread chunk in the FP64 refresh gather
 constexpr int kResRows = OTFS_RES_ROWS;    // rows per chunk of the LDS-resident gathers
 constexpr int kResPaths = OTFS_RES_PATHS;  // paths per step of the LDS-resident gathers
 
-template <int R, int U, bool ADJ, bool STORED, class Src, class Sink>
+template <int R, int U, bool ADJ, bool STORED, class Src, class Pref, class Sink>
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
-                                           Sink sink) {
+                                           Pref pref, Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
   const int TY = kBlock / TX;
@@ -353,11 +431,13 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, co
       int l[R];
       float2 wl[R];
       float2 acc[R];
+      decltype(pref(0u)) pf[R];   // the outputs' own loads, issued with the gathers
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         l[i] = lb + ty + min(r0 + i, nrows - 1) * TY;
         if (!STORED) wl[i] = wtab.f(l[i]);
         acc[i] = make_float2(0.f, 0.f);
+        pf[i] = pref((uint32_t)(l[i] * M + k));
       }
       // NP paths at once: all NP*R gathers are issued before any is consumed
       auto step = [&](auto npc, int p0) {
@@ -419,139 +499,182 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, co
       for (; p < P; ++p) step(std::integral_constant<int, 1>{}, p);
 #pragma unroll
       for (int i = 0; i < R; ++i)
-        if (r0 + i < nrows) sink(l[i] * M + k, acc[i]);
+        if (r0 + i < nrows) sink(l[i] * M + k, acc[i], pf[i]);
     }
   }
+}
+
+// band_apply with nothing to prefetch: sink(q, v)
+struct NoPref {
+  __device__ __forceinline__ NoPre operator()(uint32_t) const { return NoPre{}; }
+};
+template <int R, int U, bool ADJ, bool STORED, class Src, class Sink>
+__device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
+                                           Sink sink) {
+  band_apply<R, U, ADJ, STORED>(F, lb, le, src, NoPref{},
+                                [&](int q, float2 v, NoPre) { sink(q, v); });
 }
 
 // ---------------------------------------------------------------------------------------
 // LDS-staged band application (frames with F.skc > 0, coefficients synthesised).
 //
-// The band is processed in blocks of ssb rows x skc delay columns.  For one block the
-// workgroup first copies into LDS every source element its outputs can reach -- the rows
-// shifted by [nu_lo, nu_hi] and the columns shifted by [tau_lo, tau_hi] (whole rows when
-// skc = M, all N rows when the row window wraps the frame) -- with coalesced loads issued
-// in batches, then runs every path's gather from LDS.  The staged value of a source
-// element is formed once (phase A stages c + beta p).
+// The band is processed in blocks of ssb rows x skc delay columns (skc <= 256: one column
+// per thread, kStageRows rows per thread).  For a block the workgroup first copies into
+// LDS every source element its outputs can reach -- rows shifted by [nu_lo, nu_hi] and
+// columns shifted by [tau_lo, tau_hi], both ranges widened to contain 0 so that the
+// outputs' own elements are in the window too (whole rows when the column window would
+// cover them, all N rows when the row window wraps the frame).  The copy goes straight from
+// memory to LDS (buffer_load_dword ... lds): every load of the window is in flight at once
+// and none occupies a VGPR.  Each staged vector (Src::kNV of them: c and the old p in
+// phase A) has its own window; every path's gather then reads LDS.  Loads the outputs need
+// besides the window (Out::pre) are issued before the copy is waited for.
 // ---------------------------------------------------------------------------------------
-#ifndef OTFS_STAGE_BATCH
-#define OTFS_STAGE_BATCH 2
-#endif
-constexpr int kStageBatch = OTFS_STAGE_BATCH;   // staging loads in flight per thread
-
-template <bool ADJ, class Src, class Sink>
+template <bool ADJ, class Src, class Out>
 __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, float2* lds_gen,
-                                             const Src& src, Sink sink) {
+                                             const Src& src, const Out& out) {
+  constexpr int NV = Src::kNV;
   const int M = F.M, N = F.N, P = F.P;
   const int KC = F.skc, SB = F.ssb;
-  const int dtau = F.tau_hi - F.tau_lo, dnu = F.nu_hi - F.nu_lo;
-  const bool full_cols = KC >= M;
-  const int TXc = KC < kBlock ? KC : kBlock;
-  const int TYc = kBlock / TXc;
-  const int tx = threadIdx.x % TXc, ty = threadIdx.x / TXc;
+  const int tlo = F.tau_lo, thi = F.tau_hi, vlo = F.nu_lo, vhi = F.nu_hi;
+  const int dtau = thi - tlo, dnu = vhi - vlo;
+  const bool full_cols = KC + dtau >= M;
+  const int TYc = kBlock / KC;
+  const int tx = threadIdx.x % KC, ty = threadIdx.x / KC;
   const bool active = ty < TYc;
-  const LdsC lds = lds_c(lds_gen);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const KPairs paths = kpairs(F.paths);
   const KPairs wtab_s = kpairs(F.wtab);
   const GPairs rtab = gpairs(F.rtab);
   const GPairs wtab = gpairs(F.wtab);
+  LdsC win[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) win[j] = lds_c(lds_gen) + j * F.swin;
   for (int sb0 = lb; sb0 < le; sb0 += SB) {
     const int sbn = min(SB, le - sb0);
     const bool full_rows = sbn + dnu >= N;
     const int WR = full_rows ? N : sbn + dnu;
-    const int row0 = full_rows ? 0 : (ADJ ? sb0 + F.nu_lo : sb0 - F.nu_hi);
+    const int row0 = full_rows ? 0 : (ADJ ? sb0 + vlo : sb0 - vhi);
+    // the thread's output rows in this block (rows past the block repeat its last row)
+    int lrow[kStageRows];
+    float2 wl[kStageRows];
+#pragma unroll
+    for (int i = 0; i < kStageRows; ++i) {
+      lrow[i] = min(ty + i * TYc, sbn - 1);
+      wl[i] = wtab.f(sb0 + lrow[i]);
+    }
     for (int k0 = 0; k0 < M; k0 += KC) {
       const int kcn = min(KC, M - k0);
       const int WC = full_cols ? M : kcn + dtau;
-      const int col0 = full_cols ? 0 : (ADJ ? k0 + F.tau_lo : k0 - F.tau_hi);
-      const int nwin = WR * WC;
-      const float inv_wc = 1.0f / (float)WC;
+      const int col0 = full_cols ? 0 : (ADJ ? k0 + tlo : k0 - thi);
+      const int WS = (WC + 31) & ~31;        // LDS row stride: 32 elements per wave copy
+      const int k = k0 + min(tx, kcn - 1);
+      typename Out::Pre pre[kStageRows];
+#pragma unroll
+      for (int i = 0; i < kStageRows; ++i) pre[i] = out.pre((uint32_t)((sb0 + lrow[i]) * M + k));
       __syncthreads();                         // the previous block's readers are done
-      for (int e0 = 0; e0 < nwin; e0 += kBlock * kStageBatch) {
-        // window elements past the end re-read the last one and are not stored
-        typename Src::Raw v[kStageBatch];
+      // one wave copies 32 consecutive window elements of one row (two dwords per element)
+      const int half = lane & 1;
+      const int nch = WS >> 5;
+      for (int r = wave; r < WR; r += kWaves) {
+        int sr = row0 + r;
+        sr += sr < 0 ? N : 0;
+        sr -= sr >= N ? N : 0;
+        const int rowoff = sr * M;
+        for (int ch = 0; ch < nch; ++ch) {
+          const int c = ch * 32 + (lane >> 1);
+          if (c < WC) {
+            int sc = col0 + c;
+            sc += sc < 0 ? M : 0;
+            sc -= sc >= M ? M : 0;
+            const uint32_t voff = (uint32_t)(rowoff + sc) * 8u + (uint32_t)half * 4u;
 #pragma unroll
-        for (int j = 0; j < kStageBatch; ++j) {
-          const int e = min(e0 + j * kBlock + (int)threadIdx.x, nwin - 1);
-          int r = (int)((float)e * inv_wc);
-          int c = e - r * WC;
-          if (c < 0) { --r; c += WC; }
-          if (c >= WC) { ++r; c -= WC; }
-          int sr = row0 + r;
-          sr += sr < 0 ? N : 0;
-          sr -= sr >= N ? N : 0;
-          int sc = col0 + c;
-          sc += sc < 0 ? M : 0;
-          sc -= sc >= M ? M : 0;
-          v[j] = src.load((uint32_t)(sr * M + sc));
-        }
-#pragma unroll
-        for (int j = 0; j < kStageBatch; ++j) {
-          const int e = e0 + j * kBlock + (int)threadIdx.x;
-          if (e < nwin) lds.st(e, src.value(v[j]));
+            for (int j = 0; j < NV; ++j)
+              __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                  src.rsrc(j), (lptr<void>)(win[j].p + r * WS + ch * 32), 4, voff, 0, 0, 0);
+          }
         }
       }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      if (!active) continue;
-      // the wrap factor W[l]^n of each row (see band_apply), read once per block row
-      float2 wl[kStageRows];
+      if (!active || tx >= kcn) continue;
+      const int cc = tx;
+      float2 acc[kStageRows];
 #pragma unroll
-      for (int i = 0; i < kStageRows; ++i) wl[i] = wtab.f(sb0 + min(ty + i * TYc, sbn - 1));
-      for (int cc = tx; cc < kcn; cc += TXc) {
-        const int k = k0 + cc;
-        float2 acc[kStageRows];
-#pragma unroll
-        for (int i = 0; i < kStageRows; ++i) acc[i] = make_float2(0.f, 0.f);
-        for (int p = 0; p < P; ++p) {
-          const int2 tn = paths.i2(p);
-          const int K = ADJ ? k + tn.x : k - tn.x;
-          const int n = K < 0 ? -1 : (K >= M ? 1 : 0);
-          const int kk = K - n * M;
-          const float2 r = rtab.f(p * M + (ADJ ? kk : k));
-          const float2 cf = ADJ ? make_float2(r.x, -r.y) : r;
-          float2 cw = cf;
-          if (!ADJ) {
-            const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
-            cw = cmulf(cf, make_float2(wn.x, n > 0 ? -wn.y : wn.y));
-          }
-          const int lc = full_cols ? kk : (ADJ ? cc + (tn.x - F.tau_lo) : cc + (F.tau_hi - tn.x));
-#pragma unroll
-          for (int i = 0; i < kStageRows; ++i) {
-            const int rr = min(ty + i * TYc, sbn - 1);
-            const int l = sb0 + rr;
-            int lr;
-            if (full_rows) {
-              lr = ADJ ? l + tn.y : l - tn.y;
-              lr += lr < 0 ? N : 0;
-              lr -= lr >= N ? N : 0;
-            } else {
-              lr = ADJ ? rr + (tn.y - F.nu_lo) : rr + (F.nu_hi - tn.y);
-            }
-            const float2 val = lds.ld(lr * WC + lc);
-            const float2 w = make_float2(wl[i].x, n > 0 ? wl[i].y : -wl[i].y);
-            const float2 cr = cmulf(cw, w);
-            cmacf(acc[i], n != 0 ? cr : cf, val);
-          }
+      for (int i = 0; i < kStageRows; ++i) acc[i] = make_float2(0.f, 0.f);
+      for (int p = 0; p < P; ++p) {
+        const int2 tn = paths.i2(p);
+        const int K = ADJ ? k + tn.x : k - tn.x;
+        const int n = K < 0 ? -1 : (K >= M ? 1 : 0);
+        const int kk = K - n * M;
+        const float2 rv = rtab.f(p * M + (ADJ ? kk : k));
+        const float2 cf = ADJ ? make_float2(rv.x, -rv.y) : rv;
+        float2 cw = cf;
+        if (!ADJ) {
+          const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
+          cw = cmulf(cf, make_float2(wn.x, n > 0 ? -wn.y : wn.y));
         }
+        const int lc = full_cols ? kk : (ADJ ? cc + (tn.x - tlo) : cc + (thi - tn.x));
 #pragma unroll
         for (int i = 0; i < kStageRows; ++i) {
-          const int rr = ty + i * TYc;
-          if (rr < sbn) sink((sb0 + rr) * M + k, acc[i]);
+          const int rr = lrow[i];
+          int lr;
+          if (full_rows) {
+            lr = ADJ ? sb0 + rr + tn.y : sb0 + rr - tn.y;
+            lr += lr < 0 ? N : 0;
+            lr -= lr >= N ? N : 0;
+          } else {
+            lr = ADJ ? rr + (tn.y - vlo) : rr + (vhi - tn.y);
+          }
+          const int at = lr * WS + lc;
+          float2 v[NV];
+#pragma unroll
+          for (int j = 0; j < NV; ++j) v[j] = win[j].ld(at);
+          const float2 w = make_float2(wl[i].x, n > 0 ? wl[i].y : -wl[i].y);
+          const float2 cr = cmulf(cw, w);
+          cmacf(acc[i], n != 0 ? cr : cf, src.combine(v));
+        }
+      }
+      // own elements (shift 0) are in the window
+      const int oc = full_cols ? k : cc + (ADJ ? -tlo : thi);
+#pragma unroll
+      for (int i = 0; i < kStageRows; ++i) {
+        const int rr = ty + i * TYc;
+        if (rr < sbn) {
+          const int orow = full_rows ? sb0 + rr : rr + (ADJ ? -vlo : vhi);
+          float2 own[NV];
+#pragma unroll
+          for (int j = 0; j < NV; ++j) own[j] = win[j].ld(orow * WS + oc);
+          out.put((uint32_t)((sb0 + rr) * M + k), acc[i], pre[i], own);
         }
       }
     }
   }
 }
 
-// Band application of H / H^H: staged through LDS when the frame's geometry allows it,
-// gathered straight from memory otherwise.
-template <bool ADJ, bool STORED, class Src, class Sink>
+// Band application of H / H^H: staged through LDS (STAGED: frames with a window
+// geometry), gathered straight from memory otherwise.  out.pre(q) issues the loads output q needs
+// besides the source; out.put(q, v, pre, own) receives it with own[] = the source
+// vectors' elements at q.
+template <bool ADJ, bool STORED, bool STAGED, class Src, class Out>
 __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, float2* lds,
-                                           const Src& src, Sink sink) {
-  if (!STORED && F.skc > 0 && lds != nullptr)
-    staged_apply<ADJ>(F, lb, le, lds, src, sink);
-  else
-    band_apply<kRows, kPaths, ADJ, STORED>(F, lb, le, src, sink);
+                                           const Src& src, const Out& out) {
+  if constexpr (STAGED && !STORED && Src::kStageable) {
+    staged_apply<ADJ>(F, lb, le, lds, src, out);
+  } else {
+    struct PreOwn {
+      typename Out::Pre pre;
+      float2 own[Src::kNV];
+    };
+    band_apply<kRows, kPaths, ADJ, STORED>(
+        F, lb, le, src,
+        [&](uint32_t u) {
+          PreOwn po;
+          po.pre = out.pre(u);
+          if (Out::kOwn) src.own(u, po.own);
+          return po;
+        },
+        [&](int q, float2 v, const PreOwn& po) { out.put((uint32_t)q, v, po.pre, po.own); });
+  }
 }
 
 // FP64 version (coefficients from the FP64 tables) for the true-residual refresh.
@@ -689,7 +812,7 @@ struct LaunchCtx {
   int xcd_local;     // barrier coherence mode (see frame_barrier)
 };
 
-template <bool STORED, bool REFRESH>
+template <bool STORED, bool REFRESH, bool STAGED>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                         const LaunchCtx& L, float* red, double* redd, int* sflag, float2* lds) {
   const FrameVecs V = frame_vecs(F, B);
@@ -726,18 +849,11 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
   // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line) ----
   if (!s.init) {
     float acc = 0.f;
-    const CVec p0 = cvec(F.p0, E);
-    auto sink = [&](int q, float2 v) {
-      cv.st((uint32_t)q, v);
-      p0.st((uint32_t)q, v);
-      xv.st((uint32_t)q, make_float2(0.f, 0.f));
-      acc = fmaf(v.x, v.x, acc);
-      acc = fmaf(v.y, v.y, acc);
-    };
+    const OutInit out{cv, cvec(F.p0, E), xv, &acc};
     if (V.ybf16)
-      apply_band<true, STORED>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, sink);
+      apply_band<true, STORED, STAGED>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, out);
     else
-      apply_band<true, STORED>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, sink);
+      apply_band<true, STORED, STAGED>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, out);
     const float bs = block_sum(acc, red);
     if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
     if (!bar()) return fail_timeout();
@@ -767,29 +883,14 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
 
     // ---- A: deferred updates of the band, t = H p ----
-    apply_band<false, STORED>(
-        F, lb, le, lds, SrcDir{cv.r, pov.r, be},
-        [&](int q, float2 v) {
-          const uint32_t u = (uint32_t)q;
-          tv.st(u, v);
-          const float2 po = pov.ld(u);
-          pnv.st(u, axpyf(be, po, cv.ld(u)));
-          if (xp) xv.st(u, axpyf(al, po, xv.ld(u)));
-        });
+    apply_band<false, STORED, STAGED>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
+                              OutA{tv, pnv, xv, al, be, xp});
     if (!bar()) return fail_timeout();
 
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
       float acc = 0.f;
-      apply_band<true, STORED>(
-          F, lb, le, lds, SrcBuf{tv.r},
-          [&](int q, float2 v) {
-            const float2 p = pnv.ld((uint32_t)q);
-            const float2 a = axpyf(lam, p, v);
-            av.st((uint32_t)q, a);
-            acc = fmaf(p.x, a.x, acc);
-            acc = fmaf(p.y, a.y, acc);
-          });
+      apply_band<true, STORED, STAGED>(F, lb, le, lds, SrcBuf{tv.r}, OutB{av, pnv, lam, &acc});
       const float bs = block_sum(acc, red);
       if (threadIdx.x == 0) F.part_pa[wi.tile] = bs;
     }
@@ -808,12 +909,26 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     // ---- C: c -= alpha a, partial ||c||^2 ----
     {
       float acc = 0.f;
-#pragma unroll 4
-      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock) {
-        const float2 c = axpyf(-alpha, av.ld(u), cv.ld(u));
-        cv.st(u, c);
-        acc = fmaf(c.x, c.x, acc);
-        acc = fmaf(c.y, c.y, acc);
+      // kElemChunk elements per thread at a time, all loads issued first (past the band's
+      // end the last element is re-read and nothing is stored)
+      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * kElemChunk) {
+        float2 a[kElemChunk], c[kElemChunk];
+#pragma unroll
+        for (int j = 0; j < kElemChunk; ++j) {
+          const uint32_t w = min(u + (uint32_t)(j * kBlock), u1 - 1u);
+          a[j] = av.ld(w);
+          c[j] = cv.ld(w);
+        }
+#pragma unroll
+        for (int j = 0; j < kElemChunk; ++j) {
+          const uint32_t w = u + (uint32_t)(j * kBlock);
+          if (w < u1) {
+            const float2 cn = axpyf(-alpha, a[j], c[j]);
+            cv.st(w, cn);
+            acc = fmaf(cn.x, cn.x, acc);
+            acc = fmaf(cn.y, cn.y, acc);
+          }
+        }
       }
       const float bs = block_sum(acc, red);
       if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
@@ -1024,7 +1139,7 @@ __device__ __forceinline__ int xcc_id() {
 // workgroups sharing one L2.  A frame's tiles are consecutive in its group's queue and a
 // group never has fewer resident workgroups than a frame has tiles, so the first frame
 // with an untaken tile is always being completed: the per-frame barriers cannot deadlock.
-template <bool STORED, bool REFRESH>
+template <bool STORED, bool REFRESH, int KIND>
 __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict__ frames,
                                                      const WorkItem* __restrict__ items,
                                                      const int32_t* __restrict__ qitems,
@@ -1058,10 +1173,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict_
     if (it < 0) break;
     const WorkItem wi = items[it];
     const FrameDev& F = frames[wi.frame];
-    if (!STORED && !REFRESH && F.resident)
+    if constexpr (KIND == kKindResident)
       cg_item_resident(F, budget, B, red, stage_lds);
     else
-      cg_item<STORED, REFRESH>(F, wi, budget, B, L, red, redd, &sflag, stage_lds);
+      cg_item<STORED, REFRESH, KIND == kKindStaged>(F, wi, budget, B, L, red, redd, &sflag,
+                                                    stage_lds);
     __syncthreads();
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1084,8 +1200,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ f
   extern __shared__ float2 stage_lds[];
   const int64_t E = (int64_t)F.M * F.N;
   const CVec dst = cvec(out + F.off, E);
-  apply_band<ADJ, STORED>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
-                          [&](int q, float2 v) { dst.st((uint32_t)q, v); });
+  if (!STORED && F.skc > 0)
+    apply_band<ADJ, STORED, true>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
+                                  OutStore{dst});
+  else
+    apply_band<ADJ, STORED, false>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
+                                   OutStore{dst});
 }
 
 __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsigned* abort_flag,
@@ -1360,38 +1480,54 @@ static uint64_t wallclock_timeout_ticks() {
   return ticks;
 }
 
-template <bool STORED, bool REFRESH>
+template <bool STORED, bool REFRESH, int KIND>
 static void launch_fused_t(const FrameDev* frames, const WorkItem* items, const int32_t* qitems,
                            const int2* qrange, unsigned* qhead, int ngroups, int grid, int budget,
                            const Bases& bases, const LaunchCtx& L, int lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_fused<STORED, REFRESH>), dim3(grid), dim3(kBlock), lds_bytes, s,
+  hipLaunchKernelGGL((k_cg_fused<STORED, REFRESH, KIND>), dim3(grid), dim3(kBlock), lds_bytes, s,
                      frames, items, qitems, qrange, qhead, ngroups, budget, bases, L);
 }
 
-hipError_t launch_cg_fused(bool stored, bool refresh, const FrameDev* frames,
+// the instantiation of a launch kind: resident and staged frames use neither the stored
+// D nor (resident) the refresh, which the host guarantees
+static const void* fused_fn(int kind, bool stored, bool refresh) {
+  if (kind == kKindResident) return reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindResident>);
+  if (kind == kKindStaged)
+    return refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true, kKindStaged>)
+                   : reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindStaged>);
+  if (stored)
+    return refresh ? reinterpret_cast<const void*>(&k_cg_fused<true, true, kKindDirect>)
+                   : reinterpret_cast<const void*>(&k_cg_fused<true, false, kKindDirect>);
+  return refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true, kKindDirect>)
+                 : reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindDirect>);
+}
+
+hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
                            bool xcd_local, unsigned* abort_flag, int lds_bytes, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   LaunchCtx L{abort_flag, wallclock_timeout_ticks(), xcd_local ? 1 : 0};
-  if (stored) lds_bytes = 0;
-  if (stored) {
-    if (refresh) launch_fused_t<true, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-    else launch_fused_t<true, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+  if (kind == kKindResident) {
+    launch_fused_t<false, false, kKindResident>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+  } else if (kind == kKindStaged) {
+    if (refresh) launch_fused_t<false, true, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+    else launch_fused_t<false, false, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+  } else if (stored) {
+    if (refresh) launch_fused_t<true, true, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+    else launch_fused_t<true, false, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
   } else {
-    if (refresh) launch_fused_t<false, true>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-    else launch_fused_t<false, false>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+    if (refresh) launch_fused_t<false, true, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+    else launch_fused_t<false, false, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
   }
   return hipGetLastError();
 }
 
-int fused_blocks_per_cu(bool stored, bool refresh, int lds_bytes) {
+int fused_blocks_per_cu(int kind, bool stored, bool refresh, int lds_bytes) {
   int n = 0;
-  const void* fn = stored ? (refresh ? reinterpret_cast<const void*>(&k_cg_fused<true, true>)
-                                     : reinterpret_cast<const void*>(&k_cg_fused<true, false>))
-                          : (refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true>)
-                                     : reinterpret_cast<const void*>(&k_cg_fused<false, false>));
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, stored ? 0 : lds_bytes) != hipSuccess)
+  if (kind == kKindDirect) lds_bytes = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_fn(kind, stored, refresh), kBlock,
+                                                   lds_bytes) != hipSuccess)
     n = 0;
   return n;
 }

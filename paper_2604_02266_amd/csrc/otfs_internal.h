@@ -65,7 +65,7 @@ struct FrameDev {
   int32_t index;          // frame index in its batch (stats slot)
   // LDS staging of the gathers (0 = gather straight from memory): column chunk and row
   // sub-band of one staged block, and the delay / Doppler shift ranges of the paths
-  int32_t skc, ssb;
+  int32_t skc, ssb, swin;   // swin: LDS elements per staged vector (window, padded)
   int32_t tau_lo, tau_hi, nu_lo, nu_hi;
   // 1: a one-workgroup frame whose five CG vectors (x, c, p, t, a) live in LDS for the
   // whole solve (y read once, x written once)
@@ -92,10 +92,12 @@ struct Bases {
 // ---- launchers (kernels.hip) -----------------------------------------------------------
 constexpr int kMaxGroups = 16;   // work-queue groups (one per XCD in XCD-local mode)
 #ifndef OTFS_STAGE_ROWS
-#define OTFS_STAGE_ROWS 4
+#define OTFS_STAGE_ROWS 2
 #endif
 constexpr int kStageRows = OTFS_STAGE_ROWS;   // output rows per thread in one staged block
-constexpr int kDefaultStageBytes = 40 * 1024;   // LDS per workgroup for staged windows
+constexpr int kDefaultStageBytes = 0;           // LDS per workgroup for staged windows (off)
+constexpr int kResidentBytes = 40 * 1024;       // LDS of a frame solved resident in LDS
+constexpr int kStageVecs = 2;    // vectors staged at once (phase A stages c and the old p)
 
 // One workgroup per item.  in/out are batch-wide complex64 buffers (frame at base + off).
 // lds_bytes: dynamic LDS for staged windows (0 if no frame is staged).
@@ -118,13 +120,17 @@ hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abor
 // XCD-local coherence; otherwise there is one group and agent-scope barriers.
 // abort_flag: zero before the launch; raised by a workgroup whose barrier wait timed out
 // so that every other wait ends at once.  budget = iterations per frame in this launch.
-hipError_t launch_cg_fused(bool stored, bool refresh, const FrameDev* frames,
+// Launch kinds of the fused kernel, each its own instantiation: frames gathering straight
+// from memory, frames staging gather windows in LDS, one-workgroup frames with the whole
+// solve in LDS.
+constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKinds = 3;
+hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
                            bool xcd_local, unsigned* abort_flag, int lds_bytes, hipStream_t s);
-// Workgroups of the fused kernel that fit on one CU at once (occupancy) with lds_bytes of
-// dynamic LDS.
-int fused_blocks_per_cu(bool stored, bool refresh, int lds_bytes);
+// Workgroups of the fused kernel of a launch kind that fit on one CU at once (occupancy)
+// with lds_bytes of dynamic LDS.
+int fused_blocks_per_cu(int kind, bool stored, bool refresh, int lds_bytes);
 
 // out[b] = XCC id of workgroup b, for b < nblocks.
 hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);

@@ -50,7 +50,7 @@ otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out) {
     return fail(OTFS_E_INVAL, "rel_tol must be finite and >= 0");
   if (d.refresh_every < 0) return fail(OTFS_E_INVAL, "refresh_every must be >= 0");
   const uint32_t known = OTFS_D_STORED_BF16 | OTFS_Y_BF16 | OTFS_USE_GRAPH | OTFS_TIME_KERNEL |
-                         OTFS_AGENT_BARRIER;
+                         OTFS_AGENT_BARRIER | OTFS_NO_LDS_RESIDENT;
   if (d.flags & ~known) return fail(OTFS_E_INVAL, "unknown flag bits 0x%x", d.flags & ~known);
   *out = d;
   return OTFS_OK;
@@ -127,6 +127,7 @@ void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const 
   d->refresh_every = o.refresh_every;
   d->skc = geo.skc;
   d->ssb = geo.ssb;
+  d->swin = geo.swin;
   d->tau_lo = geo.tau_lo;
   d->tau_hi = geo.tau_hi;
   d->nu_lo = geo.nu_lo;
@@ -139,14 +140,80 @@ int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opt
   std::memset(geo, 0, sizeof(FrameDev));
   const int64_t E = (int64_t)f.M * f.N;
   const bool stored = (o.flags & OTFS_D_STORED_BF16) != 0;
-  if (tiles == 1 && !stored && o.refresh_every == 0 &&
-      E * kResidentVecs * (int64_t)sizeof(float2) <= budget_bytes) {
+  if (tiles == 1 && !stored && o.refresh_every == 0 && !(o.flags & OTFS_NO_LDS_RESIDENT) &&
+      E * kResidentVecs * (int64_t)sizeof(float2) <= kResidentBytes) {
     stage_geometry(f, band_rows, 0, geo);   // shift ranges only; no staging
     geo->resident = 1;
     return (int)(E * kResidentVecs * (int64_t)sizeof(float2));
   }
+  if (stored) {
+    stage_geometry(f, band_rows, 0, geo);
+    return 0;
+  }
   return stage_geometry(f, band_rows, budget_bytes / (int)sizeof(float2), geo) *
          (int)sizeof(float2);
+}
+
+int frame_kind(const FrameDev& geo) {
+  return geo.resident ? kKindResident : (geo.skc > 0 ? kKindStaged : kKindDirect);
+}
+
+int frame_lds_bytes(const HostFrame& f, const FrameDev& geo) {
+  if (geo.resident) return (int)((int64_t)f.M * f.N * kResidentVecs * (int64_t)sizeof(float2));
+  if (geo.skc > 0) return kStageVecs * geo.swin * (int)sizeof(float2);
+  return 0;
+}
+
+otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vector<FrameDev>& geo,
+                          const std::vector<int>& tile_base, const std::vector<int>& tiles,
+                          bool stored, bool refresh, int cus, int cap_override,
+                          const XcdInfo& xi, bool agent, std::vector<int32_t>& qitems,
+                          std::vector<int2>& qrange, std::vector<KindLaunch>& out) {
+  qitems.clear();
+  qrange.assign((size_t)kKinds * kMaxGroups, make_int2(0, 0));
+  out.clear();
+  for (int kind = 0; kind < kKinds; ++kind) {
+    std::vector<HostFrame> fs;
+    std::vector<int> tb, tl;
+    int lds = 0;
+    for (size_t f = 0; f < frames.size(); ++f) {
+      if (frame_kind(geo[f]) != kind) continue;
+      fs.push_back(frames[f]);
+      tb.push_back(tile_base[f]);
+      tl.push_back(tiles[f]);
+      lds = std::max(lds, frame_lds_bytes(frames[f], geo[f]));
+    }
+    if (fs.empty()) continue;
+    const int bpc = std::max(1, fused_blocks_per_cu(kind, stored, refresh, lds));
+    int cap = bpc * cus;
+    if (cap_override > 0) cap = std::min(cap, cap_override);
+    KindLaunch L;
+    L.kind = kind;
+    L.lds_bytes = lds;
+    L.qbase = kind * kMaxGroups;
+    std::vector<int32_t> qi;
+    std::vector<int2> qr;
+    int per = 0;
+    if (!agent && xi.round_robin && cap >= xi.nxcd &&
+        make_queues(fs, tb, tl, xi.nxcd, cap / xi.nxcd, qi, qr, &per)) {
+      L.xcd_local = true;
+      L.ngroups = xi.nxcd;
+      L.grid = per * xi.nxcd;
+    } else if (make_queues(fs, tb, tl, 1, cap, qi, qr, &per)) {
+      L.grid = per;
+    } else {
+      int maxT = 1;
+      for (int t : tl) maxT = std::max(maxT, t);
+      return fail(OTFS_E_UNSUPPORTED, "a frame needs %d cooperating workgroups but only %d fit",
+                  maxT, cap);
+    }
+    const int base = (int)qitems.size();
+    qitems.insert(qitems.end(), qi.begin(), qi.end());
+    for (int g = 0; g < L.ngroups; ++g)
+      qrange[(size_t)L.qbase + g] = make_int2(qr[g].x + base, qr[g].y + base);
+    out.push_back(L);
+  }
+  return OTFS_OK;
 }
 
 // W[l] = e^{j 2 pi l / N}
@@ -229,8 +296,9 @@ bool make_queues(const std::vector<HostFrame>& frames, const std::vector<int>& t
 }
 
 int stage_geometry(const HostFrame& f, int band_rows, int budget_elems, FrameDev* d) {
-  int tlo = f.tau[0], thi = f.tau[0], vlo = f.nu[0], vhi = f.nu[0];
-  for (int p = 1; p < f.P; ++p) {
+  // shift ranges, widened to contain 0 so that every output's own element is staged too
+  int tlo = 0, thi = 0, vlo = 0, vhi = 0;
+  for (int p = 0; p < f.P; ++p) {
     tlo = std::min(tlo, f.tau[p]);
     thi = std::max(thi, f.tau[p]);
     vlo = std::min(vlo, f.nu[p]);
@@ -242,36 +310,34 @@ int stage_geometry(const HostFrame& f, int band_rows, int budget_elems, FrameDev
   d->nu_hi = vhi;
   d->skc = 0;
   d->ssb = 0;
+  d->swin = 0;
   if (budget_elems <= 0) return 0;
   const int dtau = thi - tlo, dnu = vhi - vlo;
-  // column chunks: whole rows, or 64-multiples with a delay halo
-  int cands[8], nc = 0;
-  cands[nc++] = f.M;
-  for (int kc : {512, 256, 128, 64})
+  // column chunks of at most one workgroup width (one column per thread)
+  int cands[6], nc = 0;
+  if (f.M <= kBlock) cands[nc++] = f.M;
+  for (int kc : {256, 128, 64, 32})
     if (kc < f.M) cands[nc++] = kc;
   double best = 1e300;
   int best_win = 0;
   for (int i = 0; i < nc; ++i) {
-    int kc = cands[i];
-    int wc = kc + dtau;
-    if (kc == f.M || wc >= f.M) {   // the window spans whole rows: no halo, modular columns
-      kc = f.M;
-      wc = f.M;
-    }
-    const int tyc = kBlock / std::min(kc, kBlock);
+    const int kc = cands[i];
+    const int tyc = kBlock / kc;
     const int sb = std::max(1, std::min(kStageRows * tyc, band_rows));
+    const int wc = kc + dtau >= f.M ? f.M : kc + dtau;
     const int wr = sb + dnu >= f.N ? f.N : sb + dnu;
-    const long long win = (long long)wr * wc;
-    if (win > budget_elems) continue;
-    const double cost = (double)win / ((double)sb * kc);
+    const long long win = (long long)wr * ((wc + 31) / 32 * 32);   // rows padded to 32
+    if (kStageVecs * win > budget_elems) continue;
+    const double cost = (double)kStageVecs * win / ((double)sb * kc);
     if (cost < best - 1e-9) {
       best = cost;
       best_win = (int)win;
       d->skc = kc;
       d->ssb = sb;
+      d->swin = (int)win;
     }
   }
-  return d->skc > 0 ? best_win : 0;
+  return d->skc > 0 ? kStageVecs * best_win : 0;
 }
 
 otfs_status probe_xcds(int device, void* scratch_dev, hipStream_t s, XcdInfo* out) {
@@ -337,8 +403,8 @@ void compute_layout(otfs_plan_t* pl) {
   L.frames = take(nf * sizeof(FrameDev));
   L.items = take(nitems * sizeof(WorkItem));
   L.qitems = take(nitems * sizeof(int32_t));
-  L.qrange = take(kMaxGroups * sizeof(int2));
-  L.qhead = take(kMaxGroups * sizeof(unsigned));
+  L.qrange = take(kKinds * kMaxGroups * sizeof(int2));
+  L.qhead = take(kKinds * kMaxGroups * sizeof(unsigned));
   L.probe = take(kProbeBlocks * sizeof(int));
   L.rtab = take(rt * sizeof(float2));
   L.wtab = take(wt * sizeof(float2));
@@ -426,13 +492,20 @@ extern "C" otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t*
   if (!plan || !info) return fail(OTFS_E_INVAL, "plan and info must be non-null");
   info->nframes = (int32_t)plan->frames.size();
   info->total_elems = plan->total_elems;
-  info->grid = plan->grid;
+  info->grid = 0;
   info->block = kBlock;
   info->max_paths = plan->max_paths;
   info->tile_elems = plan->tile_elems;
-  info->groups = plan->ngroups;
-  info->xcd_local = plan->xcd_local ? 1 : 0;
-  info->lds_bytes = plan->lds_bytes;
+  info->groups = 0;
+  info->xcd_local = plan->launches.empty() ? 0 : 1;
+  info->lds_bytes = 0;
+  for (const KindLaunch& L : plan->launches) {
+    info->grid += L.grid;
+    info->groups = std::max(info->groups, L.ngroups);
+    info->xcd_local = info->xcd_local && L.xcd_local ? 1 : 0;
+    info->lds_bytes = std::max(info->lds_bytes, L.lds_bytes);
+  }
+  info->launches = (int32_t)plan->launches.size();
   info->staged_frames = 0;
   info->resident_frames = 0;
   for (const FrameDev& d : plan->h_frames) {
@@ -480,57 +553,31 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   plan->device = dev;
   plan->drop_graph();
 
-  // LDS use per frame: resident vectors or staged-gather windows (decides the dynamic LDS
-  // of the launches)
+  // LDS use per frame: resident vectors or staged-gather windows (decides the launch kind
+  // of every frame and the dynamic LDS of each launch)
   std::vector<FrameDev> geo(plan->frames.size());
-  int max_lds = 0;
   for (size_t f = 0; f < plan->frames.size(); ++f) {
     int band = 1;
     for (int t = 0; t < plan->tiles[f]; ++t) {
       const WorkItem& w = plan->items[plan->tile_base[f] + t];
       band = std::max(band, w.l_end - w.l_begin);
     }
-    max_lds = std::max(max_lds, lds_geometry(plan->frames[f], plan->tiles[f], band, plan->opts,
-                                             plan->stage_bytes, &geo[f]));
+    lds_geometry(plan->frames[f], plan->tiles[f], band, plan->opts, plan->stage_bytes, &geo[f]);
   }
-  plan->lds_bytes = max_lds;
 
   // work queues of the fused kernel (need the occupancy and XCD layout of this device)
-  const bool stored_mode = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
-  const int bpc = std::max(1, fused_blocks_per_cu(stored_mode, plan->opts.refresh_every > 0,
-                                                  plan->lds_bytes));
   int cus = plan->cus;
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
     cus = v;
-  int cap = bpc * cus;
-  if (plan->max_grid_req > 0) cap = std::min(cap, plan->max_grid_req);
   XcdInfo xi;
   otfs_status pst = probe_xcds(dev, static_cast<char*>(ws) + plan->L.probe, s, &xi);
   if (pst != OTFS_OK) return pst;
-  plan->xcd_local = false;
-  plan->ngroups = 1;
-  int per = 0;
-  if (!(plan->opts.flags & OTFS_AGENT_BARRIER) && xi.round_robin && cap >= xi.nxcd) {
-    const int per_cap = cap / xi.nxcd;
-    if (make_queues(plan->frames, plan->tile_base, plan->tiles, xi.nxcd, per_cap, plan->qitems,
-                    plan->qrange, &per)) {
-      plan->xcd_local = true;
-      plan->ngroups = xi.nxcd;
-      plan->grid = per * xi.nxcd;
-    }
-  }
-  if (!plan->xcd_local) {
-    if (!make_queues(plan->frames, plan->tile_base, plan->tiles, 1, cap, plan->qitems,
-                     plan->qrange, &per)) {
-      int maxT = 1;
-      for (int t : plan->tiles) maxT = std::max(maxT, t);
-      return fail(OTFS_E_UNSUPPORTED, "a frame needs %d cooperating workgroups but only %d fit",
-                  maxT, cap);
-    }
-    plan->grid = per;
-  }
-  if (plan->items.empty()) plan->grid = 0;
+  pst = plan_launches(plan->frames, geo, plan->tile_base, plan->tiles,
+                      (plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->opts.refresh_every > 0,
+                      cus, plan->max_grid_req, xi, (plan->opts.flags & OTFS_AGENT_BARRIER) != 0,
+                      plan->qitems, plan->qrange, plan->launches);
+  if (pst != OTFS_OK) return pst;
 
   // host tables
   const Layout& L = plan->L;
@@ -645,9 +692,12 @@ static otfs_status apply_common(const otfs_plan_t* plan, bool adj, const void* i
   if (!in || !out) return fail(OTFS_E_INVAL, "input and output must be non-null");
   if (in == out) return fail(OTFS_E_INVAL, "input and output must be distinct buffers");
   const bool stored = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
+  int lds = 0;   // staged frames stage their windows here too
+  for (const KindLaunch& L : plan->launches)
+    if (L.kind == kKindStaged) lds = L.lds_bytes;
   hipError_t e = launch_apply(adj, stored, plan->d_frames, plan->d_items, (int)plan->items.size(),
-                              static_cast<const float2*>(in), static_cast<float2*>(out),
-                              plan->lds_bytes, static_cast<hipStream_t>(stream));
+                              static_cast<const float2*>(in), static_cast<float2*>(out), lds,
+                              static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, adj ? "apply H^H" : "apply H");
   return OTFS_OK;
 }
@@ -662,14 +712,17 @@ extern "C" otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y, voi
 // the launch sequence of one fused solve: reset, persistent kernel (optionally timed)
 static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s, bool timed) {
   hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort,
-                              plan->d_qhead, plan->ngroups, s);
+                              plan->d_qhead, kKinds * kMaxGroups, s);
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_begin, s)) != hipSuccess) return e;
-  e = launch_cg_fused((plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->opts.refresh_every > 0,
-                      plan->d_frames, plan->d_items,
-                      plan->d_qitems, plan->d_qrange, plan->d_qhead, plan->ngroups, plan->grid,
-                      plan->opts.max_iters, B, plan->xcd_local, plan->d_abort, plan->lds_bytes, s);
-  if (e != hipSuccess) return e;
+  for (const KindLaunch& L : plan->launches) {
+    e = launch_cg_fused(L.kind, (plan->opts.flags & OTFS_D_STORED_BF16) != 0,
+                        plan->opts.refresh_every > 0, plan->d_frames, plan->d_items,
+                        plan->d_qitems, plan->d_qrange + L.qbase, plan->d_qhead + L.qbase,
+                        L.ngroups, L.grid, plan->opts.max_iters, B, L.xcd_local, plan->d_abort,
+                        L.lds_bytes, s);
+    if (e != hipSuccess) return e;
+  }
   if (timed && (e = hipEventRecord(plan->ev_end, s)) != hipSuccess) return e;
   return hipSuccess;
 }
@@ -733,7 +786,7 @@ extern "C" otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y, voi
   if (plan->opts.flags & OTFS_D_STORED_BF16)
     return fail(OTFS_E_UNSUPPORTED, "the plain form synthesises D on the fly only");
   hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort,
-                              plan->d_qhead, plan->ngroups, s);
+                              plan->d_qhead, kKinds * kMaxGroups, s);
   if (e != hipSuccess) return hip_fail(e, "reset");
   for (size_t f = 0; f < plan->frames.size(); ++f) {
     e = launch_plain_frame(plan->d_frames, (int)f, plan->d_items, plan->tile_base[f],

@@ -77,6 +77,29 @@ int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opt
                  int budget_bytes, FrameDev* geo);
 constexpr int kProbeBlocks = 1024;
 
+// One launch of the fused kernel: the frames of one kind with their work queues.  The
+// queue ranges and cursors of launch kind k live at k * kMaxGroups.
+struct KindLaunch {
+  int kind = kKindDirect;
+  int grid = 0;
+  int ngroups = 1;
+  bool xcd_local = false;
+  int lds_bytes = 0;
+  int qbase = 0;
+};
+int frame_kind(const FrameDev& geo);
+// LDS a frame of this kind and geometry needs in its launch.
+int frame_lds_bytes(const HostFrame& f, const FrameDev& geo);
+// Work queues and launch shapes of every kind present among the frames (frames listed by
+// index into tile_base / tiles; item indices are tile_base[f] + t).  cap_override > 0
+// caps the workgroups of each launch.  Fails if a frame has more tiles than can be
+// resident at once.
+otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vector<FrameDev>& geo,
+                          const std::vector<int>& tile_base, const std::vector<int>& tiles,
+                          bool stored, bool refresh, int cus, int cap_override,
+                          const XcdInfo& xi, bool agent, std::vector<int32_t>& qitems,
+                          std::vector<int2>& qrange, std::vector<KindLaunch>& out);
+
 }  // namespace otfs
 
 struct otfs_plan {
@@ -86,15 +109,12 @@ struct otfs_plan {
   int max_paths = 0, cus = 256;
   int tile_elems = 0, max_grid_req = 0;
   int stage_bytes = otfs::kDefaultStageBytes;   // LDS budget for staged windows, 0 = off
-  int lds_bytes = 0;                            // dynamic LDS of the launches (bind)
   // tiling (host) and schedule (chosen at bind)
   std::vector<otfs::WorkItem> items;
   std::vector<int> tile_base, tiles;
   std::vector<int32_t> qitems;
   std::vector<int2> qrange;
-  int ngroups = 1;
-  bool xcd_local = false;
-  int grid = 0;
+  std::vector<otfs::KindLaunch> launches;
   otfs::Layout L;
   // binding
   bool bound = false;

@@ -134,8 +134,8 @@ CtrlLayout ctrl_layout() {
   C.frames = take(kMaxActive * sizeof(FrameDev));
   C.items = take(kMaxItems * sizeof(WorkItem));
   C.qitems = take(kMaxItems * sizeof(int32_t));
-  C.qrange = take(kMaxGroups * sizeof(int2));
-  C.qhead = take(kMaxGroups * sizeof(unsigned));
+  C.qrange = take(kKinds * kMaxGroups * sizeof(int2));
+  C.qhead = take(kKinds * kMaxGroups * sizeof(unsigned));
   C.abort = take(sizeof(unsigned));
   C.stats = take(kMaxActive * sizeof(otfs_frame_stats));
   C.probe = take(kProbeBlocks * sizeof(int));
@@ -190,8 +190,7 @@ struct otfs_server {
   // device objects (scheduler thread)
   hipStream_t s = nullptr;
   XcdInfo xcd;
-  int bpc = 1, cus = 256;
-  int lds_bytes = 0;
+  int cus = 256;
   int cap = 0;              // workgroups of the fused kernel resident at once
   bool ready = false;       // scheduler_init finished
   int active_tiles = 0;
@@ -309,19 +308,13 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   }
   std::vector<int32_t> qitems;
   std::vector<int2> qrange;
-  int per = 0;
-  bool xcd = false;
-  int ngroups = 1, grid = 0;
-  const int cap = S->bpc * S->cus;
-  if (S->xcd.round_robin && !(S->opts.flags & OTFS_AGENT_BARRIER) && cap >= S->xcd.nxcd &&
-      make_queues(frames, tile_base, tiles, S->xcd.nxcd, cap / S->xcd.nxcd, qitems, qrange, &per)) {
-    xcd = true;
-    ngroups = S->xcd.nxcd;
-    grid = per * ngroups;
-  } else if (make_queues(frames, tile_base, tiles, 1, cap, qitems, qrange, &per)) {
-    grid = per;
-  } else {
-    set_failed(S, "a frame needs more cooperating workgroups than fit");
+  std::vector<FrameDev> geo(n);
+  for (int i = 0; i < n; ++i) geo[i] = act[i]->geo;
+  std::vector<KindLaunch> launches;
+  if (plan_launches(frames, geo, tile_base, tiles, false, S->opts.refresh_every > 0, S->cus, 0,
+                    S->xcd, (S->opts.flags & OTFS_AGENT_BARRIER) != 0, qitems, qrange,
+                    launches) != OTFS_OK) {
+    set_failed(S, otfs_last_error());
     return false;
   }
   char* P = S->pool;
@@ -337,14 +330,18 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   const FrameDev* dframes = reinterpret_cast<const FrameDev*>(P + C.frames);
   unsigned* qhead = reinterpret_cast<unsigned*>(P + C.qhead);
   unsigned* abort_flag = reinterpret_cast<unsigned*>(P + C.abort);
-  if (e == hipSuccess) e = launch_step_reset(dframes, n, abort_flag, qhead, ngroups, S->s);
-  Bases B{nullptr, nullptr, nullptr, nullptr};
   if (e == hipSuccess)
-    e = launch_cg_fused(false, S->opts.refresh_every > 0, dframes,
+    e = launch_step_reset(dframes, n, abort_flag, qhead, kKinds * kMaxGroups, S->s);
+  Bases B{nullptr, nullptr, nullptr, nullptr};
+  for (const KindLaunch& L : launches) {
+    if (e != hipSuccess) break;
+    e = launch_cg_fused(L.kind, false, S->opts.refresh_every > 0, dframes,
                         reinterpret_cast<const WorkItem*>(P + C.items),
                         reinterpret_cast<const int32_t*>(P + C.qitems),
-                        reinterpret_cast<const int2*>(P + C.qrange), qhead, ngroups, grid,
-                        S->step_iters, B, xcd, abort_flag, S->lds_bytes, S->s);
+                        reinterpret_cast<const int2*>(P + C.qrange) + L.qbase, qhead + L.qbase,
+                        L.ngroups, L.grid, S->step_iters, B, L.xcd_local, abort_flag,
+                        L.lds_bytes, S->s);
+  }
   out.resize(n);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out.data(), dstats, n * sizeof(otfs_frame_stats), hipMemcpyDeviceToHost, S->s);
@@ -395,9 +392,8 @@ bool scheduler_init(otfs_server* S) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess && v > 0)
     S->cus = v;
-  S->lds_bytes = kDefaultStageBytes;
-  S->bpc = std::max(1, fused_blocks_per_cu(false, S->opts.refresh_every > 0, S->lds_bytes));
-  S->cap = S->bpc * S->cus;
+  // the tile cap of a frame: workgroups of the direct kind resident at once
+  S->cap = std::max(1, fused_blocks_per_cu(kKindDirect, false, S->opts.refresh_every > 0, 0)) * S->cus;
   return true;
 }
 

@@ -145,7 +145,8 @@ def test_cg_single_64x16_config(otfs):
 @pytest.mark.parametrize("tile_elems,max_grid,agent,stage", [
     (0, 0, 0, None), (700, 0, 0, None), (700, 8, 1, None), (700, 64, 0, None),
     (2048, 3, 1, None), (0, 0, 1, None), (350, 0, 0, None), (200, 0, 0, None),
-    (200, 0, 1, None), (0, 0, 0, 0), (700, 0, 0, 0), (700, 0, 0, 16384)])
+    (200, 0, 1, None), (0, 0, 0, 0), (700, 0, 0, 0), (700, 0, 0, 16384), (700, 0, 0, 40960),
+    (0, 0, 1, 40960)])
 def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent, stage):
     frames = _mixed_frames(11, 9, [(128, 32), (64, 16), (100, 30), (96, 8), (256, 16)],
                            (1, 9), 12, 4)
@@ -161,8 +162,8 @@ def test_cg_ragged_batch_tilings(otfs, tile_elems, max_grid, agent, stage):
 
 
 def test_cg_resident_small_frames(otfs):
-    # one-tile frames whose vectors fit in LDS run the resident form; with the LDS budget
-    # set to zero the same frames run the memory-resident form
+    # one-tile frames whose vectors fit in LDS run the resident form; with
+    # NO_LDS_RESIDENT the same frames run the memory form
     frames = _mixed_frames(21, 8, [(64, 16), (32, 32), (37, 11), (8, 4), (5, 3), (16, 64),
                                    (1, 7), (100, 10)], (1, 6), 12, 4)
     ops, xs, y = oracle_batch(frames)
@@ -172,7 +173,7 @@ def test_cg_resident_small_frames(otfs):
     out_res = _run(otfs, res, y)
     _cg_check(out_res, frames, ops, y, NMSE_TOL, "resident")
     say("cg small frames without LDS")
-    mem = otfs.Plan([f.spec for f in frames], stage_bytes=0)
+    mem = otfs.Plan([f.spec for f in frames], flags=otfs.NO_LDS_RESIDENT)
     assert mem.info().resident_frames == 0 and mem.info().lds_bytes == 0
     out_mem = _run(otfs, mem, y)
     _cg_check(out_mem, frames, ops, y, NMSE_TOL, "memory")
@@ -202,9 +203,12 @@ def test_cg_plain_matches_oracle_and_fused(otfs):
     xf, sf, stf = _run(otfs, plan, y, "fused")
     xp, sp_, stp = _run(otfs, plan, y, "plain")
     _cg_check((xp, sp_, stp), frames, ops, y, NMSE_TOL, "plain")
-    assert np.array_equal(stf["iters"], stp["iters"])
+    assert np.all(np.abs(stf["iters"] - stp["iters"]) <= 1)
+    # same algorithm and stop rule; the two forms may sum the per-thread partials of the
+    # inner products in different orders (the staged fused form walks the band in blocks),
+    # so they agree to FP32 rounding rather than bit for bit
     for a, b in zip(split(xf, frames), split(xp, frames)):
-        assert O.nmse(a, b) <= 1e-9
+        assert O.nmse(a, b) <= 1e-6
 
 
 def test_cg_fixed_iterations_and_first_step(otfs):
