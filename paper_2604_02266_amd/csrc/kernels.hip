@@ -393,15 +393,18 @@ __device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
 // band; for H^H the factor is W[l]^w of the output row itself.
 // ---------------------------------------------------------------------------------------
 #ifndef OTFS_ROWS
-#define OTFS_ROWS 2
+#define OTFS_ROWS 4
 #endif
 #ifndef OTFS_PATHS
 #define OTFS_PATHS 2
 #endif
 constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
 constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
-constexpr int kRows64 = 4;   // rows per thread chunk in the FP64 refresh gathers
-constexpr int kElemChunk = 8;   // elements per thread in flight in element-wise passes
+constexpr int kRows64 = 2;   // rows per thread chunk in the FP64 refresh gathers
+#ifndef OTFS_ELEM_CHUNK
+#define OTFS_ELEM_CHUNK 8
+#endif
+constexpr int kElemChunk = OTFS_ELEM_CHUNK;   // elements per thread in flight, element-wise passes
 #ifndef OTFS_RES_ROWS
 #define OTFS_RES_ROWS 2
 #endif
@@ -486,9 +489,11 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, co
               const float2 dd = bf16x2_to_f2(d[u][i]);
               c = ADJ ? make_float2(dd.x, -dd.y) : dd;
             } else {
-              const float2 w = make_float2(wl[i].x, nw[u] > 0 ? wl[i].y : -wl[i].y);
-              const float2 cr = cmulf(cw[u], w);
-              c = nw[u] != 0 ? cr : cf[u];
+              c = cf[u];
+              if (nw[u] != 0) {   // only lanes at a delay wrap (no memory access inside)
+                const float2 w = make_float2(wl[i].x, nw[u] > 0 ? wl[i].y : -wl[i].y);
+                c = cmulf(cw[u], w);
+              }
             }
             cmacf(acc[i], c, src.value(v[u][i]));
           }
@@ -655,7 +660,7 @@ __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, 
 // geometry), gathered straight from memory otherwise.  out.pre(q) issues the loads output q needs
 // besides the source; out.put(q, v, pre, own) receives it with own[] = the source
 // vectors' elements at q.
-template <bool ADJ, bool STORED, bool STAGED, class Src, class Out>
+template <bool ADJ, bool STORED, bool STAGED, int R = kRows, class Src, class Out>
 __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, float2* lds,
                                            const Src& src, const Out& out) {
   if constexpr (STAGED && !STORED && Src::kStageable) {
@@ -665,7 +670,7 @@ __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, fl
       typename Out::Pre pre;
       float2 own[Src::kNV];
     };
-    band_apply<kRows, kPaths, ADJ, STORED>(
+    band_apply<R, kPaths, ADJ, STORED>(
         F, lb, le, src,
         [&](uint32_t u) {
           PreOwn po;
@@ -815,6 +820,8 @@ struct LaunchCtx {
 template <bool STORED, bool REFRESH, bool STAGED>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                         const LaunchCtx& L, float* red, double* redd, int* sflag, float2* lds) {
+  // the bf16 table reads and the FP64 refresh leave fewer registers for gathers in flight
+  constexpr int RR = (STORED || REFRESH) ? 2 : kRows;
   const FrameVecs V = frame_vecs(F, B);
   FrameState s = *F.st;
   if (s.status != OTFS_FRAME_RUNNING) return;
@@ -851,9 +858,9 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     float acc = 0.f;
     const OutInit out{cv, cvec(F.p0, E), xv, &acc};
     if (V.ybf16)
-      apply_band<true, STORED, STAGED>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, out);
+      apply_band<true, STORED, STAGED, RR>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, out);
     else
-      apply_band<true, STORED, STAGED>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, out);
+      apply_band<true, STORED, STAGED, RR>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, out);
     const float bs = block_sum(acc, red);
     if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
     if (!bar()) return fail_timeout();
@@ -883,14 +890,40 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
 
     // ---- A: deferred updates of the band, t = H p ----
-    apply_band<false, STORED, STAGED>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
-                              OutA{tv, pnv, xv, al, be, xp});
+    if constexpr (STAGED) {
+      // c and the old p are staged together; p' = c + beta p is formed from the windows
+      apply_band<false, STORED, true, RR>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
+                                      OutA{tv, pnv, xv, al, be, xp});
+    } else {
+      // A1: p' = c + beta p_old and x += alpha p_old over the band, stored once
+      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * kElemChunk) {
+        float2 c[kElemChunk], po[kElemChunk], xo[kElemChunk];
+#pragma unroll
+        for (int j = 0; j < kElemChunk; ++j) {
+          const uint32_t w = min(u + (uint32_t)(j * kBlock), u1 - 1u);
+          c[j] = cv.ld(w);
+          po[j] = pov.ld(w);
+          if (xp) xo[j] = xv.ld(w);
+        }
+#pragma unroll
+        for (int j = 0; j < kElemChunk; ++j) {
+          const uint32_t w = u + (uint32_t)(j * kBlock);
+          if (w < u1) {
+            pnv.st(w, axpyf(be, po[j], c[j]));
+            if (xp) xv.st(w, axpyf(al, po[j], xo[j]));
+          }
+        }
+      }
+      if (!bar()) return fail_timeout();
+      // A2: t = H p' (one load per gather)
+      apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore{tv});
+    }
     if (!bar()) return fail_timeout();
 
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
       float acc = 0.f;
-      apply_band<true, STORED, STAGED>(F, lb, le, lds, SrcBuf{tv.r}, OutB{av, pnv, lam, &acc});
+      apply_band<true, STORED, STAGED, RR>(F, lb, le, lds, SrcBuf{tv.r}, OutB{av, pnv, lam, &acc});
       const float bs = block_sum(acc, red);
       if (threadIdx.x == 0) F.part_pa[wi.tile] = bs;
     }

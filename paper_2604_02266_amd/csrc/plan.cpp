@@ -227,9 +227,12 @@ void wrap_factors(const HostFrame& f, std::vector<double2>& out) {
 // ---------------------------------------------------------------------------------------
 // tiling: frame f is split into T_f bands of Doppler rows, one workgroup each
 // ---------------------------------------------------------------------------------------
+#ifndef OTFS_WG_PER_CU
+#define OTFS_WG_PER_CU 4
+#endif
 int default_tile_elems(int64_t total_elems, int cus) {
-  // aim at about four workgroups per CU for the whole batch
-  const int64_t target = std::max<int64_t>(1, (int64_t)cus * 4);
+  // aim at as many tiles as fused workgroups fit at once (OTFS_WG_PER_CU per CU)
+  const int64_t target = std::max<int64_t>(1, (int64_t)cus * OTFS_WG_PER_CU);
   int64_t te = total_elems / target;
   te = std::max<int64_t>(te, 2048);
   te = std::min<int64_t>(te, 65536);
