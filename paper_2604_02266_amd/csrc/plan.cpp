@@ -92,7 +92,21 @@ otfs_status validate_frame(const otfs_frame_desc& f, int idx, HostFrame* out) {
     h.nu[p] = v;
     h.h[p] = {re, im};
   }
-  *out = std::move(h);
+  // Paths in (Doppler, delay) order: consecutive paths of the gather loop then read the
+  // same or neighbouring source rows, which the caches serve (the sum over paths is the
+  // same; only its rounding order follows this order).
+  std::vector<int> ord(h.P);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    return h.nu[a] != h.nu[b] ? h.nu[a] < h.nu[b] : h.tau[a] < h.tau[b];
+  });
+  HostFrame g = h;
+  for (int p = 0; p < h.P; ++p) {
+    g.tau[p] = h.tau[ord[p]];
+    g.nu[p] = h.nu[ord[p]];
+    g.h[p] = h.h[ord[p]];
+  }
+  *out = std::move(g);
   return OTFS_OK;
 }
 
