@@ -501,6 +501,12 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, co
       };
       int p = 0;
       for (; p + U <= P; p += U) step(std::integral_constant<int, U>{}, p);
+      if constexpr (U > 2) {
+        if (p + 2 <= P) {
+          step(std::integral_constant<int, 2>{}, p);
+          p += 2;
+        }
+      }
       for (; p < P; ++p) step(std::integral_constant<int, 1>{}, p);
 #pragma unroll
       for (int i = 0; i < R; ++i)

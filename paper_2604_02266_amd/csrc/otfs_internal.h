@@ -10,7 +10,10 @@
 
 namespace otfs {
 
-constexpr int kBlock = 256;          // threads per workgroup of every kernel
+#ifndef OTFS_BLOCK
+#define OTFS_BLOCK 512
+#endif
+constexpr int kBlock = OTFS_BLOCK;   // threads per workgroup of every kernel
 constexpr int kWaves = kBlock / 64;  // wave64
 
 // Per-frame CG scalars that persist between launches of the fused kernel (a serving step

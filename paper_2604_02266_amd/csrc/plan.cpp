@@ -249,7 +249,7 @@ void wrap_factors(const HostFrame& f, std::vector<double2>& out) {
 // the same memory-channel pattern; measured 2-3 % on the 64-frame batch.
 constexpr int kFramePad = OTFS_FRAME_PAD;
 #ifndef OTFS_WG_PER_CU
-#define OTFS_WG_PER_CU 4
+#define OTFS_WG_PER_CU 2
 #endif
 int default_tile_elems(int64_t total_elems, int cus) {
   // aim at as many tiles as fused workgroups fit at once (OTFS_WG_PER_CU per CU)
