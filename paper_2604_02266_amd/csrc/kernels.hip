@@ -114,11 +114,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int64_
 }
 
 // Source views of a band application: load(i) issues the reads of element i, value(raw)
-// forms the element from them.  A stageable view also names the kNV complex64 vectors it
+// forms the element from them; load_b(vb, sb) reads the element at byte offset vb + sb of
+// a complex64 vector, where sb is the same for the whole wave when the caller can prove
+// it (it then goes into the instruction's scalar offset).  A stageable view also names the kNV complex64 vectors it
 // reads (rsrc(j)) and forms the element from their values (combine); own(i, v) reads them
 // at element i.
 __device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, uint32_t i) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+}
+__device__ __forceinline__ float2 buf_ld2b(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vb, sb, 0));
 }
 struct SrcBuf {   // complex64 vector
   __amdgpu_buffer_rsrc_t r;
@@ -126,6 +131,7 @@ struct SrcBuf {   // complex64 vector
   static constexpr bool kStageable = true;
   using Raw = float2;
   __device__ __forceinline__ Raw load(uint32_t i) const { return buf_ld2(r, i); }
+  __device__ __forceinline__ Raw load_b(uint32_t vb, uint32_t sb) const { return buf_ld2b(r, vb, sb); }
   __device__ __forceinline__ float2 value(Raw v) const { return v; }
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int) const { return r; }
   __device__ __forceinline__ float2 combine(const float2* v) const { return v[0]; }
@@ -138,6 +144,9 @@ struct SrcBf16 {  // complex stored as a bf16 pair per element (not staged)
   using Raw = uint32_t;
   __device__ __forceinline__ Raw load(uint32_t i) const {
     return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0);
+  }
+  __device__ __forceinline__ Raw load_b(uint32_t vb, uint32_t sb) const {   // bytes of complex64
+    return __builtin_amdgcn_raw_buffer_load_b32(r, vb >> 1, sb >> 1, 0);
   }
   __device__ __forceinline__ float2 value(Raw v) const { return bf16x2_to_f2(v); }
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int) const { return r; }
@@ -153,6 +162,9 @@ struct SrcDir {   // the new direction c + beta p, formed from c and the old p
     float2 c, p;
   };
   __device__ __forceinline__ Raw load(uint32_t i) const { return Raw{buf_ld2(c, i), buf_ld2(p, i)}; }
+  __device__ __forceinline__ Raw load_b(uint32_t vb, uint32_t sb) const {
+    return Raw{buf_ld2b(c, vb, sb), buf_ld2b(p, vb, sb)};
+  }
   __device__ __forceinline__ float2 value(const Raw& v) const { return axpyf(beta, v.p, v.c); }
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int j) const { return j == 0 ? c : p; }
   __device__ __forceinline__ float2 combine(const float2* v) const { return axpyf(beta, v[1], v[0]); }
@@ -165,6 +177,9 @@ struct SrcLds {   // complex64 vector in LDS
   LdsC v;
   using Raw = float2;
   __device__ __forceinline__ Raw load(uint32_t i) const { return v.ld((int)i); }
+  __device__ __forceinline__ Raw load_b(uint32_t vb, uint32_t sb) const {
+    return v.ld((int)((vb + sb) >> 3));
+  }
   __device__ __forceinline__ float2 value(Raw x) const { return x; }
 };
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -414,55 +429,63 @@ constexpr int kElemChunk = OTFS_ELEM_CHUNK;   // elements per thread in flight, 
 constexpr int kResRows = OTFS_RES_ROWS;    // rows per chunk of the LDS-resident gathers
 constexpr int kResPaths = OTFS_RES_PATHS;  // paths per step of the LDS-resident gathers
 
-template <int R, int U, bool ADJ, bool STORED, class Src, class Pref, class Sink>
-__device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
-                                           Pref pref, Sink sink) {
+template <int R, int U, bool ADJ, bool STORED, bool UNI, class Src, class Pref, class Sink>
+__device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int le, const Src& src,
+                                                Pref pref, Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
   const int TY = kBlock / TX;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int tx = threadIdx.x % TX;
+  // UNI: TX is a multiple of 64, so every wave lies in one row group ty and the row
+  // arithmetic below is the same for all its lanes (scalar registers, scalar offsets).
+  const int ty = UNI ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / TX)
+                     : (int)threadIdx.x / TX;
   if (ty >= TY) return;
   const int64_t E = (int64_t)M * N;
+  const uint32_t M8 = 8u * (uint32_t)M, E8 = 8u * (uint32_t)E;   // E8 < 2^31
   const int nrows = le - lb - ty > 0 ? (le - lb - ty + TY - 1) / TY : 0;
   const KPairs paths = kpairs(F.paths);
   const KPairs wtab_s = kpairs(F.wtab);
-  const GPairs rtab = gpairs(F.rtab);
+  const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(F.rtab, (int64_t)P * M * 8);
   const GPairs wtab = gpairs(F.wtab);
   const gptr<const uint32_t> dtab = glb(F.dtab);
   for (int k = tx; k < M; k += TX) {
     for (int r0 = 0; r0 < nrows; r0 += R) {
       int l[R];
+      uint32_t l8[R];   // byte offset of row l
       float2 wl[R];
       float2 acc[R];
       decltype(pref(0u)) pf[R];   // the outputs' own loads, issued with the gathers
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         l[i] = lb + ty + min(r0 + i, nrows - 1) * TY;
-        if (!STORED) wl[i] = wtab.f(l[i]);
+        l8[i] = (uint32_t)l[i] * M8;
+        if (!STORED) wl[i] = UNI ? wtab_s.f(l[i]) : wtab.f(l[i]);
         acc[i] = make_float2(0.f, 0.f);
         pf[i] = pref((uint32_t)(l[i] * M + k));
       }
       // NP paths at once: all NP*R gathers are issued before any is consumed
       auto step = [&](auto npc, int p0) {
         constexpr int NP = decltype(npc)::value;
-        int kk[NP], nw[NP], nuv[NP];
-        float2 cf[NP], cw[NP];
+        uint32_t kk8[NP], dn8[NP];
+        bool lo[NP], hi[NP];   // delay wrap: the source column is K + M (lo) or K - M (hi)
+        float2 cf[NP], wn[NP];
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
           const int2 tn = paths.i2(p0 + u);
           const int K = ADJ ? k + tn.x : k - tn.x;   // H: <k - tau>_M; H^H: <k + tau>_M
-          nw[u] = K < 0 ? -1 : (K >= M ? 1 : 0);     // wrap count
-          kk[u] = K - nw[u] * M;
-          nuv[u] = tn.y;
+          lo[u] = K < 0;
+          hi[u] = K >= M;
+          kk8[u] = 8u * (uint32_t)(lo[u] ? K + M : (hi[u] ? K - M : K));
+          // source row <l -+ nu>_N = l + d - N (+ N when negative), d = <-+nu>_N
+          const int sh = ADJ ? tn.y : -tn.y;
+          dn8[u] = (uint32_t)((sh < 0 ? sh : sh - N) * M8);
           if (!STORED) {
-            const float2 r = rtab.f((p0 + u) * M + (ADJ ? kk[u] : k));
+            const float2 r = __builtin_bit_cast(
+                float2, __builtin_amdgcn_raw_buffer_load_b64(
+                            rtab, ADJ ? kk8[u] : 8u * (uint32_t)k, (uint32_t)(p0 + u) * M8, 0));
             cf[u] = ADJ ? make_float2(r.x, -r.y) : r;
-            if (ADJ) {
-              cw[u] = cf[u];
-            } else {
-              const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
-              cw[u] = cmulf(cf[u], make_float2(wn.x, nw[u] > 0 ? -wn.y : wn.y));
-            }
+            if (!ADJ) wn[u] = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
           }
         }
         typename Src::Raw v[NP][R];
@@ -471,31 +494,40 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, co
         for (int u = 0; u < NP; ++u) {
 #pragma unroll
           for (int i = 0; i < R; ++i) {
-            int ls = ADJ ? l[i] + nuv[u] : l[i] - nuv[u];
-            ls += ls < 0 ? N : 0;
-            ls -= ls >= N ? N : 0;
-            const int qs = ls * M + kk[u];
-            v[u][i] = src.load((uint32_t)qs);
+            // (ls - N) * 8M wraps below zero exactly when ls < N; min picks the row in range
+            const uint32_t x = l8[i] + dn8[u];
+            const uint32_t rs = min(x, x + E8);
+            if (UNI)
+              v[u][i] = src.load_b(kk8[u], rs);
+            else
+              v[u][i] = src.load_b(kk8[u] + rs, 0u);
             if (STORED)
-              d[u][i] = dtab[(int64_t)(p0 + u) * E + (ADJ ? (int64_t)qs : (int64_t)l[i] * M + k)];
+              d[u][i] = dtab[(int64_t)(p0 + u) * E +
+                             (ADJ ? (int64_t)((rs + kk8[u]) >> 3) : (int64_t)l[i] * M + k)];
           }
         }
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
+          if (STORED) {
 #pragma unroll
-          for (int i = 0; i < R; ++i) {
-            float2 c;
-            if (STORED) {
+            for (int i = 0; i < R; ++i) {
               const float2 dd = bf16x2_to_f2(d[u][i]);
-              c = ADJ ? make_float2(dd.x, -dd.y) : dd;
-            } else {
-              c = cf[u];
-              if (nw[u] != 0) {   // only lanes at a delay wrap (no memory access inside)
-                const float2 w = make_float2(wl[i].x, nw[u] > 0 ? wl[i].y : -wl[i].y);
-                c = cmulf(cw[u], w);
-              }
+              cmacf(acc[i], ADJ ? make_float2(dd.x, -dd.y) : dd, src.value(v[u][i]));
             }
-            cmacf(acc[i], c, src.value(v[u][i]));
+          } else if (__builtin_amdgcn_ballot_w64(lo[u] || hi[u]) != 0) {
+            // a wave holding a delay wrap of this path (few of them): wrapped lanes take
+            // W^n, n = -1 (lo) or +1 (hi); for H also the path part conj(W[nu])^n
+            const float2 cw = ADJ ? cf[u]
+                                  : cmulf(cf[u], make_float2(wn[u].x, hi[u] ? -wn[u].y : wn[u].y));
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+              const float2 w = make_float2(wl[i].x, hi[u] ? wl[i].y : -wl[i].y);
+              const float2 c = (lo[u] || hi[u]) ? cmulf(cw, w) : cf[u];
+              cmacf(acc[i], c, src.value(v[u][i]));
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < R; ++i) cmacf(acc[i], cf[u], src.value(v[u][i]));
           }
         }
       };
@@ -513,6 +545,16 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, co
         if (r0 + i < nrows) sink(l[i] * M + k, acc[i], pf[i]);
     }
   }
+}
+
+template <int R, int U, bool ADJ, bool STORED, class Src, class Pref, class Sink>
+__device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
+                                           Pref pref, Sink sink) {
+  const int TX = F.M < kBlock ? F.M : kBlock;
+  if ((TX & 63) == 0)
+    band_apply_rows<R, U, ADJ, STORED, true>(F, lb, le, src, pref, sink);
+  else
+    band_apply_rows<R, U, ADJ, STORED, false>(F, lb, le, src, pref, sink);
 }
 
 // band_apply with nothing to prefetch: sink(q, v)
