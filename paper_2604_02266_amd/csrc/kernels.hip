@@ -185,15 +185,28 @@ struct SrcLds {   // complex64 vector in LDS
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // A complex64 vector read and written element-wise through a buffer resource (one 32-bit
 // offset per element, shared by every vector accessed at that element).
+// NT: non-temporal cache policy (streamed data that should not displace gather sources
+// in L2).
 struct CVec {
   __amdgpu_buffer_rsrc_t r;
+  template <bool NT = false>
   __device__ __forceinline__ float2 ld(uint32_t i) const {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+    return __builtin_bit_cast(float2,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, NT ? 2 : 0));
   }
+  template <bool NT = false>
   __device__ __forceinline__ void st(uint32_t i, float2 v) const {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, 0,
+                                          NT ? 2 : 0);
   }
 };
+#ifndef OTFS_NT
+#define OTFS_NT 7
+#endif
+constexpr bool kNtElem = (OTFS_NT & 1) != 0;   // element-wise passes: loads, x and c stores
+constexpr bool kNtB = (OTFS_NT & 2) != 0;      // H^H pass: p' read, a stored
+constexpr bool kNtT = (OTFS_NT & 4) != 0;      // H pass: t stored
+constexpr bool kNtP = (OTFS_NT & 8) != 0;      // direction pass: p' stored
 __device__ __forceinline__ CVec cvec(const float2* p, int64_t n) { return CVec{buf_rsrc(p, n * 8)}; }
 __device__ __forceinline__ SrcBuf src_vec(const float2* p, int64_t n) {
   return SrcBuf{buf_rsrc(p, n * 8)};
@@ -205,13 +218,14 @@ __device__ __forceinline__ SrcDir src_dir(const float2* c, const float2* p, floa
 
 // Output views of a band application (see apply_band).
 struct NoPre {};
+template <bool NT = false>
 struct OutStore {   // out = v
   CVec o;
   static constexpr bool kOwn = false;
   using Pre = NoPre;
   __device__ __forceinline__ Pre pre(uint32_t) const { return Pre{}; }
   __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre&, const float2*) const {
-    o.st(q, v);
+    o.st<NT>(q, v);
   }
 };
 struct OutInit {    // b = H^H y: c = p = b, x = 0, partial ||b||^2
@@ -253,10 +267,10 @@ struct OutB {       // a = H^H t + lam p', partial Re(p'^H a)
   struct Pre {
     float2 p;
   };
-  __device__ __forceinline__ Pre pre(uint32_t q) const { return Pre{pn.ld(q)}; }
+  __device__ __forceinline__ Pre pre(uint32_t q) const { return Pre{pn.ld<kNtB>(q)}; }
   __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre& pr, const float2*) const {
     const float2 av = axpyf(lam, pr.p, v);
-    a.st(q, av);
+    a.st<kNtB>(q, av);
     *acc = fmaf(pr.p.x, av.x, *acc);
     *acc = fmaf(pr.p.y, av.y, *acc);
   }
@@ -376,6 +390,83 @@ __device__ bool frame_barrier(unsigned* ctr, unsigned target, bool xcd_local,
       }
     }
     *sflag = ok;
+  }
+  __syncthreads();
+  if (xcd_local)
+    xcd_acquire();
+  else
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *sflag != 0;
+}
+
+// Neighbour synchronisation.  Between the direction pass and the H pass, and between the
+// H pass and the H^H pass, a tile reads only rows within the Doppler shift range of its
+// own band, so it waits for the tiles owning those rows instead of the whole frame.  Each
+// tile counts the phases it has finished in prog[tile] (an L2 atomic after its stores are
+// released); a waiting tile polls the counters of the tiles it reads, one lane per tile.
+// Every earlier writer of the rows it reads is separated from the read by a full barrier.
+__device__ __forceinline__ void tile_publish(unsigned* flag, bool xcd_local) {
+  if (xcd_local)
+    xcd_release();
+  else
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(flag, 1u, __ATOMIC_RELAXED,
+                           xcd_local ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tiles owning the cyclic row range [r0, r0 + span) of a frame of N rows in T bands
+// (band t = [t N / T, (t + 1) N / T)): first tile and count.
+struct TileRange {
+  int first, count;
+};
+__device__ __forceinline__ int tile_of_row(int r, int N, int T) {
+  return (int)((((int64_t)r + 1) * T - 1) / N);
+}
+__device__ __forceinline__ TileRange tiles_of_rows(int r0, int span, int N, int T) {
+  if (span >= N) return TileRange{0, T};
+  r0 %= N;
+  if (r0 < 0) r0 += N;
+  int r1 = r0 + span - 1;
+  if (r1 >= N) r1 -= N;
+  const int t0 = tile_of_row(r0, N, T), t1 = tile_of_row(r1, N, T);
+  int cnt = t1 - t0 + 1;
+  if (cnt <= 0) cnt += T;
+  return TileRange{t0, cnt};
+}
+
+__device__ bool halo_wait(const unsigned* prog, int T, TileRange tr, unsigned target,
+                          bool xcd_local, unsigned* abort_flag, uint64_t timeout, int* sflag) {
+  if (threadIdx.x < 64) {
+    const int lane = (int)threadIdx.x;
+    int ok = 1;
+    const uint64_t t0 = wall_clock64();
+    for (int b = 0; b < tr.count && ok; b += 64) {
+      const int j = b + lane;
+      bool done = j >= tr.count;
+      int tile = tr.first + j;
+      if (tile >= T) tile -= T;
+      unsigned* fl = const_cast<unsigned*>(prog) + (done ? 0 : tile);
+      for (;;) {
+        if (!done) {
+          const unsigned v = xcd_local ? l2_poll(fl)
+                                       : __hip_atomic_load(fl, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+          done = v >= target;
+        }
+        if (__builtin_amdgcn_ballot_w64(!done) == 0) break;
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            wall_clock64() - t0 > timeout) {
+          if (lane == 0)
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    if (lane == 0) *sflag = ok;
   }
   __syncthreads();
   if (xcd_local)
@@ -889,6 +980,20 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     nbar += (unsigned)T;
     return frame_barrier(F.bar, nbar, L.xcd_local != 0, L.abort_flag, L.timeout, sflag);
   };
+  // tiles whose rows the H pass (rows l - nu) and the H^H pass (rows l + nu) read
+  const int span = le - lb + (F.nu_hi - F.nu_lo);
+  const TileRange rd_h = tiles_of_rows(lb - F.nu_hi, span, F.N, T);
+  const TileRange rd_hh = tiles_of_rows(lb + F.nu_lo, span, F.N, T);
+  unsigned npub = 0;
+  auto halo = [&](const TileRange& tr) -> bool {
+    if (T == 1) {
+      __syncthreads();
+      return true;
+    }
+    tile_publish(F.prog + wi.tile, L.xcd_local != 0);
+    ++npub;
+    return halo_wait(F.prog, T, tr, npub, L.xcd_local != 0, L.abort_flag, L.timeout, sflag);
+  };
   auto fail_timeout = [&]() {
     if (wi.tile == 0 && threadIdx.x == 0) {
       FrameState o = s;
@@ -949,24 +1054,24 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
 #pragma unroll
         for (int j = 0; j < kElemChunk; ++j) {
           const uint32_t w = min(u + (uint32_t)(j * kBlock), u1 - 1u);
-          c[j] = cv.ld(w);
-          po[j] = pov.ld(w);
-          if (xp) xo[j] = xv.ld(w);
+          c[j] = cv.ld<kNtElem>(w);
+          po[j] = pov.ld<kNtElem>(w);
+          if (xp) xo[j] = xv.ld<kNtElem>(w);
         }
 #pragma unroll
         for (int j = 0; j < kElemChunk; ++j) {
           const uint32_t w = u + (uint32_t)(j * kBlock);
           if (w < u1) {
-            pnv.st(w, axpyf(be, po[j], c[j]));
-            if (xp) xv.st(w, axpyf(al, po[j], xo[j]));
+            pnv.st<kNtP>(w, axpyf(be, po[j], c[j]));
+            if (xp) xv.st<kNtElem>(w, axpyf(al, po[j], xo[j]));
           }
         }
       }
-      if (!bar()) return fail_timeout();
+      if (!halo(rd_h)) return fail_timeout();
       // A2: t = H p' (one load per gather)
-      apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore{tv});
+      apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<kNtT>{tv});
     }
-    if (!bar()) return fail_timeout();
+    if (!halo(rd_hh)) return fail_timeout();
 
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
@@ -997,15 +1102,15 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
 #pragma unroll
         for (int j = 0; j < kElemChunk; ++j) {
           const uint32_t w = min(u + (uint32_t)(j * kBlock), u1 - 1u);
-          a[j] = av.ld(w);
-          c[j] = cv.ld(w);
+          a[j] = av.ld<kNtElem>(w);
+          c[j] = cv.ld<kNtElem>(w);
         }
 #pragma unroll
         for (int j = 0; j < kElemChunk; ++j) {
           const uint32_t w = u + (uint32_t)(j * kBlock);
           if (w < u1) {
             const float2 cn = axpyf(-alpha, a[j], c[j]);
-            cv.st(w, cn);
+            cv.st<kNtElem>(w, cn);
             acc = fmaf(cn.x, cn.x, acc);
             acc = fmaf(cn.y, cn.y, acc);
           }
@@ -1283,10 +1388,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ f
   const CVec dst = cvec(out + F.off, E);
   if (!STORED && F.skc > 0)
     apply_band<ADJ, STORED, true>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
-                                  OutStore{dst});
+                                  OutStore<>{dst});
   else
     apply_band<ADJ, STORED, false>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
-                                   OutStore{dst});
+                                   OutStore<>{dst});
 }
 
 __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsigned* abort_flag,
@@ -1297,6 +1402,7 @@ __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsign
   for (int i = t; i < nframes; i += gridDim.x * blockDim.x) {
     const FrameDev& F = frames[i];
     *F.bar = 0u;
+    for (int j = 0; j < F.T; ++j) F.prog[j] = 0u;
     FrameState s;
     s.iter = 0;
     s.status = OTFS_FRAME_RUNNING;
@@ -1319,6 +1425,7 @@ __global__ void k_step_reset(const FrameDev* __restrict__ frames, int nframes,
   for (int i = t; i < nframes; i += gridDim.x * blockDim.x) {
     const FrameDev& F = frames[i];
     *F.bar = 0u;
+    for (int j = 0; j < F.T; ++j) F.prog[j] = 0u;
     if (F.stats) {
       otfs_frame_stats st{0, 0.f, OTFS_FRAME_RUNNING, F.T};
       *F.stats = st;

@@ -55,6 +55,7 @@ struct FrameDev {
   float* part_cc;         // T partial sums of ||c||^2
   double* part_d;         // T FP64 partial sums (refresh)
   unsigned* bar;          // arrival counter of the per-frame barrier
+  unsigned* prog;         // T per-tile counters: phases whose rows the neighbours may gather
   FrameState* st;
   int64_t off;            // element offset of the frame inside batch-wide buffers
   int32_t M, N, P, T;     // grid, paths, workgroup tiles

@@ -439,6 +439,7 @@ void compute_layout(otfs_plan_t* pl) {
   L.part_cc = take(nitems * sizeof(float));
   L.part_d = take(nitems * sizeof(double));
   L.bar = take(nf * sizeof(unsigned));
+  L.prog = take(nitems * sizeof(unsigned));
   L.st = take(nf * sizeof(FrameState));
   L.abort = take(sizeof(unsigned));
   const size_t Ep = E + pl->frames.size() * (size_t)kFramePad;   // frames staggered
@@ -639,6 +640,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
     d.part_cc = reinterpret_cast<float*>(base + L.part_cc) + tb;
     d.part_d = reinterpret_cast<double*>(base + L.part_d) + tb;
     d.bar = reinterpret_cast<unsigned*>(base + L.bar) + f;
+    d.prog = reinterpret_cast<unsigned*>(base + L.prog) + tb;
     d.st = reinterpret_cast<FrameState*>(base + L.st) + f;
     frame_scalars(fr, plan->opts, plan->tiles[f], geo[f], &d);
     d.off = fr.off;

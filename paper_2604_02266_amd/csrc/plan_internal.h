@@ -26,7 +26,7 @@ struct HostFrame {
 struct Layout {
   size_t frames = 0, items = 0, qitems = 0, qrange = 0, qhead = 0, probe = 0;
   size_t rtab = 0, wtab = 0, rtab64 = 0, wtab64 = 0, paths = 0;
-  size_t part_pa = 0, part_cc = 0, part_d = 0, bar = 0, st = 0, abort = 0;
+  size_t part_pa = 0, part_cc = 0, part_d = 0, bar = 0, prog = 0, st = 0, abort = 0;
   size_t c = 0, p0 = 0, p1 = 0, t = 0, a = 0, u = 0, dtab = 0;
   size_t total = 0;
 };

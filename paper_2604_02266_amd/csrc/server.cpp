@@ -84,7 +84,7 @@ class PoolAlloc {
 // Byte offsets inside one frame's slot.
 struct SlotLayout {
   size_t y, x, c, p0, p1, t, a, u, rtab, wtab, rtab64, wtab64, paths, part_pa, part_cc, part_d,
-      bar, st, sym, total;
+      bar, prog, st, sym, total;
 };
 
 SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
@@ -113,6 +113,7 @@ SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
   L.part_cc = take((size_t)tiles * 4);
   L.part_d = take((size_t)tiles * 8);
   L.bar = take(4);
+  L.prog = take((size_t)tiles * 4);
   L.st = take(sizeof(FrameState));
   L.sym = take(E);
   L.total = o;
@@ -237,6 +238,7 @@ void build_frame_dev(otfs_server* S, Request* r, std::vector<double2>& r64,
   d.part_cc = reinterpret_cast<float*>(base + L.part_cc);
   d.part_d = reinterpret_cast<double*>(base + L.part_d);
   d.bar = reinterpret_cast<unsigned*>(base + L.bar);
+  d.prog = reinterpret_cast<unsigned*>(base + L.prog);
   d.st = reinterpret_cast<FrameState*>(base + L.st);
   d.sym = f.qam > 0 ? reinterpret_cast<uint8_t*>(base + L.sym) : nullptr;
   frame_scalars(f, S->opts, r->tiles, r->geo, &d);
