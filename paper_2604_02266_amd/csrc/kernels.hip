@@ -201,9 +201,10 @@ struct CVec {
   }
 };
 #ifndef OTFS_NT
-#define OTFS_NT 7
+#define OTFS_NT 23
 #endif
-constexpr bool kNtElem = (OTFS_NT & 1) != 0;   // element-wise passes: loads, x and c stores
+constexpr bool kNtElem = (OTFS_NT & 1) != 0;   // element-wise passes: loads
+constexpr bool kNtElemSt = (OTFS_NT & 16) != 0;  // element-wise passes: x and c stored
 constexpr bool kNtB = (OTFS_NT & 2) != 0;      // H^H pass: p' read, a stored
 constexpr bool kNtT = (OTFS_NT & 4) != 0;      // H pass: t stored
 constexpr bool kNtP = (OTFS_NT & 8) != 0;      // direction pass: p' stored
@@ -1063,7 +1064,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
           const uint32_t w = u + (uint32_t)(j * kBlock);
           if (w < u1) {
             pnv.st<kNtP>(w, axpyf(be, po[j], c[j]));
-            if (xp) xv.st<kNtElem>(w, axpyf(al, po[j], xo[j]));
+            if (xp) xv.st<kNtElemSt>(w, axpyf(al, po[j], xo[j]));
           }
         }
       }
@@ -1110,7 +1111,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
           const uint32_t w = u + (uint32_t)(j * kBlock);
           if (w < u1) {
             const float2 cn = axpyf(-alpha, a[j], c[j]);
-            cv.st<kNtElem>(w, cn);
+            cv.st<kNtElemSt>(w, cn);
             acc = fmaf(cn.x, cn.x, acc);
             acc = fmaf(cn.y, cn.y, acc);
           }
