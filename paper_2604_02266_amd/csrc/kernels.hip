@@ -312,13 +312,30 @@ __device__ double block_sum_d(double v, double* red) {
 }
 // sum of the T per-tile partials of a frame, in tile order, by every thread
 __device__ __forceinline__ double tile_sum(const float* part, int T) {
+  // loads in groups of 8 in flight together; the sum runs in tile order
   double s = 0.0;
-  for (int i = 0; i < T; ++i) s += (double)part[i];
+  int i = 0;
+  for (; i + 8 <= T; i += 8) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[i + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += (double)v[j];
+  }
+  for (; i < T; ++i) s += (double)part[i];
   return s;
 }
 __device__ __forceinline__ double tile_sum_d(const double* part, int T) {
   double s = 0.0;
-  for (int i = 0; i < T; ++i) s += part[i];
+  int i = 0;
+  for (; i + 8 <= T; i += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[i + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += v[j];
+  }
+  for (; i < T; ++i) s += part[i];
   return s;
 }
 

@@ -182,6 +182,27 @@ def test_cg_resident_small_frames(otfs):
         assert O.nmse(a, b) <= 1e-10
 
 
+@pytest.mark.parametrize("tile_elems,agent", [(256, 0), (128, 0), (640, 0), (256, 1)])
+def test_cg_wide_doppler_neighbour_waits(otfs, tile_elems, agent):
+    # Between the direction, H and H^H passes a tile waits only for the tiles owning the
+    # rows it gathers (its band shifted by the Doppler range).  Wide and one-sided Doppler
+    # ranges make those tile ranges wrap around the frame, cover most of it, or all of it.
+    rng = np.random.default_rng(31 + tile_elems + agent)
+    frames = [W.small_frame(rng, 64, 64, 6, (0, 20), (-20, 20), qam=16, snr_db=25.0,
+                            max_iters=40),
+              W.small_frame(rng, 64, 64, 5, (0, 9), (5, 30), qam=4, snr_db=20.0, max_iters=40),
+              W.small_frame(rng, 128, 48, 7, (-10, 10), (-30, -3), qam=16, snr_db=22.0,
+                            max_iters=40),
+              W.small_frame(rng, 64, 40, 4, (0, 5), (-39, 39), qam=4, snr_db=15.0,
+                            max_iters=40)]
+    ops, xs, y = oracle_batch(frames)
+    say("cg wide doppler", "tile_elems", tile_elems, "agent" if agent else "xcd",
+        [(f.spec.M, f.spec.N, f.spec.P) for f in frames])
+    plan = otfs.Plan([f.spec for f in frames], max_iters=40, rel_tol=1e-6,
+                     tile_elems=tile_elems, flags=otfs.AGENT_BARRIER if agent else 0)
+    _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
+
+
 def test_cg_fresh_plans_reusing_memory(otfs):
     # Regression: each new plan gets memory that earlier plans (other frame-to-XCD
     # assignments) used; stale cache lines must not leak into the solve.
