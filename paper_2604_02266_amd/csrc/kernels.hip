@@ -520,10 +520,17 @@ __device__ bool halo_wait(const unsigned* prog, int T, TileRange tr, unsigned ta
 #define OTFS_ROWS 4
 #endif
 #ifndef OTFS_PATHS
-#define OTFS_PATHS 2
+#define OTFS_PATHS 4
 #endif
 constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
 constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
+#ifndef OTFS_PATHS_GENERAL
+#define OTFS_PATHS_GENERAL 2
+#endif
+constexpr int kPathsGeneral = OTFS_PATHS_GENERAL;   // the same where rows are per lane
+#ifndef OTFS_FUSED_MIN_WAVES
+#define OTFS_FUSED_MIN_WAVES 4
+#endif
 constexpr int kRows64 = 2;   // rows per thread chunk in the FP64 refresh gathers
 #ifndef OTFS_ELEM_CHUNK
 #define OTFS_ELEM_CHUNK 8
@@ -660,10 +667,13 @@ template <int R, int U, bool ADJ, bool STORED, class Src, class Pref, class Sink
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
                                            Pref pref, Sink sink) {
   const int TX = F.M < kBlock ? F.M : kBlock;
+  // the per-lane row arithmetic of the general form holds more registers: fewer paths
+  // in flight there
   if ((TX & 63) == 0)
     band_apply_rows<R, U, ADJ, STORED, true>(F, lb, le, src, pref, sink);
   else
-    band_apply_rows<R, U, ADJ, STORED, false>(F, lb, le, src, pref, sink);
+    band_apply_rows<R, (U < kPathsGeneral ? U : kPathsGeneral), ADJ, STORED, false>(F, lb, le, src,
+                                                                                  pref, sink);
 }
 
 // band_apply with nothing to prefetch: sink(q, v)
@@ -1344,7 +1354,7 @@ __device__ __forceinline__ int xcc_id() {
 // group never has fewer resident workgroups than a frame has tiles, so the first frame
 // with an untaken tile is always being completed: the per-frame barriers cannot deadlock.
 template <bool STORED, bool REFRESH, int KIND>
-__global__ __launch_bounds__(kBlock) void k_cg_fused(const FrameDev* __restrict__ frames,
+__global__ __launch_bounds__(kBlock, OTFS_FUSED_MIN_WAVES) void k_cg_fused(const FrameDev* __restrict__ frames,
                                                      const WorkItem* __restrict__ items,
                                                      const int32_t* __restrict__ qitems,
                                                      const int2* __restrict__ qrange,
