@@ -89,8 +89,13 @@ enum {
                                     per-frame barriers, independent of workgroup placement
                                     (default: frames stay on one XCD, barriers coherent
                                     through that XCD's L2)                                   */
-  OTFS_NO_LDS_RESIDENT = 1u << 5 /* solve small one-tile frames with their vectors in memory
+  OTFS_NO_LDS_RESIDENT = 1u << 5, /* solve small one-tile frames with their vectors in memory
                                     too (default: in LDS when 5*M*N*8 bytes fit 40 KiB)      */
+  OTFS_SPLIT_DIRECTION = 1u << 6  /* always form the direction p = c + beta p in a pass of its
+                                    own before the H pass.  By default, when every frame
+                                    gathered straight from memory has P <= 8 (and neither the
+                                    stored-D mode nor the refresh is on), the H pass forms it
+                                    inside its gathers instead; the results are identical  */
 };
 
 /* CG options (Algorithm 1 with a per-frame stop test added in front of the direction
@@ -164,6 +169,7 @@ typedef struct {
   int32_t staged_frames;    /* frames whose gathers are staged through LDS windows          */
   int32_t resident_frames;  /* one-workgroup frames solved with all CG vectors in LDS       */
   int32_t launches;         /* fused-kernel launches per solve: one per kind of frame        */
+  int32_t fused_direction_frames; /* frames whose H pass forms the direction in its gathers */
 } otfs_plan_info_t;
 otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
 

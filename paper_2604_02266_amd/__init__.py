@@ -30,6 +30,7 @@ USE_GRAPH = 1 << 2
 TIME_KERNEL = 1 << 3
 AGENT_BARRIER = 1 << 4
 NO_LDS_RESIDENT = 1 << 5
+SPLIT_DIRECTION = 1 << 6
 (FRAME_RUNNING, FRAME_CONVERGED, FRAME_CAPPED, FRAME_NONFINITE, FRAME_BREAKDOWN, FRAME_TIMEOUT,
  FRAME_DRYRUN) = range(7)
 
@@ -64,7 +65,8 @@ class PlanInfo(ctypes.Structure):
                 ("max_paths", ctypes.c_int32), ("tile_elems", ctypes.c_int32),
                 ("groups", ctypes.c_int32), ("xcd_local", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("staged_frames", ctypes.c_int32),
-                ("resident_frames", ctypes.c_int32), ("launches", ctypes.c_int32)]
+                ("resident_frames", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("fused_direction_frames", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):

@@ -30,8 +30,10 @@ namespace {
 // ---------------------------------------------------------------------------------------
 // small complex helpers
 // ---------------------------------------------------------------------------------------
+// explicit fused multiply-adds: the rounding does not depend on how the compiler would
+// contract the expression in each kernel, so every kernel forms the same coefficients
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ void cmacf(float2& acc, float2 c, float2 v) {
   acc.x = fmaf(c.x, v.x, acc.x);
@@ -40,7 +42,7 @@ __device__ __forceinline__ void cmacf(float2& acc, float2 c, float2 v) {
   acc.y = fmaf(c.y, v.x, acc.y);
 }
 __device__ __forceinline__ double2 cmuld(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ void cmacd(double2& acc, double2 c, double2 v) {
   acc.x = fma(c.x, v.x, acc.x);
@@ -255,7 +257,7 @@ struct OutA {       // t = H p', p_new = c + beta p_old, x += alpha p_old (defer
     return Pre{xp ? x.ld(q) : make_float2(0.f, 0.f)};
   }
   __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre& pr, const float2* own) const {
-    t.st(q, v);
+    t.st(q, v);   // default cache policy: measured faster here than the streamed one
     pn.st(q, axpyf(beta, own[1], own[0]));
     if (xp) x.st(q, axpyf(alpha, own[1], pr.x));
   }
@@ -528,6 +530,14 @@ constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight togethe
 #define OTFS_PATHS_GENERAL 2
 #endif
 constexpr int kPathsGeneral = OTFS_PATHS_GENERAL;   // the same where rows are per lane
+#ifndef OTFS_FD_ROWS
+#define OTFS_FD_ROWS 4
+#endif
+#ifndef OTFS_FD_PATHS
+#define OTFS_FD_PATHS 1
+#endif
+constexpr int kFdRows = OTFS_FD_ROWS;     // H pass forming the direction in its gathers
+constexpr int kFdPaths = OTFS_FD_PATHS;
 #ifndef OTFS_FUSED_MIN_WAVES
 #define OTFS_FUSED_MIN_WAVES 4
 #endif
@@ -827,7 +837,8 @@ __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, 
 // geometry), gathered straight from memory otherwise.  out.pre(q) issues the loads output q needs
 // besides the source; out.put(q, v, pre, own) receives it with own[] = the source
 // vectors' elements at q.
-template <bool ADJ, bool STORED, bool STAGED, int R = kRows, class Src, class Out>
+template <bool ADJ, bool STORED, bool STAGED, int R = kRows, int UP = kPaths, class Src,
+          class Out>
 __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, float2* lds,
                                            const Src& src, const Out& out) {
   if constexpr (STAGED && !STORED && Src::kStageable) {
@@ -837,7 +848,7 @@ __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, fl
       typename Out::Pre pre;
       float2 own[Src::kNV];
     };
-    band_apply<R, kPaths, ADJ, STORED>(
+    band_apply<R, UP, ADJ, STORED>(
         F, lb, le, src,
         [&](uint32_t u) {
           PreOwn po;
@@ -984,7 +995,8 @@ struct LaunchCtx {
   int xcd_local;     // barrier coherence mode (see frame_barrier)
 };
 
-template <bool STORED, bool REFRESH, bool STAGED>
+// FDIR: the H pass forms p' = c + beta p inside its gathers (direct-fd kind).
+template <bool STORED, bool REFRESH, bool STAGED, bool FDIR = false>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                         const LaunchCtx& L, float* red, double* redd, int* sflag, float2* lds) {
   // the bf16 table reads and the FP64 refresh leave fewer registers for gathers in flight
@@ -1075,6 +1087,12 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       // c and the old p are staged together; p' = c + beta p is formed from the windows
       apply_band<false, STORED, true, RR>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
                                       OutA{tv, pnv, xv, al, be, xp});
+    } else if constexpr (FDIR) {
+      // p' = c + beta p_old formed from both vectors at every gather (two loads each: fewer
+      // paths in flight), stored once for the own rows with x += alpha p_old
+      apply_band<false, STORED, false, kFdRows, kFdPaths>(F, lb, le, lds,
+                                                         SrcDir{cv.r, pov.r, be},
+                                                         OutA{tv, pnv, xv, al, be, xp});
     } else {
       // A1: p' = c + beta p_old and x += alpha p_old over the band, stored once
       for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * kElemChunk) {
@@ -1390,7 +1408,8 @@ __global__ __launch_bounds__(kBlock, OTFS_FUSED_MIN_WAVES) void k_cg_fused(const
     if constexpr (KIND == kKindResident)
       cg_item_resident(F, budget, B, red, stage_lds);
     else
-      cg_item<STORED, REFRESH, KIND == kKindStaged>(F, wi, budget, B, L, red, redd, &sflag,
+      cg_item<STORED, REFRESH, KIND == kKindStaged, KIND == kKindDirectFD>(F, wi, budget, B, L,
+                                                                          red, redd, &sflag,
                                                     stage_lds);
     __syncthreads();
   }
@@ -1708,6 +1727,9 @@ static void launch_fused_t(const FrameDev* frames, const WorkItem* items, const 
 // D nor (resident) the refresh, which the host guarantees
 static const void* fused_fn(int kind, bool stored, bool refresh) {
   if (kind == kKindResident) return reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindResident>);
+  if (kind == kKindDirectFD)
+    return (stored || refresh) ? nullptr
+                               : reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindDirectFD>);
   if (kind == kKindStaged)
     return refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true, kKindStaged>)
                    : reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindStaged>);
@@ -1726,6 +1748,9 @@ hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* 
   LaunchCtx L{abort_flag, wallclock_timeout_ticks(), xcd_local ? 1 : 0};
   if (kind == kKindResident) {
     launch_fused_t<false, false, kKindResident>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+  } else if (kind == kKindDirectFD) {
+    if (stored || refresh) return hipErrorInvalidValue;
+    launch_fused_t<false, false, kKindDirectFD>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
   } else if (kind == kKindStaged) {
     if (refresh) launch_fused_t<false, true, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
     else launch_fused_t<false, false, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
@@ -1741,7 +1766,7 @@ hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* 
 
 int fused_blocks_per_cu(int kind, bool stored, bool refresh, int lds_bytes) {
   int n = 0;
-  if (kind == kKindDirect) lds_bytes = 0;
+  if (kind == kKindDirect || kind == kKindDirectFD) lds_bytes = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_fn(kind, stored, refresh), kBlock,
                                                    lds_bytes) != hipSuccess)
     n = 0;

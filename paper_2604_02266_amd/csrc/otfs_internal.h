@@ -127,7 +127,10 @@ hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abor
 // Launch kinds of the fused kernel, each its own instantiation: frames gathering straight
 // from memory, frames staging gather windows in LDS, one-workgroup frames with the whole
 // solve in LDS.
-constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKinds = 3;
+// direct-fd: direct frames whose H pass forms the direction inside its gathers (batches
+// whose direct frames all have P <= kFusedDirMaxPaths)
+constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKindDirectFD = 3, kKinds = 4;
+constexpr int kFusedDirMaxPaths = 8;
 hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,

@@ -50,7 +50,7 @@ otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out) {
     return fail(OTFS_E_INVAL, "rel_tol must be finite and >= 0");
   if (d.refresh_every < 0) return fail(OTFS_E_INVAL, "refresh_every must be >= 0");
   const uint32_t known = OTFS_D_STORED_BF16 | OTFS_Y_BF16 | OTFS_USE_GRAPH | OTFS_TIME_KERNEL |
-                         OTFS_AGENT_BARRIER | OTFS_NO_LDS_RESIDENT;
+                         OTFS_AGENT_BARRIER | OTFS_NO_LDS_RESIDENT | OTFS_SPLIT_DIRECTION;
   if (d.flags & ~known) return fail(OTFS_E_INVAL, "unknown flag bits 0x%x", d.flags & ~known);
   *out = d;
   return OTFS_OK;
@@ -180,18 +180,28 @@ int frame_lds_bytes(const HostFrame& f, const FrameDev& geo) {
 
 otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vector<FrameDev>& geo,
                           const std::vector<int>& tile_base, const std::vector<int>& tiles,
-                          bool stored, bool refresh, int cus, int cap_override,
+                          bool stored, bool refresh, bool split_dir, int cus, int cap_override,
                           const XcdInfo& xi, bool agent, std::vector<int32_t>& qitems,
                           std::vector<int2>& qrange, std::vector<KindLaunch>& out) {
   qitems.clear();
   qrange.assign((size_t)kKinds * kMaxGroups, make_int2(0, 0));
   out.clear();
+  // The H pass forms the direction inside its gathers when the direct frames have few
+  // paths: the gathers then read two vectors, which costs more than the separate
+  // direction pass saves once P is large (measured on the 16-path batches).
+  bool fdir = !stored && !refresh && !split_dir;
+  for (size_t f = 0; f < frames.size(); ++f)
+    if (frame_kind(geo[f]) == kKindDirect && frames[f].P > kFusedDirMaxPaths) fdir = false;
+  auto kind_of = [&](size_t f) {
+    const int k = frame_kind(geo[f]);
+    return (k == kKindDirect && fdir) ? kKindDirectFD : k;
+  };
   for (int kind = 0; kind < kKinds; ++kind) {
     std::vector<HostFrame> fs;
     std::vector<int> tb, tl;
     int lds = 0;
     for (size_t f = 0; f < frames.size(); ++f) {
-      if (frame_kind(geo[f]) != kind) continue;
+      if (kind_of(f) != kind) continue;
       fs.push_back(frames[f]);
       tb.push_back(tile_base[f]);
       tl.push_back(tiles[f]);
@@ -203,6 +213,7 @@ otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vecto
     if (cap_override > 0) cap = std::min(cap, cap_override);
     KindLaunch L;
     L.kind = kind;
+    L.nframes = (int)fs.size();
     L.lds_bytes = lds;
     L.qbase = kind * kMaxGroups;
     std::vector<int32_t> qi;
@@ -532,6 +543,9 @@ extern "C" otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t*
     info->lds_bytes = std::max(info->lds_bytes, L.lds_bytes);
   }
   info->launches = (int32_t)plan->launches.size();
+  info->fused_direction_frames = 0;
+  for (const KindLaunch& L : plan->launches)
+    if (L.kind == kKindDirectFD) info->fused_direction_frames += L.nframes;
   info->staged_frames = 0;
   info->resident_frames = 0;
   for (const FrameDev& d : plan->h_frames) {
@@ -601,7 +615,8 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   if (pst != OTFS_OK) return pst;
   pst = plan_launches(plan->frames, geo, plan->tile_base, plan->tiles,
                       (plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->opts.refresh_every > 0,
-                      cus, plan->max_grid_req, xi, (plan->opts.flags & OTFS_AGENT_BARRIER) != 0,
+                      (plan->opts.flags & OTFS_SPLIT_DIRECTION) != 0, cus, plan->max_grid_req, xi,
+                      (plan->opts.flags & OTFS_AGENT_BARRIER) != 0,
                       plan->qitems, plan->qrange, plan->launches);
   if (pst != OTFS_OK) return pst;
 

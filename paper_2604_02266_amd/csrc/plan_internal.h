@@ -81,6 +81,7 @@ constexpr int kProbeBlocks = 1024;
 // queue ranges and cursors of launch kind k live at k * kMaxGroups.
 struct KindLaunch {
   int kind = kKindDirect;
+  int nframes = 0;          // frames of this kind
   int grid = 0;
   int ngroups = 1;
   bool xcd_local = false;
@@ -92,11 +93,12 @@ int frame_kind(const FrameDev& geo);
 int frame_lds_bytes(const HostFrame& f, const FrameDev& geo);
 // Work queues and launch shapes of every kind present among the frames (frames listed by
 // index into tile_base / tiles; item indices are tile_base[f] + t).  cap_override > 0
-// caps the workgroups of each launch.  Fails if a frame has more tiles than can be
-// resident at once.
+// caps the workgroups of each launch.  Direct frames run the direct-fd kind when every
+// one of them has P <= kFusedDirMaxPaths, neither stored nor refresh is on, and split_dir
+// is false.  Fails if a frame has more tiles than can be resident at once.
 otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vector<FrameDev>& geo,
                           const std::vector<int>& tile_base, const std::vector<int>& tiles,
-                          bool stored, bool refresh, int cus, int cap_override,
+                          bool stored, bool refresh, bool split_dir, int cus, int cap_override,
                           const XcdInfo& xi, bool agent, std::vector<int32_t>& qitems,
                           std::vector<int2>& qrange, std::vector<KindLaunch>& out);
 

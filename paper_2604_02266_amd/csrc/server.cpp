@@ -313,8 +313,8 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   std::vector<FrameDev> geo(n);
   for (int i = 0; i < n; ++i) geo[i] = act[i]->geo;
   std::vector<KindLaunch> launches;
-  if (plan_launches(frames, geo, tile_base, tiles, false, S->opts.refresh_every > 0, S->cus, 0,
-                    S->xcd, (S->opts.flags & OTFS_AGENT_BARRIER) != 0, qitems, qrange,
+  if (plan_launches(frames, geo, tile_base, tiles, false, S->opts.refresh_every > 0,
+                    (S->opts.flags & OTFS_SPLIT_DIRECTION) != 0, S->cus, 0, S->xcd, (S->opts.flags & OTFS_AGENT_BARRIER) != 0, qitems, qrange,
                     launches) != OTFS_OK) {
     set_failed(S, otfs_last_error());
     return false;

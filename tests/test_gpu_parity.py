@@ -203,6 +203,33 @@ def test_cg_wide_doppler_neighbour_waits(otfs, tile_elems, agent):
     _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
 
 
+@pytest.mark.parametrize("tile_elems", [0, 700, 200])
+def test_cg_direction_in_gathers_identical_to_split(otfs, tile_elems):
+    # Batches whose frames all have P <= 8 form p' = c + beta p inside the H pass's gathers;
+    # the separate direction pass computes the same values in the same order, so the two
+    # forms agree bit for bit (and both with the oracle).
+    frames = _mixed_frames(41 + tile_elems, 7, [(128, 32), (64, 16), (100, 30), (256, 16)],
+                           (1, 8), 12, 6)
+    ops, xs, y = oracle_batch(frames)
+    say("cg direction in gathers", "tile_elems", tile_elems,
+        [(f.spec.M, f.spec.N, f.spec.P) for f in frames])
+    fd = otfs.Plan([f.spec for f in frames], tile_elems=tile_elems, flags=otfs.NO_LDS_RESIDENT)
+    sp = otfs.Plan([f.spec for f in frames], tile_elems=tile_elems,
+                   flags=otfs.NO_LDS_RESIDENT | otfs.SPLIT_DIRECTION)
+    assert fd.info().fused_direction_frames == len(frames)
+    assert sp.info().fused_direction_frames == 0
+    out_fd = _run(otfs, fd, y)
+    out_sp = _run(otfs, sp, y)
+    _cg_check(out_fd, frames, ops, y, NMSE_TOL, "direction in gathers")
+    assert np.array_equal(out_fd[0], out_sp[0])
+    assert np.array_equal(out_fd[1], out_sp[1])
+    assert np.array_equal(out_fd[2]["iters"], out_sp[2]["iters"])
+    # one frame with more paths sends the whole batch to the split form
+    more = frames + _mixed_frames(43, 1, [(64, 16)], (9, 9), 12, 6)
+    assert otfs.Plan([f.spec for f in more], tile_elems=tile_elems,
+                     flags=otfs.NO_LDS_RESIDENT).info().fused_direction_frames == 0
+
+
 def test_cg_fresh_plans_reusing_memory(otfs):
     # Regression: each new plan gets memory that earlier plans (other frame-to-XCD
     # assignments) used; stale cache lines must not leak into the solve.

@@ -65,6 +65,12 @@ def test_invalid_options_are_rejected():
         with pytest.raises(otfs.OtfsError) as ei:
             _plan(fr, **kw)
         assert ei.value.status == otfs.E_INVAL and msg in str(ei.value)
+    # every documented flag is accepted
+    for f in (otfs.NO_LDS_RESIDENT, otfs.SPLIT_DIRECTION, otfs.AGENT_BARRIER,
+              otfs.TIME_KERNEL):
+        _plan(fr, flags=f)
+    with pytest.raises(otfs.OtfsError):
+        _plan(fr, flags=1 << 7)
 
 
 def test_empty_batch_and_unbound_use(L):
