@@ -28,7 +28,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int kServeTileElems = 4096;   // frame-local tiling rule (independent of the mix)
+#ifndef OTFS_SERVE_TILE
+#define OTFS_SERVE_TILE 8192
+#endif
+constexpr int kServeTileElems = OTFS_SERVE_TILE;   // frame-local tiling rule (independent of the mix)
 constexpr int kMaxActive = 2048;        // frames admitted at once
 constexpr int kMaxItems = 65536;        // tiles of the admitted frames
 constexpr size_t kAlign = 256;
@@ -157,6 +160,12 @@ struct Request {
   std::vector<WorkItem> items;   // frame-local tiles (frame index patched per step)
   FrameDev dev{};
   FrameDev geo{};                // staging geometry
+  // tables and initial state, built at submission; they stay alive until the frame is
+  // done, so the admission copies need no synchronisation
+  std::vector<float2> r32, w32;
+  std::vector<double2> r64, w64;   // refresh only
+  std::vector<int2> paths;
+  FrameState st0{};
   // results
   std::vector<float2> xhat;
   std::vector<uint8_t> sym;
@@ -206,19 +215,33 @@ bool frame_fits_ever(otfs_server* S, const SlotLayout& L) {
   return L.total <= S->pool_bytes - S->slot_base;
 }
 
-// Host-side tables and descriptor of an admitted frame (device pointers into its slot).
-void build_frame_dev(otfs_server* S, Request* r, std::vector<double2>& r64,
-                     std::vector<double2>& w64, std::vector<int2>& paths) {
+// Host-side tables of a frame (FP64 phases, FP32 copies for the kernels) and its initial
+// state, built on the submitting thread.
+void build_tables(bool refresh, Request* r) {
+  const HostFrame& f = r->hf;
+  std::vector<double2> r64, w64;
+  for (int p = 0; p < f.P; ++p) delay_ramp(f, p, r64);
+  wrap_factors(f, w64);
+  r->paths.clear();
+  for (int p = 0; p < f.P; ++p) r->paths.push_back(make_int2(f.tau[p], f.nu[p]));
+  r->r32.resize(r64.size());
+  r->w32.resize(w64.size());
+  for (size_t i = 0; i < r64.size(); ++i) r->r32[i] = make_float2((float)r64[i].x, (float)r64[i].y);
+  for (size_t i = 0; i < w64.size(); ++i) r->w32[i] = make_float2((float)w64[i].x, (float)w64[i].y);
+  if (refresh) {
+    r->r64 = std::move(r64);
+    r->w64 = std::move(w64);
+  }
+  r->st0 = FrameState{};
+  r->st0.status = OTFS_FRAME_RUNNING;
+}
+
+// Descriptor of an admitted frame (device pointers into its slot).
+void build_frame_dev(otfs_server* S, Request* r) {
   const HostFrame& f = r->hf;
   char* base = S->pool + S->slot_base + r->slot_off;
   const SlotLayout& L = r->L;
   const bool refresh = S->opts.refresh_every > 0;
-  r64.clear();
-  w64.clear();
-  paths.clear();
-  for (int p = 0; p < f.P; ++p) delay_ramp(f, p, r64);
-  wrap_factors(f, w64);
-  for (int p = 0; p < f.P; ++p) paths.push_back(make_int2(f.tau[p], f.nu[p]));
   FrameDev& d = r->dev;
   std::memset(&d, 0, sizeof d);
   d.y = base + L.y;
@@ -252,15 +275,10 @@ void set_failed(otfs_server* S, const std::string& msg) {
 }
 
 // ---- GPU executor steps (scheduler thread) ----------------------------------------------
+// Enqueue the copies of an admitted frame's inputs into its slot (stream order puts them
+// before the next step; the sources live in the request until it is done).
 bool gpu_admit(otfs_server* S, Request* r) {
-  std::vector<double2> r64, w64;
-  std::vector<int2> paths;
-  build_frame_dev(S, r, r64, w64, paths);
-  std::vector<float2> r32(r64.size()), w32(w64.size());
-  for (size_t i = 0; i < r64.size(); ++i) r32[i] = make_float2((float)r64[i].x, (float)r64[i].y);
-  for (size_t i = 0; i < w64.size(); ++i) w32[i] = make_float2((float)w64[i].x, (float)w64[i].y);
-  FrameState st{};
-  st.status = OTFS_FRAME_RUNNING;
+  build_frame_dev(S, r);
   char* base = S->pool + S->slot_base + r->slot_off;
   hipError_t e = hipSuccess;
   auto up = [&](size_t off, const void* src, size_t bytes) {
@@ -268,15 +286,14 @@ bool gpu_admit(otfs_server* S, Request* r) {
       e = hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, S->s);
   };
   up(r->L.y, r->y.data(), r->y.size() * sizeof(float2));
-  up(r->L.rtab, r32.data(), r32.size() * sizeof(float2));
-  up(r->L.wtab, w32.data(), w32.size() * sizeof(float2));
+  up(r->L.rtab, r->r32.data(), r->r32.size() * sizeof(float2));
+  up(r->L.wtab, r->w32.data(), r->w32.size() * sizeof(float2));
   if (S->opts.refresh_every > 0) {
-    up(r->L.rtab64, r64.data(), r64.size() * sizeof(double2));
-    up(r->L.wtab64, w64.data(), w64.size() * sizeof(double2));
+    up(r->L.rtab64, r->r64.data(), r->r64.size() * sizeof(double2));
+    up(r->L.wtab64, r->w64.data(), r->w64.size() * sizeof(double2));
   }
-  up(r->L.paths, paths.data(), paths.size() * sizeof(int2));
-  up(r->L.st, &st, sizeof st);
-  if (e == hipSuccess) e = hipStreamSynchronize(S->s);   // host sources go out of scope
+  up(r->L.paths, r->paths.data(), r->paths.size() * sizeof(int2));
+  up(r->L.st, &r->st0, sizeof r->st0);
   if (e != hipSuccess) {
     set_failed(S, std::string("admission copy: ") + hipGetErrorString(e));
     return false;
@@ -355,18 +372,23 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   return true;
 }
 
-bool gpu_fetch(otfs_server* S, Request* r) {
-  const size_t E = (size_t)r->hf.M * r->hf.N;
-  r->xhat.resize(E);
-  char* base = S->pool + S->slot_base + r->slot_off;
-  hipError_t e = hipMemcpyAsync(r->xhat.data(), base + r->L.x, E * sizeof(float2),
-                                hipMemcpyDeviceToHost, S->s);
-  if (r->hf.qam > 0) {
-    r->sym.resize(E);
+// Results of the frames finished in a step: every copy enqueued, one synchronisation.
+bool gpu_fetch(otfs_server* S, const std::vector<Request*>& done) {
+  hipError_t e = hipSuccess;
+  for (Request* r : done) {
+    const size_t E = (size_t)r->hf.M * r->hf.N;
+    r->xhat.resize(E);
+    char* base = S->pool + S->slot_base + r->slot_off;
     if (e == hipSuccess)
-      e = hipMemcpyAsync(r->sym.data(), base + r->L.sym, E, hipMemcpyDeviceToHost, S->s);
+      e = hipMemcpyAsync(r->xhat.data(), base + r->L.x, E * sizeof(float2),
+                         hipMemcpyDeviceToHost, S->s);
+    if (r->hf.qam > 0) {
+      r->sym.resize(E);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(r->sym.data(), base + r->L.sym, E, hipMemcpyDeviceToHost, S->s);
+    }
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(S->s);
+  if (e == hipSuccess && !done.empty()) e = hipStreamSynchronize(S->s);
   if (e != hipSuccess) {
     set_failed(S, std::string("result copy: ") + hipGetErrorString(e));
     return false;
@@ -459,14 +481,14 @@ void scheduler(otfs_server* S) {
         act[i]->stats = st[i];
         done.push_back(act[i]);
       }
-    for (Request* r : done) {
-      if (S->dry) {
+    if (S->dry) {
+      for (Request* r : done) {
         const size_t E = (size_t)r->hf.M * r->hf.N;
         r->xhat.assign(E, make_float2(0.f, 0.f));
         if (r->hf.qam > 0) r->sym.assign(E, 0);
-      } else if (!gpu_fetch(S, r)) {
-        return;
       }
+    } else if (!gpu_fetch(S, done)) {
+      return;
     }
     {
       std::lock_guard<std::mutex> g(S->mu);
@@ -567,8 +589,9 @@ extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* fram
   if (!frame_fits_ever(S, r->L))
     return fail(OTFS_E_BUDGET, "frame state needs %zu bytes, the pool has %zu for frames",
                 r->L.total, S->pool_bytes - S->slot_base);
-  r->y.resize(E);
-  std::memcpy(r->y.data(), y_host, E * sizeof(float2));
+  const float2* yh = static_cast<const float2*>(y_host);
+  r->y.assign(yh, yh + E);
+  build_tables(S->opts.refresh_every > 0, r.get());
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> g(S->mu);
   if (S->failed) return fail(OTFS_E_DEVICE, "server failed: %s", S->fail_msg.c_str());
