@@ -1115,7 +1115,10 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       }
       if (!halo(rd_h)) return fail_timeout();
       // A2: t = H p' (one load per gather)
-      apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<kNtT>{tv});
+      if (kNtT && F.stream_t)
+        apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<true>{tv});
+      else
+        apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<false>{tv});
     }
     if (!halo(rd_hh)) return fail_timeout();
 

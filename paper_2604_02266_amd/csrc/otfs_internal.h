@@ -74,6 +74,9 @@ struct FrameDev {
   // 1: a one-workgroup frame whose five CG vectors (x, c, p, t, a) live in LDS for the
   // whole solve (y read once, x written once)
   int32_t resident;
+  // 1: the H pass of the split form stores t with the non-temporal policy (large frames,
+  // whose vectors overflow L2 anyway); smaller frames keep t in L2 for the H^H gathers
+  int32_t stream_t;
 };
 
 // One workgroup's share of one frame: Doppler rows [l_begin, l_end), all delay columns.
@@ -131,6 +134,8 @@ hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abor
 // whose direct frames all have P <= kFusedDirMaxPaths)
 constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKindDirectFD = 3, kKinds = 4;
 constexpr int kFusedDirMaxPaths = 8;
+// frames of at least this many elements stream t (see FrameDev::stream_t)
+constexpr int64_t kStreamTElems = 131072;
 hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,

@@ -162,6 +162,7 @@ void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const 
   d->nu_lo = geo.nu_lo;
   d->nu_hi = geo.nu_hi;
   d->resident = geo.resident;
+  d->stream_t = (int64_t)fr.M * fr.N >= kStreamTElems ? 1 : 0;
 }
 
 int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opts& o,
