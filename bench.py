@@ -173,7 +173,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU: frames are independent, so the path shards by "
-              "splitting the frame list across GPUs with no exchange (see DESIGN.md); only "
+              "splitting the frame list across GPUs with no exchange; only "
               "the one-GPU figure is measured.", file=sys.stderr)
         sys.exit(2)
 

@@ -19,7 +19,7 @@ directly, slowly and without fusion:
 * the point-pilot channel estimate (Eq. heff) and its Hadamard form (Eq. heff_exp,
   Eq. heff_hadamard).
 
-Conventions (readings of the paper, each listed in the design doc):
+Conventions (readings of the paper where it leaves a choice open):
 * A frame is X[k, l], delay bin k in [0, M), Doppler bin l in [0, N).  The vector form
   is q = l*M + k (Sec. IV-B indexes rows that way); Eq. Hdd's k'N + l' row index is
   re-indexed to it.

@@ -92,7 +92,7 @@ def lib() -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first "
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2604_02266_amd/build_lib.py first "
                            "(there is no fallback implementation)")
     L = ctypes.CDLL(LIB_PATH)
     st = ctypes.c_int
