@@ -1046,7 +1046,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     }
   };
 
-  // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line) ----
+  // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (the initialisation of Algorithm 1) ----
   if (!s.init) {
     float acc = 0.f;
     const OutInit out{cv, cvec(F.p0, E), xv, &acc};
@@ -1265,7 +1265,7 @@ __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, 
   };
 
   if (!s.init) {
-    // b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (Algorithm 1, first line)
+    // b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 (the initialisation of Algorithm 1)
     float acc = 0.f;
     auto sink = [&](int q, float2 v) {
       cs.st(q, v);
