@@ -91,6 +91,27 @@ def test_server_alone_equals_in_mix(otfs):
     assert alone[2].iters == mix[2].iters and alone[2].status == mix[2].status
 
 
+def test_server_kind_switch_keeps_bits(otfs):
+    # A frame with few paths runs the kind that forms the direction inside the H gathers
+    # while it is alone; next to a 12-path frame the steps use the split form. Both forms
+    # compute the same values in the same order, so its result is the same bits.
+    frames = _frames(14, 1, shapes=((128, 32),))
+    rng = np.random.default_rng(15)
+    frames.append(W.small_frame(rng, 256, 16, 12, (0, 12), (-6, 6), qam=16, snr_db=20.0,
+                                max_iters=MAX_ITERS, tol=TOL))
+    ys = [np.asarray(O.received_frame(fr)[2], np.complex64) for fr in frames]
+    say("server kind switch", [(f.spec.M, f.spec.N, f.spec.P) for f in frames])
+    with otfs.Server(256 << 20, max_iters=MAX_ITERS, rel_tol=TOL, step_iters=4) as srv:
+        alone = _serve(srv, frames[:1], ys[:1])[0]
+        mix = _serve(srv, frames, ys)
+    assert np.array_equal(alone[0].view(np.uint32), mix[0][0].view(np.uint32))
+    assert np.array_equal(alone[1], mix[0][1])
+    assert alone[2].iters == mix[0][2].iters
+    xr, _, _ = O.cg_lmmse(ys[1].astype(np.complex128), O.received_frame(frames[1])[0],
+                          frames[1].spec.lam, MAX_ITERS, TOL)
+    assert O.nmse(mix[1][0], xr) <= NMSE_TOL
+
+
 def test_server_under_pool_pressure(otfs):
     frames = _frames(13, 8, shapes=((128, 32),))
     ys = [np.asarray(O.received_frame(fr)[2], np.complex64) for fr in frames]
