@@ -155,6 +155,73 @@ def serving_leg(otfs, W, workload, torch, step_iters=5, seed=1004):
             "note": "host buffers in and out (submit copies y, poll copies x_hat)"}
 
 
+def serving_sweep(otfs, W, workload, torch, rates, nframes, pool_bytes, step_iters=5,
+                  seed=1004):
+    """Poisson arrival streams of `nframes` frames (the workload's frames, cycled) at each
+    offered rate: achieved offered rate, completed symbols/s and p50 / p99 / p99.9 latency
+    from submit to completion.  Results are polled while frames are being submitted, so
+    host memory stays bounded."""
+    import numpy as np
+    from collections import deque
+    frames = list(W.iter_frames(workload))
+    specs = [f.spec for f in frames]
+    sp0 = specs[0]
+    plan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol)
+    offs = otfs.frame_offsets(specs)
+    dev = torch.device("cuda")
+    sym = torch.from_numpy(np.concatenate([f.sym for f in frames])).to(dev)
+    x = torch.empty(plan.total_elems, dtype=torch.complex64, device=dev)
+    for i, f in enumerate(frames):
+        x[offs[i]:offs[i + 1]] = qam_points_torch(torch, sym[offs[i]:offs[i + 1]], f.spec.qam)
+    noise = torch.from_numpy(np.concatenate([f.noise for f in frames]).astype(np.complex64))
+    y = (plan.apply_H(x).cpu() + noise).numpy()
+    del plan, x, sym
+    ys = [y[offs[i]:offs[i + 1]] for i in range(len(specs))]
+    rng = np.random.default_rng(seed)
+    out = []
+    with otfs.Server(pool_bytes, max_iters=sp0.max_iters, rel_tol=sp0.tol,
+                     step_iters=step_iters) as srv:
+        warm = [srv.submit(sp, yy) for sp, yy in zip(specs, ys)]      # warm-up
+        for tk, sp in zip(warm, specs):
+            srv.wait(tk, sp, timeout=120.0)
+        for rate in rates:
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, nframes))
+            arrivals -= arrivals[0]
+            pending, lat, syms = deque(), [], 0
+            t0 = time.perf_counter()
+            for n in range(nframes):
+                k = n % len(specs)
+                wait = arrivals[n] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                pending.append((srv.submit(specs[k], ys[k]), k))
+                while pending:
+                    r = srv.poll(pending[0][0], specs[pending[0][1]])
+                    if r is None:
+                        break
+                    lat.append(r[3])
+                    syms += specs[pending[0][1]].E
+                    pending.popleft()
+            t_sub = time.perf_counter() - t0
+            for tk, k in pending:
+                r = srv.wait(tk, specs[k], timeout=300.0)
+                lat.append(r[3])
+                syms += specs[k].E
+            wall = time.perf_counter() - t0
+            lat = np.array(lat) * 1e3
+            out.append({"offered_frames_per_s": rate,
+                        "achieved_offered_frames_per_s": nframes / t_sub if t_sub > 0 else None,
+                        "completed_frames_per_s": nframes / wall,
+                        "value": syms / wall, "unit": "symbols/s",
+                        "latency_ms_p50": float(np.percentile(lat, 50)),
+                        "latency_ms_p99": float(np.percentile(lat, 99)),
+                        "latency_ms_p999": float(np.percentile(lat, 99.9))})
+            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
+    return {"workload": workload, "frames_per_point": nframes, "step_iters": step_iters,
+            "pool_bytes": pool_bytes, "points": out,
+            "note": "host buffers in and out (submit copies y, poll copies x_hat)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +233,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--serving-workload", default="serving_uneven")
+    ap.add_argument("--serving-sweep", default="", metavar="RATES",
+                    help="instead of the benchmark, sweep the serving loop over Poisson "
+                         "arrival rates (comma-separated frames/s) and print that JSON line")
+    ap.add_argument("--sweep-frames", type=int, default=10000)
+    ap.add_argument("--sweep-pool-gib", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (reference "
                          "for hardware byte counters)")
@@ -182,6 +254,13 @@ def main():
 
     import paper_2604_02266_amd as otfs
     import workloads as W
+
+    if args.serving_sweep:
+        rates = [float(r) for r in args.serving_sweep.split(",") if r]
+        res = serving_sweep(otfs, W, args.serving_workload, torch, rates, args.sweep_frames,
+                            args.sweep_pool_gib << 30)
+        print(json.dumps({"serving_sweep": res}))
+        return
 
     frames = list(W.iter_frames(args.workload))
     specs = [f.spec for f in frames]
