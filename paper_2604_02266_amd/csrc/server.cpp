@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -18,6 +19,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "otfs_internal.h"
@@ -147,10 +149,83 @@ CtrlLayout ctrl_layout() {
   return C;
 }
 
+// Host staging buffers of a server, kept per size and reused (frame shapes repeat):
+// page-locked memory on a device, so that the copies to and from the pool are direct DMA
+// instead of going through the driver's pageable staging; plain memory for the dry run,
+// or when page-locking fails.
+class HostPool {
+ public:
+  explicit HostPool(bool pinned) : pinned_(pinned) {}
+  HostPool(const HostPool&) = delete;
+  HostPool& operator=(const HostPool&) = delete;
+  ~HostPool() {
+    for (auto& kv : free_)
+      for (void* p : kv.second) {
+        if (locked_.count(p)) (void)hipHostFree(p);
+        else std::free(p);
+      }
+  }
+  void* get(size_t n) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      auto it = free_.find(n);
+      if (it != free_.end() && !it->second.empty()) {
+        void* p = it->second.back();
+        it->second.pop_back();
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (pinned_) {
+      if (hipHostMalloc(&p, n, hipHostMallocPortable) == hipSuccess && p) {
+        std::lock_guard<std::mutex> g(mu_);
+        locked_.insert(p);
+        return p;
+      }
+      (void)hipGetLastError();   // do not leave the failure for a later status check
+    }
+    return std::malloc(n);
+  }
+  void put(void* p, size_t n) {
+    std::lock_guard<std::mutex> g(mu_);
+    free_[n].push_back(p);
+  }
+
+ private:
+  bool pinned_;
+  std::mutex mu_;
+  std::unordered_map<size_t, std::vector<void*>> free_;
+  std::unordered_set<void*> locked_;
+};
+
+// One buffer from a HostPool, returned to it when reset or destroyed.
+struct HostBuf {
+  std::shared_ptr<HostPool> pool;
+  void* p = nullptr;
+  size_t n = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() { reset(); }
+  void reset() {
+    if (p) pool->put(p, n);
+    p = nullptr;
+    n = 0;
+  }
+  bool take(const std::shared_ptr<HostPool>& pl, size_t bytes) {
+    reset();
+    pool = pl;
+    p = pl->get(bytes);
+    n = p ? bytes : 0;
+    return p != nullptr;
+  }
+  bool empty() const { return p == nullptr; }
+};
+
 struct Request {
   uint64_t ticket = 0;
   HostFrame hf;
-  std::vector<float2> y;
+  HostBuf y;                     // the received frame (released at retirement)
   Clock::time_point t_submit, t_done;
   int state = 0;   // 0 queued, 1 admitted, 2 done
   // slot
@@ -167,8 +242,8 @@ struct Request {
   std::vector<int2> paths;
   FrameState st0{};
   // results
-  std::vector<float2> xhat;
-  std::vector<uint8_t> sym;
+  HostBuf xhat;                  // complex64, M*N
+  HostBuf sym;                   // u8, M*N (QAM frames)
   otfs_frame_stats stats{};
 };
 
@@ -191,6 +266,7 @@ struct otfs_server {
   std::condition_variable cv;
   std::deque<Request*> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+  std::shared_ptr<HostPool> hpool;
   std::vector<Request*> active;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -285,7 +361,7 @@ bool gpu_admit(otfs_server* S, Request* r) {
     if (e == hipSuccess && bytes)
       e = hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, S->s);
   };
-  up(r->L.y, r->y.data(), r->y.size() * sizeof(float2));
+  up(r->L.y, r->y.p, r->y.n);
   up(r->L.rtab, r->r32.data(), r->r32.size() * sizeof(float2));
   up(r->L.wtab, r->w32.data(), r->w32.size() * sizeof(float2));
   if (S->opts.refresh_every > 0) {
@@ -377,16 +453,17 @@ bool gpu_fetch(otfs_server* S, const std::vector<Request*>& done) {
   hipError_t e = hipSuccess;
   for (Request* r : done) {
     const size_t E = (size_t)r->hf.M * r->hf.N;
-    r->xhat.resize(E);
+    if (!r->xhat.take(S->hpool, E * sizeof(float2)) ||
+        (r->hf.qam > 0 && !r->sym.take(S->hpool, E))) {
+      set_failed(S, "result copy: out of host memory");
+      return false;
+    }
     char* base = S->pool + S->slot_base + r->slot_off;
     if (e == hipSuccess)
-      e = hipMemcpyAsync(r->xhat.data(), base + r->L.x, E * sizeof(float2),
-                         hipMemcpyDeviceToHost, S->s);
-    if (r->hf.qam > 0) {
-      r->sym.resize(E);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(r->sym.data(), base + r->L.sym, E, hipMemcpyDeviceToHost, S->s);
-    }
+      e = hipMemcpyAsync(r->xhat.p, base + r->L.x, E * sizeof(float2), hipMemcpyDeviceToHost,
+                         S->s);
+    if (r->hf.qam > 0 && e == hipSuccess)
+      e = hipMemcpyAsync(r->sym.p, base + r->L.sym, E, hipMemcpyDeviceToHost, S->s);
   }
   if (e == hipSuccess && !done.empty()) e = hipStreamSynchronize(S->s);
   if (e != hipSuccess) {
@@ -484,8 +561,8 @@ void scheduler(otfs_server* S) {
     if (S->dry) {
       for (Request* r : done) {
         const size_t E = (size_t)r->hf.M * r->hf.N;
-        r->xhat.assign(E, make_float2(0.f, 0.f));
-        if (r->hf.qam > 0) r->sym.assign(E, 0);
+        if (r->xhat.take(S->hpool, E * sizeof(float2))) std::memset(r->xhat.p, 0, r->xhat.n);
+        if (r->hf.qam > 0 && r->sym.take(S->hpool, E)) std::memset(r->sym.p, 0, r->sym.n);
       }
     } else if (!gpu_fetch(S, done)) {
       return;
@@ -496,6 +573,7 @@ void scheduler(otfs_server* S) {
       for (Request* r : done) {
         r->t_done = now;
         r->state = 2;
+        r->y.reset();   // its admission copy finished at an earlier step's synchronisation
         S->alloc.release(r->slot_off, r->L.total);
         S->active_tiles -= r->tiles;
         S->active.erase(std::find(S->active.begin(), S->active.end(), r));
@@ -536,6 +614,7 @@ extern "C" otfs_status otfs_server_create(int device, void* pool_dev, size_t poo
   auto S = std::make_unique<otfs_server>();
   S->device = device;
   S->dry = device < 0;
+  S->hpool = std::make_shared<HostPool>(!S->dry);
   S->pool = static_cast<char*>(pool_dev);
   S->pool_bytes = pool_bytes;
   S->opts = o;
@@ -589,8 +668,9 @@ extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* fram
   if (!frame_fits_ever(S, r->L))
     return fail(OTFS_E_BUDGET, "frame state needs %zu bytes, the pool has %zu for frames",
                 r->L.total, S->pool_bytes - S->slot_base);
-  const float2* yh = static_cast<const float2*>(y_host);
-  r->y.assign(yh, yh + E);
+  if (!r->y.take(S->hpool, E * sizeof(float2)))
+    return fail(OTFS_E_NOMEM, "no host memory for the frame's copy of y");
+  std::memcpy(r->y.p, y_host, E * sizeof(float2));
   build_tables(S->opts.refresh_every > 0, r.get());
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> g(S->mu);
@@ -635,8 +715,8 @@ extern "C" otfs_status otfs_poll(otfs_server_t* S, uint64_t ticket, void* xhat_h
     r = std::move(it->second);
     S->reqs.erase(it);
   }
-  if (xhat_host) std::memcpy(xhat_host, r->xhat.data(), r->xhat.size() * sizeof(float2));
-  if (sym_host && !r->sym.empty()) std::memcpy(sym_host, r->sym.data(), r->sym.size());
+  if (xhat_host && !r->xhat.empty()) std::memcpy(xhat_host, r->xhat.p, r->xhat.n);
+  if (sym_host && !r->sym.empty()) std::memcpy(sym_host, r->sym.p, r->sym.n);
   if (stats) *stats = r->stats;
   if (latency_ns)
     *latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
