@@ -233,7 +233,10 @@ typedef struct otfs_server otfs_server_t;
  * defaults; the bf16 flags are not supported here).  device = -1 starts a dry-run server
  * that schedules and completes frames without any device work (x_hat = 0, status
  * OTFS_FRAME_DRYRUN), for testing admission on hosts without a GPU; pool_dev is then
- * not touched. */
+ * not touched.  The server copies y, x_hat and the decisions through host buffers that it
+ * page-locks and keeps per size for reuse (plain memory if page-locking fails); they are
+ * released by otfs_server_free, so the host memory held grows with the largest number of
+ * frames in flight at once. */
 otfs_status otfs_server_create(int device, void* pool_dev, size_t pool_bytes,
                                const otfs_cg_opts* opts, int32_t step_iters,
                                otfs_server_t** out);
