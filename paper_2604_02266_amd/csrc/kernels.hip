@@ -546,6 +546,10 @@ constexpr int kRows64 = 2;   // rows per thread chunk in the FP64 refresh gather
 #define OTFS_ELEM_CHUNK 8
 #endif
 constexpr int kElemChunk = OTFS_ELEM_CHUNK;   // elements per thread in flight, element-wise passes
+#ifndef OTFS_ELEM_CHUNK_FD
+#define OTFS_ELEM_CHUNK_FD 16
+#endif
+constexpr int kElemChunkFd = OTFS_ELEM_CHUNK_FD;   // the same in the direct-fd kind (more registers free)
 #ifndef OTFS_RES_ROWS
 #define OTFS_RES_ROWS 2
 #endif
@@ -1144,18 +1148,19 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     // ---- C: c -= alpha a, partial ||c||^2 ----
     {
       float acc = 0.f;
-      // kElemChunk elements per thread at a time, all loads issued first (past the band's
-      // end the last element is re-read and nothing is stored)
-      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * kElemChunk) {
-        float2 a[kElemChunk], c[kElemChunk];
+      // EC elements per thread at a time, all loads issued first (past the band's end the
+      // last element is re-read and nothing is stored)
+      constexpr int EC = FDIR ? kElemChunkFd : kElemChunk;
+      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * EC) {
+        float2 a[EC], c[EC];
 #pragma unroll
-        for (int j = 0; j < kElemChunk; ++j) {
+        for (int j = 0; j < EC; ++j) {
           const uint32_t w = min(u + (uint32_t)(j * kBlock), u1 - 1u);
           a[j] = av.ld<kNtElem>(w);
           c[j] = cv.ld<kNtElem>(w);
         }
 #pragma unroll
-        for (int j = 0; j < kElemChunk; ++j) {
+        for (int j = 0; j < EC; ++j) {
           const uint32_t w = u + (uint32_t)(j * kBlock);
           if (w < u1) {
             const float2 cn = axpyf(-alpha, a[j], c[j]);
