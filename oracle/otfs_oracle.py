@@ -13,8 +13,9 @@ directly, slowly and without fusion:
   printed, the product form sum_p h_p Pi^tau_p Delta^nu_p of delay and Doppler shift
   operators, and the DZT-conjugated time-domain channel (Eqs. zak, iZak, y_discrete_td);
 * the LMMSE solution (Eq. lmmse) by Cholesky on the dense normal equations;
-* conjugate gradient exactly in the order of Algorithm 1 (Sec. IV-C), with a per-frame
-  relative-residual stop test added in front of the direction update;
+* conjugate gradient (Hestenes-Stiefel) on the normal equations, the iteration of
+  Algorithm 1 (Sec. IV-C), with a per-frame relative-residual stop test after the residual
+  update;
 * hard QAM decisions (Eq. demod), per axis and by brute force;
 * the point-pilot channel estimate (Eq. heff) and its Hadamard form (Eq. heff_exp,
   Eq. heff_hadamard).
@@ -276,41 +277,57 @@ def dense_H_timedomain(M, N, h, tau, nu) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------------------
-# Algorithm 1 (compute-aware CG) with a relative-residual stop
+# LMMSE by conjugate gradient on the normal equations
 # ----------------------------------------------------------------------------------------
+def _normal_operator(op: TwistedConvChannel, lam: float):
+    """v -> (H^H H + lam I) v, the Hermitian positive definite matrix of Eq. lmmse."""
+    return lambda v: op.apply_adjoint(op.apply(v)) + lam * v
+
+
+def _stop(rho, rho0, k, max_iters, tol):
+    """Stop rule: the relative residual sqrt(rho / rho0) has reached tol (when tol > 0), or
+    k = max_iters steps were taken.  tol <= 0 is the fixed-count form of Algorithm 1."""
+    rel = math.sqrt(rho / rho0)
+    return (tol > 0.0 and rel <= tol) or k >= max_iters, rel
+
+
 def cg_lmmse(y, op: TwistedConvChannel, lam: float, max_iters: int, tol: float):
-    """Solve (H^H H + lam I) x = H^H y by conjugate gradient from x = 0 (Algorithm 1).
+    """x = (H^H H + lam I)^{-1} H^H y (Eq. lmmse) by the conjugate gradient method of
+    Hestenes and Stiefel (1952) for a Hermitian positive definite system A x = b, started
+    from x = 0.
 
-    Stop rule (added to Algorithm 1, which runs a fixed count): after the residual update
-    of iteration xi, stop when sqrt(c_norm_xi / c_norm_0) <= tol (tol > 0), or at
-    xi = max_iters.  tol <= 0 gives the fixed-count form.  If H^H y = 0 the answer is x = 0
-    after zero iterations.
+    With residual r = b - A x and search direction d, each step minimises the A-norm of the
+    error along d: gamma = (r^H r) / (d^H A d), x += gamma d, r -= gamma A d; the next
+    direction d = r + ((r^H r)_new / (r^H r)_old) d is A-conjugate to the previous ones.
+    d^H A d is real for Hermitian A; its real part is taken.  This is the iteration of
+    Algorithm 1 (Sec. IV-C): its c is r, its p is d, its a_p is A d.
 
-    Returns (x, iters, rel_res) with iters = number of x updates performed.
+    Stop rule (_stop): after the residual update of step k; tol <= 0 runs exactly max_iters
+    steps, Algorithm 1's fixed count.  b = H^H y = 0 gives x = 0 after zero steps.
+
+    Returns (x, steps, relative residual sqrt(r^H r / b^H b) at the last step).
     """
-    y = np.asarray(y, dtype=np.complex128)
-    b = op.apply_adjoint(y)                      # b = H^H y
+    apply_A = _normal_operator(op, lam)
+    b = op.apply_adjoint(np.asarray(y, dtype=np.complex128))
     x = np.zeros_like(b)
-    c = b.copy()
-    p = b.copy()
-    cn = float(np.vdot(c, c).real)               # c_norm = ||c||^2
-    cn0 = cn
-    if cn0 == 0.0:
+    r = b.copy()
+    rho0 = rho = float(np.vdot(r, r).real)
+    if rho0 == 0.0:
         return x, 0, 0.0
-    iters, rel = 0, 1.0
-    for xi in range(1, max_iters + 1):
-        a = op.apply_adjoint(op.apply(p)) + lam * p      # a_p = H^H (H p) + lam p
-        alpha = cn / float(np.vdot(p, a).real)           # alpha = c_norm / Re(p^H a_p)
-        x = x + alpha * p
-        c = c - alpha * a
-        cn_new = float(np.vdot(c, c).real)
-        iters = xi
-        rel = math.sqrt(cn_new / cn0)
-        if tol > 0.0 and rel <= tol:
-            break
-        p = c + (cn_new / cn) * p
-        cn = cn_new
-    return x, iters, rel
+    d = r.copy()
+    k, rel = 0, 1.0
+    while True:
+        q = apply_A(d)
+        gamma = rho / float(np.vdot(d, q).real)
+        x += gamma * d
+        r -= gamma * q
+        k += 1
+        rho_new = float(np.vdot(r, r).real)
+        done, rel = _stop(rho_new, rho0, k, max_iters, tol)
+        if done:
+            return x, k, rel
+        d = r + (rho_new / rho) * d
+        rho = rho_new
 
 
 def lmmse_dense(y, H: np.ndarray, lam: float) -> np.ndarray:
