@@ -91,11 +91,17 @@ enum {
                                     through that XCD's L2)                                   */
   OTFS_NO_LDS_RESIDENT = 1u << 5, /* solve small one-tile frames with their vectors in memory
                                     too (default: in LDS when 5*M*N*8 bytes fit 40 KiB)      */
-  OTFS_SPLIT_DIRECTION = 1u << 6  /* always form the direction p = c + beta p in a pass of its
+  OTFS_SPLIT_DIRECTION = 1u << 6, /* always form the direction p = c + beta p in a pass of its
                                     own before the H pass.  By default, when every frame
                                     gathered straight from memory has P <= 8 (and neither the
                                     stored-D mode nor the refresh is on), the H pass forms it
                                     inside its gathers instead; the results are identical  */
+  OTFS_D_STORED_C64 = 1u << 7    /* store D_{p,q} (Eq. D_definition) in complex64 in the
+                                    workspace: the SS table of Eq. ds_repr as the paper keeps
+                                    it (Sec. IV-B, "Efficient Data Structure"), P x total_elems
+                                    entries of 8 bytes, built on the device at bind from the
+                                    FP32 delay-ramp and wrap tables.  Excludes
+                                    OTFS_D_STORED_BF16                                        */
 };
 
 /* CG options (Algorithm 1 with a per-frame stop test added in front of the direction
@@ -178,6 +184,14 @@ otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t* info);
  * the next otfs_plan_bind.  Used by the autotuner. */
 otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elems, int32_t max_grid);
 
+/* Windowed gathers: frames whose delay bins divide into strips of strip_cols columns (a
+ * multiple of 64 dividing 512) and whose paths number at most 16 are tiled into such strips
+ * over all Doppler rows; every gather pass streams each source row once through an LDS ring
+ * chunk_rows output rows at a time and gathers every path from there.  0 turns it off (the
+ * default).  Takes effect at the next otfs_plan_bind; frames outside the form's limits keep
+ * row bands. */
+otfs_status otfs_plan_set_window(otfs_plan_t* plan, int32_t strip_cols, int32_t chunk_rows);
+
 /* LDS budget per workgroup for staging the gather windows of H and H^H (Eqs. sparse_mvm,
  * sparse_herm_mvm), in bytes, at most 65536; takes effect at the next otfs_plan_bind.  A
  * staged frame's workgroup copies the source rows and columns a block of its outputs can
@@ -207,11 +221,20 @@ otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y_dev, void* x_de
 otfs_status otfs_lmmse_cg(otfs_plan_t* plan, const void* y_dev, void* xhat_dev, uint8_t* sym_dev,
                           otfs_frame_stats* stats_dev, void* stream);
 
-/* Plain form of the same computation: one frame at a time, five unfused kernel launches
- * per iteration (H, H^H + lam + dot, update + norm, direction), scalars kept on the
- * device, the same stop rule.  The baseline the fused form is measured against. */
+/* Plain form of the same computation: one frame at a time, four unfused kernel launches
+ * per iteration (H; H^H + lam + dot; update + norm; direction), scalars kept on the
+ * device, the same stop rule, no FP64 refresh.  The baseline the fused form is measured
+ * against. */
 otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y_dev, void* xhat_dev,
                                 uint8_t* sym_dev, otfs_frame_stats* stats_dev, void* stream);
+
+/* Bound of the fused kernel's in-kernel waits (per-frame barriers and neighbour waits), in
+ * microseconds: a wait that is not satisfied within it gives up, raises the launch-wide
+ * abort word (every other wait of the launch then gives up too), and the frames concerned
+ * report OTFS_FRAME_TIMEOUT; every workgroup still exits normally.  wait_us < 0 restores
+ * the default (20 s); 0 gives up at the first unsatisfied poll (for tests of that path).
+ * Takes effect at the next otfs_lmmse_cg call. */
+otfs_status otfs_plan_set_wait_limit(otfs_plan_t* plan, int64_t wait_us);
 
 /* Duration in milliseconds of the fused CG kernel of the last otfs_lmmse_cg call that ran
  * with OTFS_TIME_KERNEL (waits for its end event). */

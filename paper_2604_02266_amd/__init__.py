@@ -31,6 +31,7 @@ TIME_KERNEL = 1 << 3
 AGENT_BARRIER = 1 << 4
 NO_LDS_RESIDENT = 1 << 5
 SPLIT_DIRECTION = 1 << 6
+D_STORED_C64 = 1 << 7
 (FRAME_RUNNING, FRAME_CONVERGED, FRAME_CAPPED, FRAME_NONFINITE, FRAME_BREAKDOWN, FRAME_TIMEOUT,
  FRAME_DRYRUN) = range(7)
 
@@ -107,11 +108,13 @@ def lib() -> ctypes.CDLL:
         "otfs_plan_info": (st, [_vp, ctypes.POINTER(PlanInfo)]),
         "otfs_plan_set_tiling": (st, [_vp, ctypes.c_int32, ctypes.c_int32]),
         "otfs_plan_set_staging": (st, [_vp, ctypes.c_int32]),
+        "otfs_plan_set_window": (st, [_vp, ctypes.c_int32, ctypes.c_int32]),
         "otfs_apply_H": (st, [_vp, _vp, _vp, _vp]),
         "otfs_apply_HH": (st, [_vp, _vp, _vp, _vp]),
         "otfs_lmmse_cg": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "otfs_lmmse_cg_plain": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "otfs_plan_kernel_ms": (st, [_vp, ctypes.POINTER(ctypes.c_float)]),
+        "otfs_plan_set_wait_limit": (st, [_vp, ctypes.c_int64]),
         "otfs_server_create": (st, [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(CgOpts),
                                     ctypes.c_int32, ctypes.POINTER(_vp)]),
         "otfs_submit": (st, [_vp, ctypes.POINTER(FrameDesc), _vp,
@@ -186,7 +189,8 @@ class Plan:
 
     def __init__(self, frames: Sequence, max_iters: int = 50, rel_tol: float = 1e-6,
                  refresh_every: int = 0, flags: int = 0, tile_elems: int = 0,
-                 max_grid: int = 0, stage_bytes: Optional[int] = None, bind: bool = True):
+                 max_grid: int = 0, stage_bytes: Optional[int] = None,
+                 window: Optional[Sequence[int]] = None, bind: bool = True):
         self._lib = lib()
         self.frames = list(frames)
         self.opts = make_opts(max_iters, rel_tol, refresh_every, flags)
@@ -200,6 +204,8 @@ class Plan:
             _check(self._lib.otfs_plan_set_tiling(self._h, int(tile_elems), int(max_grid)))
         if stage_bytes is not None:
             _check(self._lib.otfs_plan_set_staging(self._h, int(stage_bytes)))
+        if window is not None:
+            _check(self._lib.otfs_plan_set_window(self._h, int(window[0]), int(window[1])))
         if bind:
             self.bind()
 
@@ -307,6 +313,9 @@ class Plan:
 
     def lmmse_cg_plain(self, y, xhat=None, sym=None, stats=None, stream=None):
         return self._solve(self._lib.otfs_lmmse_cg_plain, y, xhat, sym, stats, stream)
+
+    def set_wait_limit(self, wait_us: int):
+        _check(self._lib.otfs_plan_set_wait_limit(self._h, int(wait_us)))
 
     def kernel_ms(self) -> float:
         ms = ctypes.c_float()

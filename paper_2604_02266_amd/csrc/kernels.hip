@@ -20,6 +20,8 @@
 // the operator is a sparse gather, not a dense contraction.
 #include <math.h>
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "otfs_internal.h"
@@ -184,6 +186,30 @@ struct SrcLds {   // complex64 vector in LDS
   }
   __device__ __forceinline__ float2 value(Raw x) const { return x; }
 };
+// The stored coefficient table D_{p,q} (Eq. D_definition, the SS table of Eq. ds_repr):
+// one entry per (path, output element), P x E, as a bf16 pair or a complex64 value.
+template <int SD>
+struct DTab {   // kDNone: no table
+  using Raw = uint32_t;
+  const void* p;
+  __device__ __forceinline__ Raw load(int64_t) const { return 0u; }
+  __device__ __forceinline__ float2 value(Raw) const { return make_float2(0.f, 0.f); }
+};
+template <>
+struct DTab<kDBf16> {
+  using Raw = uint32_t;
+  const void* p;
+  __device__ __forceinline__ Raw load(int64_t i) const { return glb(static_cast<const uint32_t*>(p))[i]; }
+  __device__ __forceinline__ float2 value(Raw w) const { return bf16x2_to_f2(w); }
+};
+template <>
+struct DTab<kDC64> {
+  using Raw = u64;
+  const void* p;
+  __device__ __forceinline__ Raw load(int64_t i) const { return glb(static_cast<const u64*>(p))[i]; }
+  __device__ __forceinline__ float2 value(Raw w) const { return __builtin_bit_cast(float2, w); }
+};
+
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // A complex64 vector read and written element-wise through a buffer resource (one 32-bit
 // offset per element, shared by every vector accessed at that element).
@@ -312,19 +338,20 @@ __device__ double block_sum_d(double v, double* red) {
   __syncthreads();
   return s;
 }
-// sum of the T per-tile partials of a frame, in tile order, by every thread
-__device__ __forceinline__ double tile_sum(const float* part, int T) {
+// sum of the T per-tile partials of a frame, in FP32 and in tile order, by every thread:
+// every workgroup of the frame forms the same value, independent of the rest of the batch
+__device__ __forceinline__ float tile_sum(const float* part, int T) {
   // loads in groups of 8 in flight together; the sum runs in tile order
-  double s = 0.0;
+  float s = 0.f;
   int i = 0;
   for (; i + 8 <= T; i += 8) {
     float v[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = part[i + j];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += (double)v[j];
+    for (int j = 0; j < 8; ++j) s = __fadd_rn(s, v[j]);
   }
-  for (; i < T; ++i) s += (double)part[i];
+  for (; i < T; ++i) s = __fadd_rn(s, part[i]);
   return s;
 }
 __device__ __forceinline__ double tile_sum_d(const double* part, int T) {
@@ -559,9 +586,10 @@ constexpr int kElemChunkFd = OTFS_ELEM_CHUNK_FD;   // the same in the direct-fd 
 constexpr int kResRows = OTFS_RES_ROWS;    // rows per chunk of the LDS-resident gathers
 constexpr int kResPaths = OTFS_RES_PATHS;  // paths per step of the LDS-resident gathers
 
-template <int R, int U, bool ADJ, bool STORED, bool UNI, class Src, class Pref, class Sink>
+template <int R, int U, bool ADJ, int SD, bool UNI, class Src, class Pref, class Sink>
 __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int le, const Src& src,
                                                 Pref pref, Sink sink) {
+  constexpr bool STORED = SD != kDNone;
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
   const int TY = kBlock / TX;
@@ -578,7 +606,7 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
   const KPairs wtab_s = kpairs(F.wtab);
   const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(F.rtab, (int64_t)P * M * 8);
   const GPairs wtab = gpairs(F.wtab);
-  const gptr<const uint32_t> dtab = glb(F.dtab);
+  const DTab<SD> dtab{F.dtab};
   for (int k = tx; k < M; k += TX) {
     for (int r0 = 0; r0 < nrows; r0 += R) {
       int l[R];
@@ -619,7 +647,7 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
           }
         }
         typename Src::Raw v[NP][R];
-        uint32_t d[NP][R];
+        typename DTab<SD>::Raw d[NP][R];
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
 #pragma unroll
@@ -632,8 +660,8 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
             else
               v[u][i] = src.load_b(kk8[u] + rs, 0u);
             if (STORED)
-              d[u][i] = dtab[(int64_t)(p0 + u) * E +
-                             (ADJ ? (int64_t)((rs + kk8[u]) >> 3) : (int64_t)l[i] * M + k)];
+              d[u][i] = dtab.load((int64_t)(p0 + u) * E +
+                                  (ADJ ? (int64_t)((rs + kk8[u]) >> 3) : (int64_t)l[i] * M + k));
           }
         }
 #pragma unroll
@@ -641,7 +669,7 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
           if (STORED) {
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-              const float2 dd = bf16x2_to_f2(d[u][i]);
+              const float2 dd = dtab.value(d[u][i]);
               cmacf(acc[i], ADJ ? make_float2(dd.x, -dd.y) : dd, src.value(v[u][i]));
             }
           } else if (__builtin_amdgcn_ballot_w64(lo[u] || hi[u]) != 0) {
@@ -677,16 +705,16 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
   }
 }
 
-template <int R, int U, bool ADJ, bool STORED, class Src, class Pref, class Sink>
+template <int R, int U, bool ADJ, int SD, class Src, class Pref, class Sink>
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
                                            Pref pref, Sink sink) {
   const int TX = F.M < kBlock ? F.M : kBlock;
   // the per-lane row arithmetic of the general form holds more registers: fewer paths
   // in flight there
   if ((TX & 63) == 0)
-    band_apply_rows<R, U, ADJ, STORED, true>(F, lb, le, src, pref, sink);
+    band_apply_rows<R, U, ADJ, SD, true>(F, lb, le, src, pref, sink);
   else
-    band_apply_rows<R, (U < kPathsGeneral ? U : kPathsGeneral), ADJ, STORED, false>(F, lb, le, src,
+    band_apply_rows<R, (U < kPathsGeneral ? U : kPathsGeneral), ADJ, SD, false>(F, lb, le, src,
                                                                                   pref, sink);
 }
 
@@ -694,10 +722,10 @@ __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, co
 struct NoPref {
   __device__ __forceinline__ NoPre operator()(uint32_t) const { return NoPre{}; }
 };
-template <int R, int U, bool ADJ, bool STORED, class Src, class Sink>
+template <int R, int U, bool ADJ, int SD, class Src, class Sink>
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
                                            Sink sink) {
-  band_apply<R, U, ADJ, STORED>(F, lb, le, src, NoPref{},
+  band_apply<R, U, ADJ, SD>(F, lb, le, src, NoPref{},
                                 [&](int q, float2 v, NoPre) { sink(q, v); });
 }
 
@@ -841,18 +869,18 @@ __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, 
 // geometry), gathered straight from memory otherwise.  out.pre(q) issues the loads output q needs
 // besides the source; out.put(q, v, pre, own) receives it with own[] = the source
 // vectors' elements at q.
-template <bool ADJ, bool STORED, bool STAGED, int R = kRows, int UP = kPaths, class Src,
+template <bool ADJ, int SD, bool STAGED, int R = kRows, int UP = kPaths, class Src,
           class Out>
 __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, float2* lds,
                                            const Src& src, const Out& out) {
-  if constexpr (STAGED && !STORED && Src::kStageable) {
+  if constexpr (STAGED && SD == kDNone && Src::kStageable) {
     staged_apply<ADJ>(F, lb, le, lds, src, out);
   } else {
     struct PreOwn {
       typename Out::Pre pre;
       float2 own[Src::kNV];
     };
-    band_apply<R, UP, ADJ, STORED>(
+    band_apply<R, UP, ADJ, SD>(
         F, lb, le, src,
         [&](uint32_t u) {
           PreOwn po;
@@ -862,6 +890,202 @@ __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, fl
         },
         [&](int q, float2 v, const PreOwn& po) { out.put((uint32_t)q, v, po.pre, po.own); });
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// Windowed band application of H (ADJ = false) or H^H (ADJ = true) over a strip.
+//
+// The workgroup owns delay columns [k0, k0 + W) of one frame over all N Doppler rows.
+// Output row l of path p reads source row l + s_l(p) at column k + s_k(p) (H: s = (-tau,
+// -nu); H^H: s = (+tau, +nu)).  The rows are produced RC at a time.  The source rows that a
+// chunk reaches -- rows [l0 + s_l,min, l0 + RC - 1 + s_l,max], columns [k0 + s_k,min,
+// k0 + W - 1 + s_k,max] (both ranges widened to contain 0) -- sit in an LDS ring of
+// NB = 2 RC + d_nu rows: while a chunk is computed from LDS, the RC rows the next chunk adds
+// are read from memory into registers (every read of the chunk issued together, none under
+// a branch), then written to their ring slots, which no workgroup-mate still reads (the ring
+// holds two chunks of new rows besides the shared ones), and one barrier per chunk
+// publishes them.  Each source element is read from memory once per strip (plus the
+// d_nu-row head of the ring and the d_tau-column margin shared with the neighbour strips),
+// instead of once per path.
+//
+// Thread (tx, ty) keeps column k = k0 + tx: the P coefficients R_p[k] (H) or conj R_p[<k +
+// tau_p>_M] (H^H) and the delay-wrap flags of that column stay in registers for the whole
+// strip.  Coefficients, wrap factors and the order of the sum over paths are exactly those
+// of band_apply, so the two give identical bits.
+//
+// src: a source view (SrcBuf, SrcDir, SrcBf16): load(i) reads element i of the frame,
+// value(raw) forms it.  pref(q) issues the loads output q needs besides the source;
+// sink(q, v, pre) receives output q.  W is a multiple of 64 dividing kBlock, P <= kWinPaths,
+// RC * ceil((W + d_tau) / 64) <= kWaves * kWinLoads (the host guarantees all three).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int mod_floor(int a, int n) {
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+template <bool ADJ, int RPT, class Src, class Pref, class Sink>
+__device__ __forceinline__ void win_apply(const FrameDev& F, int k0, float2* lds_gen,
+                                          const Src& src, Pref pref, Sink sink) {
+  const int M = F.M, N = F.N, P = F.P;
+  const int W = F.win_w, RC = F.win_rc;
+  const int TY = kBlock / W;
+  const int tx = (int)threadIdx.x % W;
+  const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.x / W);
+  const int smin_k = ADJ ? F.tau_lo : -F.tau_hi, smax_k = ADJ ? F.tau_hi : -F.tau_lo;
+  const int smin_l = ADJ ? F.nu_lo : -F.nu_hi, smax_l = ADJ ? F.nu_hi : -F.nu_lo;
+  const int WC = W + (smax_k - smin_k);
+  const int NB = 2 * RC + (smax_l - smin_l);
+  const int cbase = k0 + smin_k;                // unwrapped column of window column 0
+  const int k = k0 + tx;
+  const KPairs paths = kpairs(F.paths);
+  const KPairs wtab_s = kpairs(F.wtab);
+  const GPairs rtab = gpairs(F.rtab);
+  const LdsC ring = lds_c(lds_gen);
+
+  // per-path shifts (wave-uniform, loaded once: scalar loads inside the gather loop would
+  // make every wait for them also wait for the ring reads in flight), and per-path column
+  // state: coefficient and delay-wrap flags (lo: bit p, hi: bit 16 + p)
+  int2 tns[kWinPaths];
+#pragma unroll
+  for (int p = 0; p < kWinPaths; ++p) tns[p] = p < P ? paths.i2(p) : make_int2(0, 0);
+  float2 cf[kWinPaths];
+  uint32_t wrap = 0u;
+#pragma unroll
+  for (int p = 0; p < kWinPaths; ++p) {
+    if (p < P) {
+      const int2 tn = tns[p];
+      const int K = ADJ ? k + tn.x : k - tn.x;
+      const bool lo = K < 0, hi = K >= M;
+      const int kk = lo ? K + M : (hi ? K - M : K);
+      const float2 r = rtab.f((int64_t)p * M + (ADJ ? kk : k));
+      cf[p] = ADJ ? make_float2(r.x, -r.y) : r;
+      wrap |= (lo ? 1u : 0u) << p;
+      wrap |= (hi ? 1u : 0u) << (16 + p);
+    } else {
+      cf[p] = make_float2(0.f, 0.f);
+    }
+  }
+
+  // staging map: a chunk's RC rows x WC window columns are cut into pieces of 64
+  // consecutive columns of one row; wave w takes pieces w, w + kWaves, ... (at most
+  // kWinLoads), so a piece's row is wave-uniform and each lane reads one element (lanes
+  // past the end of a row re-read its last element and store nothing)
+  const int NBLK = (WC + 63) / 64;
+  const int pieces = RC * NBLK;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = (int)threadIdx.x & 63;
+  typename Src::Raw buf[kWinLoads];
+  // read the RC source rows starting at unwrapped row r0 into registers / write them to
+  // the ring slots of ring positions rp0 ..
+  auto issue = [&](int r0) {
+    const int rw0 = mod_floor(r0, N);
+#pragma unroll
+    for (int m = 0; m < kWinLoads; ++m) {
+      const int pc = wave + m * kWaves;
+      if (pc < pieces) {
+        const int i = pc / NBLK, b = pc - i * NBLK;
+        int r = rw0 + i;
+        r -= r >= N ? N : 0;
+        int col = cbase + min(b * 64 + lane, WC - 1);
+        col += col < 0 ? M : 0;
+        col -= col >= M ? M : 0;
+        buf[m] = src.load((uint32_t)r * (uint32_t)M + (uint32_t)col);
+      }
+    }
+  };
+  auto commit = [&](int rp0) {
+    const int s0 = rp0 % NB;
+#pragma unroll
+    for (int m = 0; m < kWinLoads; ++m) {
+      const int pc = wave + m * kWaves;
+      if (pc < pieces) {
+        const int i = pc / NBLK, b = pc - i * NBLK;
+        const int c = b * 64 + lane;
+        int sl = s0 + i;
+        sl -= sl >= NB ? NB : 0;
+        if (c < WC) ring.st(sl * WC + c, src.value(buf[m]));
+      }
+    }
+  };
+
+  // the head of the ring: rows smin_l .. RC - 1 + smax_l (d_nu + RC rows, RC at a time)
+  const int head = RC + (smax_l - smin_l);
+  for (int h = 0; h < head; h += RC) {
+    issue(smin_l + h);
+    commit(h);
+  }
+  __syncthreads();
+
+  const int nch = (N + RC - 1) / RC;
+  for (int j = 0; j < nch; ++j) {
+    const int l0 = j * RC;
+    // the next chunk's new rows, in flight during this chunk's arithmetic
+    const bool more = j + 1 < nch;
+    if (more) issue(l0 + RC + smax_l);
+    int l[RPT];
+    float2 acc[RPT];
+    decltype(pref(0u)) pf[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      l[i] = min(l0 + ty + i * TY, N - 1);
+      acc[i] = make_float2(0.f, 0.f);
+      pf[i] = pref((uint32_t)(l[i] * M + k));
+    }
+    const int jb = l0 % NB;                       // ring slot of unwrapped row l0 + smin_l
+#pragma unroll
+    for (int p = 0; p < kWinPaths; ++p) {
+      if (p < P) {
+        const int2 tn = tns[p];
+        const int sk = ADJ ? tn.x : -tn.x, sl = ADJ ? tn.y : -tn.y;
+        const uint32_t col = (uint32_t)(tx + sk - smin_k);
+        const bool lo = (wrap >> p) & 1u, hi = (wrap >> (16 + p)) & 1u;
+        float2 v[RPT];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          // ring position of source row l + sl, relative to row l0 + smin_l
+          int sp = jb + (l[i] - l0) + (sl - smin_l);
+          sp -= sp >= NB ? NB : 0;
+          v[i] = ring.ld(sp * WC + (int)col);
+        }
+        if (__builtin_amdgcn_ballot_w64(lo || hi) != 0) {
+          float2 cw = cf[p];
+          if (!ADJ) {
+            const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
+            cw = cmulf(cf[p], make_float2(wn.x, hi ? -wn.y : wn.y));
+          }
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const float2 wli = wtab_s.f(l[i]);     // only waves holding a delay wrap
+            const float2 w = make_float2(wli.x, hi ? wli.y : -wli.y);
+            const float2 c = (lo || hi) ? cmulf(cw, w) : cf[p];
+            cmacf(acc[i], c, v[i]);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) cmacf(acc[i], cf[p], v[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (l0 + ty + i * TY < N) sink(l[i] * M + k, acc[i], pf[i]);
+    if (more) commit(l0 + head);
+    __syncthreads();
+  }
+}
+
+// win_apply for the frame's rows per thread and chunk (2 or 4; the host guarantees one).
+template <bool ADJ, class Src, class Pref, class Sink>
+__device__ __forceinline__ void win_apply_any(const FrameDev& F, int k0, float2* lds,
+                                              const Src& src, Pref pref, Sink sink) {
+#ifdef OTFS_WIN_RPT_ONLY
+  win_apply<ADJ, OTFS_WIN_RPT_ONLY>(F, k0, lds, src, pref, sink);
+#else
+  if (F.win_rc / (kBlock / F.win_w) == 4)
+    win_apply<ADJ, 4>(F, k0, lds, src, pref, sink);
+  else
+    win_apply<ADJ, 2>(F, k0, lds, src, pref, sink);
+#endif
 }
 
 // FP64 version (coefficients from the FP64 tables) for the true-residual refresh.
@@ -952,15 +1176,23 @@ __device__ void finish_tile(const FrameDev& F, const WorkItem& wi, const FrameVe
                             const FrameState& s, const float2* pcur, bool xpending,
                             int status) {
   const int M = F.M;
-  const int64_t q0 = (int64_t)wi.l_begin * M, q1 = (int64_t)wi.l_end * M;
   const bool dec = V.sym != nullptr && F.qside > 0;
-  for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
+  auto one = [&](int64_t q) {
     float2 xv = V.x[q];
     if (xpending) {
       xv = axpyf(s.alpha, pcur[q], xv);
       V.x[q] = xv;
     }
     if (dec) V.sym[q] = decide(xv, F.qscale, F.qside);
+  };
+  const int cols = wi.k_end - wi.k_begin;
+  if (cols == M) {   // a band of whole rows: one contiguous range
+    const int64_t q0 = (int64_t)wi.l_begin * M, q1 = (int64_t)wi.l_end * M;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) one(q);
+  } else {           // a strip: cols divides kBlock, so each thread keeps one column
+    const int tx = (int)threadIdx.x % cols, ty = (int)threadIdx.x / cols;
+    for (int l = wi.l_begin + ty; l < wi.l_end; l += kBlock / cols)
+      one((int64_t)l * M + wi.k_begin + tx);
   }
   if (wi.tile == 0 && threadIdx.x == 0) {
     if (V.stats) {
@@ -1000,11 +1232,11 @@ struct LaunchCtx {
 };
 
 // FDIR: the H pass forms p' = c + beta p inside its gathers (direct-fd kind).
-template <bool STORED, bool REFRESH, bool STAGED, bool FDIR = false>
+template <int SD, bool REFRESH, bool STAGED, bool FDIR = false>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                         const LaunchCtx& L, float* red, double* redd, int* sflag, float2* lds) {
   // the bf16 table reads and the FP64 refresh leave fewer registers for gathers in flight
-  constexpr int RR = (STORED || REFRESH) ? 2 : kRows;
+  constexpr int RR = (SD != kDNone || REFRESH) ? 2 : kRows;
   const FrameVecs V = frame_vecs(F, B);
   FrameState s = *F.st;
   if (s.status != OTFS_FRAME_RUNNING) return;
@@ -1055,13 +1287,13 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     float acc = 0.f;
     const OutInit out{cv, cvec(F.p0, E), xv, &acc};
     if (V.ybf16)
-      apply_band<true, STORED, STAGED, RR>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, out);
+      apply_band<true, SD, STAGED, RR>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, out);
     else
-      apply_band<true, STORED, STAGED, RR>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, out);
+      apply_band<true, SD, STAGED, RR>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, out);
     const float bs = block_sum(acc, red);
     if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
     if (!bar()) return fail_timeout();
-    const float cn0 = (float)tile_sum(F.part_cc, T);
+    const float cn0 = tile_sum(F.part_cc, T);
     s.init = 1;
     s.iter = 0;
     s.pbuf = 0;
@@ -1089,12 +1321,12 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     // ---- A: deferred updates of the band, t = H p ----
     if constexpr (STAGED) {
       // c and the old p are staged together; p' = c + beta p is formed from the windows
-      apply_band<false, STORED, true, RR>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
+      apply_band<false, SD, true, RR>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
                                       OutA{tv, pnv, xv, al, be, xp});
     } else if constexpr (FDIR) {
       // p' = c + beta p_old formed from both vectors at every gather (two loads each: fewer
       // paths in flight), stored once for the own rows with x += alpha p_old
-      apply_band<false, STORED, false, kFdRows, kFdPaths>(F, lb, le, lds,
+      apply_band<false, SD, false, kFdRows, kFdPaths>(F, lb, le, lds,
                                                          SrcDir{cv.r, pov.r, be},
                                                          OutA{tv, pnv, xv, al, be, xp});
     } else {
@@ -1120,16 +1352,16 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       if (!halo(rd_h)) return fail_timeout();
       // A2: t = H p' (one load per gather)
       if (kNtT && F.stream_t)
-        apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<true>{tv});
+        apply_band<false, SD, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<true>{tv});
       else
-        apply_band<false, STORED, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<false>{tv});
+        apply_band<false, SD, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<false>{tv});
     }
     if (!halo(rd_hh)) return fail_timeout();
 
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
       float acc = 0.f;
-      apply_band<true, STORED, STAGED, RR>(F, lb, le, lds, SrcBuf{tv.r}, OutB{av, pnv, lam, &acc});
+      apply_band<true, SD, STAGED, RR>(F, lb, le, lds, SrcBuf{tv.r}, OutB{av, pnv, lam, &acc});
       const float bs = block_sum(acc, red);
       if (threadIdx.x == 0) F.part_pa[wi.tile] = bs;
     }
@@ -1137,7 +1369,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     s.pbuf ^= 1;
     s.pending = 0;                                   // both deferred updates are applied
 
-    const float den = (float)tile_sum(F.part_pa, T);
+    const float den = tile_sum(F.part_pa, T);
     const float alpha = s.cn / den;
     if (!(den > 0.f) || !isfinite(alpha)) {          // x already holds x_{xi-1}
       const int st = (isfinite(den) && isfinite(s.cn)) ? OTFS_FRAME_BREAKDOWN
@@ -1174,7 +1406,7 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
     }
     if (!bar()) return fail_timeout();
-    float cn_new = (float)tile_sum(F.part_cc, T);
+    float cn_new = tile_sum(F.part_cc, T);
     s.iter = xi;
     s.alpha = alpha;
     bool xpend = true;                               // x += alpha p_new still to do
@@ -1224,6 +1456,197 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     s.pending = (xpend ? 1 : 0) | 2;
   }
   // iteration budget of this launch used up: keep the state for the next launch
+  if (wi.tile == 0 && threadIdx.x == 0) *F.st = s;
+}
+
+// ---------------------------------------------------------------------------------------
+// One strip's share of one frame's CG loop with windowed gathers (frames with win_w > 0).
+//
+// The schedule and the arithmetic are those of the direct kind with the direction formed
+// inside the H pass (cg_item<.., FDIR = true>); only the tile shape and where the gathers
+// read from change.  A tile is a strip of W delay columns over all N Doppler rows, so the
+// Doppler wrap is inside the tile and only the delay range crosses tiles.  Per iteration:
+//   A: t = H p', p' = c + beta p_old formed as each source row enters the LDS ring; the own
+//      elements store p' and x += alpha p_old (the deferred updates); no wait before it,
+//      since c and p_old were last written before the previous frame barrier;
+//   wait for the strips whose columns the H^H window covers;
+//   B: a = H^H t + lam p', partial Re(p'^H a);                               | barrier
+//   C: c -= alpha a, partial ||c||^2 over the strip;                         | barrier
+// ---------------------------------------------------------------------------------------
+struct OwnCPX {      // own elements the H pass needs besides the window
+  float2 c, p, x;
+};
+
+template <bool REFRESH>
+__device__ void cg_item_win(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
+                            const LaunchCtx& L, float* red, int* sflag, float2* lds) {
+  const FrameVecs V = frame_vecs(F, B);
+  FrameState s = *F.st;
+  if (s.status != OTFS_FRAME_RUNNING) return;
+  const int M = F.M, N = F.N, T = F.T, W = F.win_w;
+  const int k0 = wi.k_begin;
+  const int TY = kBlock / W;
+  const int tx = (int)threadIdx.x % W;
+  const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.x / W);
+  const float lam = F.lam;
+  const int64_t E = (int64_t)M * N;
+  const CVec cv = cvec(F.c, E), tv = cvec(F.t, E), av = cvec(F.a, E), xv = cvec(V.x, E);
+  unsigned nbar = 0;
+  auto bar = [&]() -> bool {
+    if (T == 1) {
+      __syncthreads();
+      return true;
+    }
+    nbar += (unsigned)T;
+    return frame_barrier(F.bar, nbar, L.xcd_local != 0, L.abort_flag, L.timeout, sflag);
+  };
+  // strips whose columns the H^H pass gathers: [k0 + tau_lo, k0 + W - 1 + tau_hi] (mod M)
+  const TileRange rd_hh = tiles_of_rows(k0 + F.tau_lo, W + (F.tau_hi - F.tau_lo), M, T);
+  unsigned npub = 0;
+  auto halo = [&](const TileRange& tr) -> bool {
+    if (T == 1) {
+      __syncthreads();
+      return true;
+    }
+    tile_publish(F.prog + wi.tile, L.xcd_local != 0);
+    ++npub;
+    return halo_wait(F.prog, T, tr, npub, L.xcd_local != 0, L.abort_flag, L.timeout, sflag);
+  };
+  auto fail_timeout = [&]() {
+    if (wi.tile == 0 && threadIdx.x == 0) {
+      FrameState o = s;
+      o.status = OTFS_FRAME_TIMEOUT;
+      *F.st = o;
+      if (V.stats) {
+        otfs_frame_stats st{s.iter, s.rel, OTFS_FRAME_TIMEOUT, T};
+        *V.stats = st;
+      }
+    }
+  };
+
+  // ---- b = H^H y; x = 0; c = p = b; c_norm_0 = ||b||^2 ----
+  if (!s.init) {
+    float acc = 0.f;
+    const CVec p0v = cvec(F.p0, E);
+    auto sink = [&](int q, float2 v, NoPre) {
+      cv.st((uint32_t)q, v);
+      p0v.st((uint32_t)q, v);
+      xv.st((uint32_t)q, make_float2(0.f, 0.f));
+      acc = fmaf(v.x, v.x, acc);
+      acc = fmaf(v.y, v.y, acc);
+    };
+    if (V.ybf16)
+      win_apply_any<true>(F, k0, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, NoPref{}, sink);
+    else
+      win_apply_any<true>(F, k0, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, NoPref{}, sink);
+    const float bs = block_sum(acc, red);
+    if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
+    if (!bar()) return fail_timeout();
+    const float cn0 = tile_sum(F.part_cc, T);
+    s.init = 1;
+    s.iter = 0;
+    s.pbuf = 0;
+    s.pending = 0;
+    s.cn = cn0;
+    s.cn0 = cn0;
+    s.alpha = 0.f;
+    s.beta = 0.f;
+    s.rel = cn0 > 0.f ? 1.f : 0.f;
+    if (!(cn0 > 0.f)) {
+      const int st = cn0 == 0.f ? OTFS_FRAME_CONVERGED : OTFS_FRAME_NONFINITE;
+      return finish_tile(F, wi, V, s, F.p0, false, st);
+    }
+  }
+
+  for (int step = 0; step < budget; ++step) {
+    const int xi = s.iter + 1;
+    float2* const pold_g = s.pbuf ? F.p1 : F.p0;
+    float2* const pnew_g = s.pbuf ? F.p0 : F.p1;
+    const CVec pov = cvec(pold_g, E), pnv = cvec(pnew_g, E);
+    const bool xp = (s.pending & 1) != 0;
+    const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
+
+    // ---- A: t = H p' with p' = c + beta p_old formed in the ring; own p', x updates ----
+    win_apply_any<false>(
+        F, k0, lds, SrcDir{cv.r, pov.r, be},
+        [&](uint32_t q) {
+          OwnCPX o;
+          o.c = cv.ld(q);
+          o.p = pov.ld(q);
+          o.x = xp ? xv.ld(q) : make_float2(0.f, 0.f);
+          return o;
+        },
+        [&](int q, float2 v, const OwnCPX& o) {
+          tv.st((uint32_t)q, v);
+          pnv.st((uint32_t)q, axpyf(be, o.p, o.c));
+          if (xp) xv.st((uint32_t)q, axpyf(al, o.p, o.x));
+        });
+    if (!halo(rd_hh)) return fail_timeout();
+
+    // ---- B: a = H^H t + lam p', partial Re(p'^H a) ----
+    {
+      float acc = 0.f;
+      win_apply_any<true>(
+          F, k0, lds, SrcBuf{tv.r}, [&](uint32_t q) { return pnv.ld(q); },
+          [&](int q, float2 v, const float2& p) {
+            const float2 a = axpyf(lam, p, v);
+            av.st<kNtB>((uint32_t)q, a);
+            acc = fmaf(p.x, a.x, acc);
+            acc = fmaf(p.y, a.y, acc);
+          });
+      const float bs = block_sum(acc, red);
+      if (threadIdx.x == 0) F.part_pa[wi.tile] = bs;
+    }
+    if (!bar()) return fail_timeout();
+    s.pbuf ^= 1;
+    s.pending = 0;
+    const float den = tile_sum(F.part_pa, T);
+    const float alpha = s.cn / den;
+    if (!(den > 0.f) || !isfinite(alpha)) {
+      const int st = (isfinite(den) && isfinite(s.cn)) ? OTFS_FRAME_BREAKDOWN
+                                                        : OTFS_FRAME_NONFINITE;
+      return finish_tile(F, wi, V, s, pnew_g, false, st);
+    }
+
+    // ---- C: c -= alpha a over the strip, partial ||c||^2 ----
+    {
+      float acc = 0.f;
+      constexpr int EC = kElemChunkFd;
+      for (int r = ty; r < N; r += TY * EC) {
+        float2 a[EC], c[EC];
+#pragma unroll
+        for (int j = 0; j < EC; ++j) {
+          const uint32_t w = (uint32_t)(min(r + j * TY, N - 1) * M + k0 + tx);
+          a[j] = av.ld<kNtElem>(w);
+          c[j] = cv.ld<kNtElem>(w);
+        }
+#pragma unroll
+        for (int j = 0; j < EC; ++j) {
+          if (r + j * TY < N) {
+            const uint32_t w = (uint32_t)((r + j * TY) * M + k0 + tx);
+            const float2 cn = axpyf(-alpha, a[j], c[j]);
+            cv.st<kNtElemSt>(w, cn);
+            acc = fmaf(cn.x, cn.x, acc);
+            acc = fmaf(cn.y, cn.y, acc);
+          }
+        }
+      }
+      const float bs = block_sum(acc, red);
+      if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
+    }
+    if (!bar()) return fail_timeout();
+    const float cn_new = tile_sum(F.part_cc, T);
+    s.iter = xi;
+    s.alpha = alpha;
+    s.rel = sqrtf(cn_new / s.cn0);
+    if (!isfinite(cn_new)) return finish_tile(F, wi, V, s, pnew_g, true, OTFS_FRAME_NONFINITE);
+    if (F.tol > 0.f && s.rel <= F.tol)
+      return finish_tile(F, wi, V, s, pnew_g, true, OTFS_FRAME_CONVERGED);
+    if (xi >= F.max_iters) return finish_tile(F, wi, V, s, pnew_g, true, OTFS_FRAME_CAPPED);
+    s.beta = cn_new / s.cn;
+    s.cn = cn_new;
+    s.pending = 3;
+  }
   if (wi.tile == 0 && threadIdx.x == 0) *F.st = s;
 }
 
@@ -1379,8 +1802,12 @@ __device__ __forceinline__ int xcc_id() {
 // workgroups sharing one L2.  A frame's tiles are consecutive in its group's queue and a
 // group never has fewer resident workgroups than a frame has tiles, so the first frame
 // with an untaken tile is always being completed: the per-frame barriers cannot deadlock.
-template <bool STORED, bool REFRESH, int KIND>
-__global__ __launch_bounds__(kBlock, OTFS_FUSED_MIN_WAVES) void k_cg_fused(const FrameDev* __restrict__ frames,
+#ifndef OTFS_WIN_MIN_WAVES
+#define OTFS_WIN_MIN_WAVES 2
+#endif
+template <int SD, bool REFRESH, int KIND>
+__global__ __launch_bounds__(kBlock, KIND == kKindWindowed ? OTFS_WIN_MIN_WAVES
+                                                           : OTFS_FUSED_MIN_WAVES) void k_cg_fused(const FrameDev* __restrict__ frames,
                                                      const WorkItem* __restrict__ items,
                                                      const int32_t* __restrict__ qitems,
                                                      const int2* __restrict__ qrange,
@@ -1415,8 +1842,10 @@ __global__ __launch_bounds__(kBlock, OTFS_FUSED_MIN_WAVES) void k_cg_fused(const
     const FrameDev& F = frames[wi.frame];
     if constexpr (KIND == kKindResident)
       cg_item_resident(F, budget, B, red, stage_lds);
+    else if constexpr (KIND == kKindWindowed)
+      cg_item_win<REFRESH>(F, wi, budget, B, L, red, &sflag, stage_lds);
     else
-      cg_item<STORED, REFRESH, KIND == kKindStaged, KIND == kKindDirectFD>(F, wi, budget, B, L,
+      cg_item<SD, REFRESH, KIND == kKindStaged, KIND == kKindDirectFD>(F, wi, budget, B, L,
                                                                           red, redd, &sflag,
                                                     stage_lds);
     __syncthreads();
@@ -1431,7 +1860,7 @@ __global__ void k_xcc_probe(int* out) {
 // ---------------------------------------------------------------------------------------
 // standalone operator applications (one workgroup per tile)
 // ---------------------------------------------------------------------------------------
-template <bool ADJ, bool STORED>
+template <bool ADJ, int SD>
 __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ frames,
                                                   const WorkItem* __restrict__ items,
                                                   const float2* __restrict__ in,
@@ -1441,12 +1870,15 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ f
   extern __shared__ float2 stage_lds[];
   const int64_t E = (int64_t)F.M * F.N;
   const CVec dst = cvec(out + F.off, E);
-  if (!STORED && F.skc > 0)
-    apply_band<ADJ, STORED, true>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
-                                  OutStore<>{dst});
+  if (SD == kDNone && F.win_w > 0)
+    win_apply_any<ADJ>(F, wi.k_begin, stage_lds, src_vec(in + F.off, E), NoPref{},
+                       [&](int q, float2 v, NoPre) { dst.st((uint32_t)q, v); });
+  else if (SD == kDNone && F.skc > 0)
+    apply_band<ADJ, SD, true>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
+                              OutStore<>{dst});
   else
-    apply_band<ADJ, STORED, false>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
-                                   OutStore<>{dst});
+    apply_band<ADJ, SD, false>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
+                               OutStore<>{dst});
 }
 
 __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsigned* abort_flag,
@@ -1488,14 +1920,16 @@ __global__ void k_step_reset(const FrameDev* __restrict__ frames, int nframes,
   }
 }
 
-// Stored coefficients D_{p,q} (Eq. D_definition) of every frame as bf16 pairs.
+// Stored coefficients D_{p,q} (Eq. D_definition) of every frame, as bf16 pairs (SD =
+// kDBf16, rounded to nearest even) or complex64 (kDC64): the FP32 value the on-the-fly
+// synthesis forms for a gather of row q, path p.
+template <int SD>
 __global__ __launch_bounds__(kBlock) void k_build_d(const FrameDev* __restrict__ frames,
                                                     const WorkItem* __restrict__ items) {
   const WorkItem wi = items[blockIdx.x];
   const FrameDev& F = frames[wi.frame];
   const int M = F.M, N = F.N;
   const int64_t E = (int64_t)M * N;
-  uint32_t* d = const_cast<uint32_t*>(F.dtab);
   for (int64_t q = (int64_t)wi.l_begin * M + threadIdx.x; q < (int64_t)wi.l_end * M;
        q += kBlock) {
     const int k = (int)(q % M), l = (int)(q / M);
@@ -1512,7 +1946,11 @@ __global__ __launch_bounds__(kBlock) void k_build_d(const FrameDev* __restrict__
         if (n < 0) w.y = -w.y;
         c = cmulf(c, w);
       }
-      d[p * E + q] = f32_to_bf16(c.x) | (f32_to_bf16(c.y) << 16);
+      if constexpr (SD == kDC64)
+        static_cast<float2*>(const_cast<void*>(F.dtab))[p * E + q] = c;
+      else
+        static_cast<uint32_t*>(const_cast<void*>(F.dtab))[p * E + q] =
+            f32_to_bf16(c.x) | (f32_to_bf16(c.y) << 16);
     }
   }
 }
@@ -1548,7 +1986,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_init(const FrameDev* __restric
 __global__ void k_plain_start(const FrameDev* __restrict__ frames, int f) {
   if (threadIdx.x != 0) return;
   const FrameDev& F = frames[f];
-  const float cn0 = (float)tile_sum(F.part_cc, F.T);
+  const float cn0 = tile_sum(F.part_cc, F.T);
   FrameState s = *F.st;
   s.cn0 = cn0;
   s.cn_hist[0] = cn0;
@@ -1601,7 +2039,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_update(const FrameDev* __restr
   const FrameVecs V = frame_vecs(F, B);
   const WorkItem wi = items[blockIdx.x];
   const float cn = st->cn_hist[(xi - 1) & 1];
-  const float den = (float)tile_sum(F.part_pa, F.T);
+  const float den = tile_sum(F.part_pa, F.T);
   const float alpha = cn / den;
   if (!(den > 0.f) || !isfinite(alpha)) {
     if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -1629,7 +2067,7 @@ __global__ __launch_bounds__(kBlock) void k_plain_dir(const FrameDev* __restrict
   if (st->status != OTFS_FRAME_RUNNING) return;
   const WorkItem wi = items[blockIdx.x];
   const float cn = st->cn_hist[(xi - 1) & 1];
-  const float cn_new = (float)tile_sum(F.part_cc, F.T);
+  const float cn_new = tile_sum(F.part_cc, F.T);
   const float rel = sqrtf(cn_new / st->cn0);
   int status = OTFS_FRAME_RUNNING;
   if (!isfinite(cn_new))
@@ -1676,17 +2114,25 @@ __global__ __launch_bounds__(kBlock) void k_plain_finish(const FrameDev* __restr
 // ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
-hipError_t launch_apply(bool adjoint, bool stored, const FrameDev* frames, const WorkItem* items,
+hipError_t launch_apply(bool adjoint, int sd, const FrameDev* frames, const WorkItem* items,
                         int nitems, const float2* in, float2* out, int lds_bytes, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   const dim3 g(nitems), b(kBlock);
-  const int lb = stored ? 0 : lds_bytes;
+  const int lb = sd != kDNone ? 0 : lds_bytes;
+  if (lb > 0) {
+    const void* fn = adjoint ? reinterpret_cast<const void*>(&k_apply<true, kDNone>)
+                             : reinterpret_cast<const void*>(&k_apply<false, kDNone>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lb);
+    if (e != hipSuccess) return e;
+  }
   if (adjoint) {
-    if (stored) hipLaunchKernelGGL((k_apply<true, true>), g, b, lb, s, frames, items, in, out);
-    else hipLaunchKernelGGL((k_apply<true, false>), g, b, lb, s, frames, items, in, out);
+    if (sd == kDBf16) hipLaunchKernelGGL((k_apply<true, kDBf16>), g, b, lb, s, frames, items, in, out);
+    else if (sd == kDC64) hipLaunchKernelGGL((k_apply<true, kDC64>), g, b, lb, s, frames, items, in, out);
+    else hipLaunchKernelGGL((k_apply<true, kDNone>), g, b, lb, s, frames, items, in, out);
   } else {
-    if (stored) hipLaunchKernelGGL((k_apply<false, true>), g, b, lb, s, frames, items, in, out);
-    else hipLaunchKernelGGL((k_apply<false, false>), g, b, lb, s, frames, items, in, out);
+    if (sd == kDBf16) hipLaunchKernelGGL((k_apply<false, kDBf16>), g, b, lb, s, frames, items, in, out);
+    else if (sd == kDC64) hipLaunchKernelGGL((k_apply<false, kDC64>), g, b, lb, s, frames, items, in, out);
+    else hipLaunchKernelGGL((k_apply<false, kDNone>), g, b, lb, s, frames, items, in, out);
   }
   return hipGetLastError();
 }
@@ -1711,72 +2157,107 @@ hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abor
   return hipGetLastError();
 }
 
-static uint64_t wallclock_timeout_ticks() {
-  static uint64_t ticks = 0;
-  if (ticks == 0) {
+// ticks of the wall clock that the kernels' bounded waits read (s_memrealtime)
+static uint64_t wallclock_ticks_per_us() {
+  static uint64_t per_us = 0;
+  if (per_us == 0) {
     int dev = 0, khz = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
       khz = 100000;
-    ticks = (uint64_t)khz * 1000ull * 20ull;   // 20 s
+    per_us = std::max<uint64_t>(1, (uint64_t)khz / 1000ull);
   }
-  return ticks;
+  return per_us;
+}
+// wait_us < 0: the default bound of 20 s; 0: a wait gives up at its first unsatisfied poll
+static uint64_t wait_ticks(int64_t wait_us) {
+  if (wait_us < 0) wait_us = 20ll * 1000 * 1000;
+  return (uint64_t)wait_us * wallclock_ticks_per_us();
 }
 
-template <bool STORED, bool REFRESH, int KIND>
+template <int SD, bool REFRESH, int KIND>
 static void launch_fused_t(const FrameDev* frames, const WorkItem* items, const int32_t* qitems,
                            const int2* qrange, unsigned* qhead, int ngroups, int grid, int budget,
                            const Bases& bases, const LaunchCtx& L, int lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_fused<STORED, REFRESH, KIND>), dim3(grid), dim3(kBlock), lds_bytes, s,
+  hipLaunchKernelGGL((k_cg_fused<SD, REFRESH, KIND>), dim3(grid), dim3(kBlock), lds_bytes, s,
                      frames, items, qitems, qrange, qhead, ngroups, budget, bases, L);
 }
 
 // the instantiation of a launch kind: resident and staged frames use neither the stored
 // D nor (resident) the refresh, which the host guarantees
-static const void* fused_fn(int kind, bool stored, bool refresh) {
-  if (kind == kKindResident) return reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindResident>);
+template <int SD>
+static const void* fused_fn_sd(bool refresh) {
+  return refresh ? reinterpret_cast<const void*>(&k_cg_fused<SD, true, kKindDirect>)
+                 : reinterpret_cast<const void*>(&k_cg_fused<SD, false, kKindDirect>);
+}
+static const void* fused_fn(int kind, int sd, bool refresh) {
+  if (kind == kKindResident) return reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindResident>);
+  if (kind == kKindWindowed)
+    return (sd != kDNone || refresh)
+               ? nullptr
+               : reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindWindowed>);
   if (kind == kKindDirectFD)
-    return (stored || refresh) ? nullptr
-                               : reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindDirectFD>);
+    return (sd != kDNone || refresh)
+               ? nullptr
+               : reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindDirectFD>);
   if (kind == kKindStaged)
-    return refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true, kKindStaged>)
-                   : reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindStaged>);
-  if (stored)
-    return refresh ? reinterpret_cast<const void*>(&k_cg_fused<true, true, kKindDirect>)
-                   : reinterpret_cast<const void*>(&k_cg_fused<true, false, kKindDirect>);
-  return refresh ? reinterpret_cast<const void*>(&k_cg_fused<false, true, kKindDirect>)
-                 : reinterpret_cast<const void*>(&k_cg_fused<false, false, kKindDirect>);
+    return refresh ? reinterpret_cast<const void*>(&k_cg_fused<kDNone, true, kKindStaged>)
+                   : reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindStaged>);
+  if (sd == kDBf16) return fused_fn_sd<kDBf16>(refresh);
+  if (sd == kDC64) return fused_fn_sd<kDC64>(refresh);
+  return fused_fn_sd<kDNone>(refresh);
 }
 
-hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* frames,
+template <int SD>
+static void launch_direct_sd(bool refresh, const FrameDev* frames, const WorkItem* items,
+                             const int32_t* qitems, const int2* qrange, unsigned* qhead,
+                             int ngroups, int grid, int budget, const Bases& bases,
+                             const LaunchCtx& L, hipStream_t s) {
+  if (refresh)
+    launch_fused_t<SD, true, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+  else
+    launch_fused_t<SD, false, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+}
+
+hipError_t launch_cg_fused(int kind, int sd, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
-                           bool xcd_local, unsigned* abort_flag, int lds_bytes, hipStream_t s) {
+                           bool xcd_local, unsigned* abort_flag, int lds_bytes, int64_t wait_us,
+                           hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  LaunchCtx L{abort_flag, wallclock_timeout_ticks(), xcd_local ? 1 : 0};
+  LaunchCtx L{abort_flag, wait_ticks(wait_us), xcd_local ? 1 : 0};
   if (kind == kKindResident) {
-    launch_fused_t<false, false, kKindResident>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+    launch_fused_t<kDNone, false, kKindResident>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+  } else if (kind == kKindWindowed) {
+    if (sd != kDNone || refresh) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(fused_fn(kind, sd, refresh),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    launch_fused_t<kDNone, false, kKindWindowed>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
   } else if (kind == kKindDirectFD) {
-    if (stored || refresh) return hipErrorInvalidValue;
-    launch_fused_t<false, false, kKindDirectFD>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+    if (sd != kDNone || refresh) return hipErrorInvalidValue;
+    launch_fused_t<kDNone, false, kKindDirectFD>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
   } else if (kind == kKindStaged) {
-    if (refresh) launch_fused_t<false, true, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-    else launch_fused_t<false, false, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-  } else if (stored) {
-    if (refresh) launch_fused_t<true, true, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
-    else launch_fused_t<true, false, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+    if (refresh) launch_fused_t<kDNone, true, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+    else launch_fused_t<kDNone, false, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+  } else if (sd == kDBf16) {
+    launch_direct_sd<kDBf16>(refresh, frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+  } else if (sd == kDC64) {
+    launch_direct_sd<kDC64>(refresh, frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
   } else {
-    if (refresh) launch_fused_t<false, true, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
-    else launch_fused_t<false, false, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+    launch_direct_sd<kDNone>(refresh, frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
   }
   return hipGetLastError();
 }
 
-int fused_blocks_per_cu(int kind, bool stored, bool refresh, int lds_bytes) {
+int fused_blocks_per_cu(int kind, int sd, bool refresh, int lds_bytes) {
   int n = 0;
   if (kind == kKindDirect || kind == kKindDirectFD) lds_bytes = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_fn(kind, stored, refresh), kBlock,
-                                                   lds_bytes) != hipSuccess)
+  const void* fn = fused_fn(kind, sd, refresh);
+  if (!fn) return 0;
+  if (lds_bytes > 0)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, lds_bytes) != hipSuccess)
     n = 0;
   return n;
 }
@@ -1802,9 +2283,13 @@ hipError_t launch_plain_frame(const FrameDev* frames_dev, int f, const WorkItem*
   return hipGetLastError();
 }
 
-hipError_t launch_build_d(const FrameDev* frames, const WorkItem* items, int nitems, hipStream_t s) {
+hipError_t launch_build_d(int sd, const FrameDev* frames, const WorkItem* items, int nitems,
+                          hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_d, dim3(nitems), dim3(kBlock), 0, s, frames, items);
+  if (sd == kDC64)
+    hipLaunchKernelGGL(k_build_d<kDC64>, dim3(nitems), dim3(kBlock), 0, s, frames, items);
+  else
+    hipLaunchKernelGGL(k_build_d<kDBf16>, dim3(nitems), dim3(kBlock), 0, s, frames, items);
   return hipGetLastError();
 }
 

@@ -16,6 +16,13 @@ namespace otfs {
 constexpr int kBlock = OTFS_BLOCK;   // threads per workgroup of every kernel
 constexpr int kWaves = kBlock / 64;  // wave64
 
+// Coefficients D_{p,q}: synthesised on the fly from the delay-ramp and wrap tables, or read
+// from a stored P x E table (the SS representation of Eq. ds_repr) in bf16 or complex64.
+constexpr int kDNone = 0, kDBf16 = 1, kDC64 = 2;
+inline int stored_mode(uint32_t flags) {
+  return (flags & OTFS_D_STORED_C64) ? kDC64 : ((flags & OTFS_D_STORED_BF16) ? kDBf16 : kDNone);
+}
+
 // Per-frame CG scalars that persist between launches of the fused kernel (a serving step
 // ends in the middle of a frame's iteration loop and the next step resumes it).
 struct FrameState {
@@ -50,7 +57,7 @@ struct FrameDev {
   const double2* rtab64;  // FP64 copies of the two tables for the refresh (nullable)
   const double2* wtab64;
   const int2* paths;      // P x (tau_p, nu_p)
-  const uint32_t* dtab;   // stored D_{p,q} as bf16 pairs, P x E (nullable)
+  const void* dtab;       // stored D_{p,q}, P x E, bf16 pairs or complex64 (nullable)
   float* part_pa;         // T partial sums of Re(p^H a)
   float* part_cc;         // T partial sums of ||c||^2
   double* part_d;         // T FP64 partial sums (refresh)
@@ -77,15 +84,32 @@ struct FrameDev {
   // 1: the H pass of the split form stores t with the non-temporal policy (large frames,
   // whose vectors overflow L2 anyway); smaller frames keep t in L2 for the H^H gathers
   int32_t stream_t;
+  // windowed gathers (0 = off): the frame's tiles are strips of win_w delay columns over
+  // all Doppler rows, and each gather pass streams the source rows through an LDS window
+  // win_rc output rows at a time
+  int32_t win_w, win_rc;
 };
 
-// One workgroup's share of one frame: Doppler rows [l_begin, l_end), all delay columns.
+// One workgroup's share of one frame: Doppler rows [l_begin, l_end) of delay columns
+// [k_begin, k_end) (row bands span every column; windowed strips span every row).
 struct WorkItem {
   int32_t frame;
   int32_t tile;
   int32_t l_begin;
   int32_t l_end;
+  int32_t k_begin;
+  int32_t k_end;
 };
+
+// Windowed gathers: paths held in registers per thread (frames with more paths use the
+// other launch kinds), and 64-element row pieces each wave stages per chunk.
+constexpr int kWinPaths = 16;
+constexpr int kWinLoads = 6;
+// LDS bytes of a frame's window: (2 rc + d_nu) rows x (w + d_tau) complex64 columns,
+// with d_nu, d_tau the Doppler and delay shift ranges of its paths (both widened to 0)
+inline int win_lds_bytes(int w, int rc, int dtau, int dnu) {
+  return (2 * rc + dnu) * (w + dtau) * 8;
+}
 
 // Batch-wide buffers passed to a launch.  A null base means "use the per-frame pointer
 // in FrameDev" (server slots); otherwise the frame's data lives at base + off.
@@ -108,7 +132,7 @@ constexpr int kStageVecs = 2;    // vectors staged at once (phase A stages c and
 
 // One workgroup per item.  in/out are batch-wide complex64 buffers (frame at base + off).
 // lds_bytes: dynamic LDS for staged windows (0 if no frame is staged).
-hipError_t launch_apply(bool adjoint, bool stored, const FrameDev* frames, const WorkItem* items,
+hipError_t launch_apply(bool adjoint, int sd, const FrameDev* frames, const WorkItem* items,
                         int nitems, const float2* in, float2* out, int lds_bytes, hipStream_t s);
 
 // Reset barrier counters and CG state of frames [0, nframes), the abort word and the
@@ -132,17 +156,20 @@ hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abor
 // solve in LDS.
 // direct-fd: direct frames whose H pass forms the direction inside its gathers (batches
 // whose direct frames all have P <= kFusedDirMaxPaths)
-constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKindDirectFD = 3, kKinds = 4;
+// windowed: frames tiled into strips whose gathers stream source rows through an LDS ring
+constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKindDirectFD = 3,
+              kKindWindowed = 4, kKinds = 5;
 constexpr int kFusedDirMaxPaths = 8;
 // frames of at least this many elements stream t (see FrameDev::stream_t)
 constexpr int64_t kStreamTElems = 131072;
-hipError_t launch_cg_fused(int kind, bool stored, bool refresh, const FrameDev* frames,
+hipError_t launch_cg_fused(int kind, int sd, bool refresh, const FrameDev* frames,
                            const WorkItem* items, const int32_t* qitems, const int2* qrange,
                            unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
-                           bool xcd_local, unsigned* abort_flag, int lds_bytes, hipStream_t s);
+                           bool xcd_local, unsigned* abort_flag, int lds_bytes, int64_t wait_us,
+                           hipStream_t s);
 // Workgroups of the fused kernel of a launch kind that fit on one CU at once (occupancy)
 // with lds_bytes of dynamic LDS.
-int fused_blocks_per_cu(int kind, bool stored, bool refresh, int lds_bytes);
+int fused_blocks_per_cu(int kind, int sd, bool refresh, int lds_bytes);
 
 // out[b] = XCC id of workgroup b, for b < nblocks.
 hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
@@ -152,8 +179,8 @@ hipError_t launch_plain_frame(const FrameDev* frames_dev, int frame, const WorkI
                               int item_begin, int ntiles, int max_iters, Bases bases,
                               hipStream_t s);
 
-// Build the stored bf16 D table of every frame.
-hipError_t launch_build_d(const FrameDev* frames, const WorkItem* items, int nitems,
+// Build the stored D table of every frame (sd = kDBf16 or kDC64).
+hipError_t launch_build_d(int sd, const FrameDev* frames, const WorkItem* items, int nitems,
                           hipStream_t s);
 
 }  // namespace otfs

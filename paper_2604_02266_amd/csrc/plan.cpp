@@ -50,8 +50,11 @@ otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out) {
     return fail(OTFS_E_INVAL, "rel_tol must be finite and >= 0");
   if (d.refresh_every < 0) return fail(OTFS_E_INVAL, "refresh_every must be >= 0");
   const uint32_t known = OTFS_D_STORED_BF16 | OTFS_Y_BF16 | OTFS_USE_GRAPH | OTFS_TIME_KERNEL |
-                         OTFS_AGENT_BARRIER | OTFS_NO_LDS_RESIDENT | OTFS_SPLIT_DIRECTION;
+                         OTFS_AGENT_BARRIER | OTFS_NO_LDS_RESIDENT | OTFS_SPLIT_DIRECTION |
+                         OTFS_D_STORED_C64;
   if (d.flags & ~known) return fail(OTFS_E_INVAL, "unknown flag bits 0x%x", d.flags & ~known);
+  if ((d.flags & OTFS_D_STORED_BF16) && (d.flags & OTFS_D_STORED_C64))
+    return fail(OTFS_E_INVAL, "OTFS_D_STORED_BF16 and OTFS_D_STORED_C64 exclude each other");
   *out = d;
   return OTFS_OK;
 }
@@ -163,13 +166,15 @@ void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const 
   d->nu_hi = geo.nu_hi;
   d->resident = geo.resident;
   d->stream_t = (int64_t)fr.M * fr.N >= kStreamTElems ? 1 : 0;
+  d->win_w = geo.win_w;
+  d->win_rc = geo.win_rc;
 }
 
 int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opts& o,
                  int budget_bytes, FrameDev* geo) {
   std::memset(geo, 0, sizeof(FrameDev));
   const int64_t E = (int64_t)f.M * f.N;
-  const bool stored = (o.flags & OTFS_D_STORED_BF16) != 0;
+  const bool stored = stored_mode(o.flags) != kDNone;
   if (tiles == 1 && !stored && o.refresh_every == 0 && !(o.flags & OTFS_NO_LDS_RESIDENT) &&
       E * kResidentVecs * (int64_t)sizeof(float2) <= kResidentBytes) {
     stage_geometry(f, band_rows, 0, geo);   // shift ranges only; no staging
@@ -185,10 +190,13 @@ int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opt
 }
 
 int frame_kind(const FrameDev& geo) {
+  if (geo.win_w > 0) return kKindWindowed;
   return geo.resident ? kKindResident : (geo.skc > 0 ? kKindStaged : kKindDirect);
 }
 
 int frame_lds_bytes(const HostFrame& f, const FrameDev& geo) {
+  if (geo.win_w > 0)
+    return win_lds_bytes(geo.win_w, geo.win_rc, geo.tau_hi - geo.tau_lo, geo.nu_hi - geo.nu_lo);
   if (geo.resident) return (int)((int64_t)f.M * f.N * kResidentVecs * (int64_t)sizeof(float2));
   if (geo.skc > 0) return kStageVecs * geo.swin * (int)sizeof(float2);
   return 0;
@@ -196,7 +204,7 @@ int frame_lds_bytes(const HostFrame& f, const FrameDev& geo) {
 
 otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vector<FrameDev>& geo,
                           const std::vector<int>& tile_base, const std::vector<int>& tiles,
-                          bool stored, bool refresh, bool split_dir, int cus, int cap_override,
+                          int sd, bool refresh, bool split_dir, int cus, int cap_override,
                           const XcdInfo& xi, bool agent, std::vector<int32_t>& qitems,
                           std::vector<int2>& qrange, std::vector<KindLaunch>& out) {
   qitems.clear();
@@ -205,7 +213,7 @@ otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vecto
   // The H pass forms the direction inside its gathers when the direct frames have few
   // paths: the gathers then read two vectors, which costs more than the separate
   // direction pass saves once P is large (measured on the 16-path batches).
-  bool fdir = !stored && !refresh && !split_dir;
+  bool fdir = sd == kDNone && !refresh && !split_dir;
   for (size_t f = 0; f < frames.size(); ++f)
     if (frame_kind(geo[f]) == kKindDirect && frames[f].P > kFusedDirMaxPaths) fdir = false;
   auto kind_of = [&](size_t f) {
@@ -224,7 +232,7 @@ otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vecto
       lds = std::max(lds, frame_lds_bytes(frames[f], geo[f]));
     }
     if (fs.empty()) continue;
-    const int bpc = std::max(1, fused_blocks_per_cu(kind, stored, refresh, lds));
+    const int bpc = std::max(1, fused_blocks_per_cu(kind, sd, refresh, lds));
     int cap = bpc * cus;
     if (cap_override > 0) cap = std::min(cap, cap_override);
     KindLaunch L;
@@ -287,13 +295,54 @@ int default_tile_elems(int64_t total_elems, int cus) {
   return (int)te;
 }
 
+// Delay and Doppler shift ranges of a frame's paths, widened to contain 0.
+static void shift_ranges(const HostFrame& f, int* tlo, int* thi, int* vlo, int* vhi) {
+  *tlo = *thi = *vlo = *vhi = 0;
+  for (int p = 0; p < f.P; ++p) {
+    *tlo = std::min(*tlo, f.tau[p]);
+    *thi = std::max(*thi, f.tau[p]);
+    *vlo = std::min(*vlo, f.nu[p]);
+    *vhi = std::max(*vhi, f.nu[p]);
+  }
+}
+
+int window_width(const HostFrame& f, int w, int rc) {
+  if (w <= 0 || rc <= 0) return 0;
+  if (w % 64 != 0 || kBlock % w != 0 || f.M % w != 0) return 0;
+  if (f.P > kWinPaths || rc > f.N) return 0;
+  const int ty = kBlock / w;
+  if (rc != 2 * ty && rc != 4 * ty) return 0;   // 2 or 4 output rows per thread and chunk
+  int tlo, thi, vlo, vhi;
+  shift_ranges(f, &tlo, &thi, &vlo, &vhi);
+  const int dtau = thi - tlo, dnu = vhi - vlo;
+  if (rc * ((w + dtau + 63) / 64) > kWaves * kWinLoads) return 0;
+  if (win_lds_bytes(w, rc, dtau, dnu) > kMaxLdsBytes) return 0;
+  return w;
+}
+
 void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vector<WorkItem>& items,
-                std::vector<int>& tile_base, std::vector<int>& tiles) {
+                std::vector<int>& tile_base, std::vector<int>& tiles, const std::vector<int>* winw) {
   items.clear();
   tile_base.assign(frames.size(), 0);
   tiles.assign(frames.size(), 0);
   for (size_t f = 0; f < frames.size(); ++f) {
     const HostFrame& fr = frames[f];
+    const int w = winw ? (*winw)[f] : 0;
+    if (w > 0) {   // windowed: strips of w delay columns over all rows
+      tile_base[f] = (int)items.size();
+      tiles[f] = fr.M / w;
+      for (int t = 0; t < fr.M / w; ++t) {
+        WorkItem it;
+        it.frame = (int)f;
+        it.tile = t;
+        it.l_begin = 0;
+        it.l_end = fr.N;
+        it.k_begin = t * w;
+        it.k_end = (t + 1) * w;
+        items.push_back(it);
+      }
+      continue;
+    }
     const int64_t E = (int64_t)fr.M * fr.N;
     int64_t T = (E + tile_elems / 2) / tile_elems;
     T = std::max<int64_t>(1, std::min<int64_t>(T, fr.N));
@@ -305,6 +354,8 @@ void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vecto
       w.tile = t;
       w.l_begin = (int)((int64_t)t * fr.N / T);
       w.l_end = (int)((int64_t)(t + 1) * fr.N / T);
+      w.k_begin = 0;
+      w.k_end = fr.M;
       items.push_back(w);
     }
   }
@@ -444,7 +495,7 @@ void compute_layout(otfs_plan_t* pl) {
   }
   const size_t E = (size_t)pl->total_elems;
   const bool refresh = pl->opts.refresh_every > 0;
-  const bool stored = (pl->opts.flags & OTFS_D_STORED_BF16) != 0;
+  const int sd = stored_mode(pl->opts.flags);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -476,8 +527,20 @@ void compute_layout(otfs_plan_t* pl) {
   L.t = take(Ep * sizeof(float2));
   L.a = take(Ep * sizeof(float2));
   L.u = refresh ? take(Ep * sizeof(double2)) : 0;
-  L.dtab = stored ? take(dt * sizeof(uint32_t)) : 0;
+  L.dtab = sd == kDNone ? 0 : take(dt * (sd == kDC64 ? sizeof(float2) : sizeof(uint32_t)));
   L.total = std::max<size_t>(o, 256);
+}
+
+// Per-frame window widths, tiles and workspace layout after a change of the tiling or the
+// windowed form.
+void retile(otfs_plan_t* pl) {
+  pl->winw.assign(pl->frames.size(), 0);
+  // the windowed kind synthesises D and has no refresh passes: those modes keep row bands
+  const bool win_ok = stored_mode(pl->opts.flags) == kDNone && pl->opts.refresh_every == 0;
+  for (size_t f = 0; f < pl->frames.size() && win_ok; ++f)
+    pl->winw[f] = window_width(pl->frames[f], pl->win_w_req, pl->win_rc_req);
+  make_tiles(pl->frames, pl->tile_elems, pl->items, pl->tile_base, pl->tiles, &pl->winw);
+  compute_layout(pl);
 }
 
 }  // namespace otfs
@@ -527,8 +590,7 @@ extern "C" otfs_status otfs_plan(const otfs_frame_desc* frames, int32_t nframes,
   (void)hipGetLastError();
   pl->cus = cus;
   pl->tile_elems = default_tile_elems(total, cus);
-  make_tiles(pl->frames, pl->tile_elems, pl->items, pl->tile_base, pl->tiles);
-  compute_layout(pl);
+  retile(pl);
   *out = pl;
   return OTFS_OK;
 }
@@ -578,8 +640,20 @@ extern "C" otfs_status otfs_plan_set_tiling(otfs_plan_t* plan, int32_t tile_elem
     return fail(OTFS_E_INVAL, "tile_elems and max_grid must be >= 0");
   plan->tile_elems = tile_elems > 0 ? tile_elems : default_tile_elems(plan->total_elems, plan->cus);
   plan->max_grid_req = max_grid;
-  make_tiles(plan->frames, plan->tile_elems, plan->items, plan->tile_base, plan->tiles);
-  compute_layout(plan);
+  retile(plan);
+  plan->bound = false;
+  plan->drop_graph();
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_set_window(otfs_plan_t* plan, int32_t strip_cols,
+                                            int32_t chunk_rows) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  if (strip_cols < 0 || chunk_rows < 0)
+    return fail(OTFS_E_INVAL, "strip_cols and chunk_rows must be >= 0");
+  plan->win_w_req = strip_cols > 0 && chunk_rows > 0 ? strip_cols : 0;
+  plan->win_rc_req = strip_cols > 0 && chunk_rows > 0 ? chunk_rows : 0;
+  retile(plan);
   plan->bound = false;
   plan->drop_graph();
   return OTFS_OK;
@@ -619,6 +693,12 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
       band = std::max(band, w.l_end - w.l_begin);
     }
     lds_geometry(plan->frames[f], plan->tiles[f], band, plan->opts, plan->stage_bytes, &geo[f]);
+    if (plan->winw[f] > 0) {   // windowed strips: no staging, not resident
+      geo[f].resident = 0;
+      geo[f].skc = geo[f].ssb = geo[f].swin = 0;
+      geo[f].win_w = plan->winw[f];
+      geo[f].win_rc = plan->win_rc_req;
+    }
   }
 
   // work queues of the fused kernel (need the occupancy and XCD layout of this device)
@@ -630,7 +710,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   otfs_status pst = probe_xcds(dev, static_cast<char*>(ws) + plan->L.probe, s, &xi);
   if (pst != OTFS_OK) return pst;
   pst = plan_launches(plan->frames, geo, plan->tile_base, plan->tiles,
-                      (plan->opts.flags & OTFS_D_STORED_BF16) != 0, plan->opts.refresh_every > 0,
+                      stored_mode(plan->opts.flags), plan->opts.refresh_every > 0,
                       (plan->opts.flags & OTFS_SPLIT_DIRECTION) != 0, cus, plan->max_grid_req, xi,
                       (plan->opts.flags & OTFS_AGENT_BARRIER) != 0,
                       plan->qitems, plan->qrange, plan->launches);
@@ -644,7 +724,8 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   std::vector<FrameDev> fd(plan->frames.size());
   size_t ro = 0, wo = 0, po = 0, dto = 0;
   const bool refresh = plan->opts.refresh_every > 0;
-  const bool stored = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
+  const int sd = stored_mode(plan->opts.flags);
+  const size_t dsz = sd == kDC64 ? sizeof(float2) : sizeof(uint32_t);
   for (size_t f = 0; f < plan->frames.size(); ++f) {
     const HostFrame& fr = plan->frames[f];
     FrameDev& d = fd[f];
@@ -665,7 +746,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
     d.rtab64 = refresh ? reinterpret_cast<const double2*>(base + L.rtab64) + ro : nullptr;
     d.wtab64 = refresh ? reinterpret_cast<const double2*>(base + L.wtab64) + wo : nullptr;
     d.paths = reinterpret_cast<const int2*>(base + L.paths) + po;
-    d.dtab = stored ? reinterpret_cast<const uint32_t*>(base + L.dtab) + dto : nullptr;
+    d.dtab = sd != kDNone ? static_cast<const void*>(base + L.dtab + dto * dsz) : nullptr;
     const int tb = plan->tile_base[f];
     d.part_pa = reinterpret_cast<float*>(base + L.part_pa) + tb;
     d.part_cc = reinterpret_cast<float*>(base + L.part_cc) + tb;
@@ -714,8 +795,8 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   plan->d_qrange = reinterpret_cast<int2*>(base + L.qrange);
   plan->d_qhead = reinterpret_cast<unsigned*>(base + L.qhead);
   plan->d_abort = reinterpret_cast<unsigned*>(base + L.abort);
-  if (stored) {
-    if ((e = launch_build_d(plan->d_frames, plan->d_items, (int)plan->items.size(), s)) != hipSuccess)
+  if (sd != kDNone) {
+    if ((e = launch_build_d(sd, plan->d_frames, plan->d_items, (int)plan->items.size(), s)) != hipSuccess)
       return hip_fail(e, "build D");
   }
   // the host arrays above must outlive the copies
@@ -749,11 +830,14 @@ static otfs_status apply_common(const otfs_plan_t* plan, bool adj, const void* i
   if (plan->total_elems == 0) return OTFS_OK;
   if (!in || !out) return fail(OTFS_E_INVAL, "input and output must be non-null");
   if (in == out) return fail(OTFS_E_INVAL, "input and output must be distinct buffers");
-  const bool stored = (plan->opts.flags & OTFS_D_STORED_BF16) != 0;
-  int lds = 0;   // staged frames stage their windows here too
+  const int sd = stored_mode(plan->opts.flags);
+  int lds = 0;   // staged frames stage their windows here too, windowed frames their rings
   for (const KindLaunch& L : plan->launches)
     if (L.kind == kKindStaged) lds = L.lds_bytes;
-  hipError_t e = launch_apply(adj, stored, plan->d_frames, plan->d_items, (int)plan->items.size(),
+  for (const FrameDev& d : plan->h_frames)
+    if (d.win_w > 0)
+      lds = std::max(lds, win_lds_bytes(d.win_w, d.win_rc, d.tau_hi - d.tau_lo, d.nu_hi - d.nu_lo));
+  hipError_t e = launch_apply(adj, sd, plan->d_frames, plan->d_items, (int)plan->items.size(),
                               static_cast<const float2*>(in), static_cast<float2*>(out), lds,
                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, adj ? "apply H^H" : "apply H");
@@ -774,11 +858,11 @@ static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_begin, s)) != hipSuccess) return e;
   for (const KindLaunch& L : plan->launches) {
-    e = launch_cg_fused(L.kind, (plan->opts.flags & OTFS_D_STORED_BF16) != 0,
+    e = launch_cg_fused(L.kind, stored_mode(plan->opts.flags),
                         plan->opts.refresh_every > 0, plan->d_frames, plan->d_items,
                         plan->d_qitems, plan->d_qrange + L.qbase, plan->d_qhead + L.qbase,
                         L.ngroups, L.grid, plan->opts.max_iters, B, L.xcd_local, plan->d_abort,
-                        L.lds_bytes, s);
+                        L.lds_bytes, plan->wait_us, s);
     if (e != hipSuccess) return e;
   }
   if (timed && (e = hipEventRecord(plan->ev_end, s)) != hipSuccess) return e;
@@ -841,7 +925,7 @@ extern "C" otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y, voi
   if (y == xhat) return fail(OTFS_E_INVAL, "y and xhat must be distinct buffers");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Bases B{y, static_cast<float2*>(xhat), sym, stats};
-  if (plan->opts.flags & OTFS_D_STORED_BF16)
+  if (stored_mode(plan->opts.flags) != kDNone)
     return fail(OTFS_E_UNSUPPORTED, "the plain form synthesises D on the fly only");
   hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort,
                               plan->d_qhead, kKinds * kMaxGroups, s);
@@ -851,6 +935,13 @@ extern "C" otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y, voi
                            plan->tiles[f], plan->opts.max_iters, B, s);
     if (e != hipSuccess) return hip_fail(e, "plain CG launch");
   }
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_set_wait_limit(otfs_plan_t* plan, int64_t wait_us) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  plan->wait_us = wait_us < 0 ? -1 : wait_us;
+  plan->drop_graph();
   return OTFS_OK;
 }
 

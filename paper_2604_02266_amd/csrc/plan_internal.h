@@ -51,8 +51,15 @@ void wrap_factors(const HostFrame& f, std::vector<double2>& out);
 void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const FrameDev& geo,
                    FrameDev* d);
 int default_tile_elems(int64_t total_elems, int cus);
+// Tiles of every frame: strips of winw[f] delay columns over all rows for windowed frames
+// (winw non-null and winw[f] > 0), else bands of Doppler rows of about tile_elems elements.
 void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vector<WorkItem>& items,
-                std::vector<int>& tile_base, std::vector<int>& tiles);
+                std::vector<int>& tile_base, std::vector<int>& tiles,
+                const std::vector<int>* winw = nullptr);
+// Strip width a frame runs with in the windowed form for a requested strip width w and
+// chunk of rc rows, or 0 when the frame does not meet the form's limits.
+int window_width(const HostFrame& f, int w, int rc);
+constexpr int kMaxLdsBytes = 160 * 1024;
 // Work queues of the fused kernel.  ngroups groups (one per XCD in XCD-local mode, else
 // one); every frame's tiles go, consecutively, to one group; groups are balanced by work.
 // per_group_cap: workgroups one group can hold resident.  Returns false if some frame has
@@ -66,6 +73,7 @@ struct XcdInfo {
   bool round_robin = false;  // workgroup b ran on XCD b % nxcd for every probed b
 };
 otfs_status probe_xcds(int device, void* scratch_dev, hipStream_t s, XcdInfo* out);
+void retile(struct ::otfs_plan* pl);
 // Staged-gather geometry of one frame whose widest tile has band_rows rows: fills
 // skc/ssb (0 = direct gathers) and the shift ranges; returns the window size in elements.
 int stage_geometry(const HostFrame& f, int band_rows, int budget_elems, FrameDev* d);
@@ -98,7 +106,7 @@ int frame_lds_bytes(const HostFrame& f, const FrameDev& geo);
 // is false.  Fails if a frame has more tiles than can be resident at once.
 otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vector<FrameDev>& geo,
                           const std::vector<int>& tile_base, const std::vector<int>& tiles,
-                          bool stored, bool refresh, bool split_dir, int cus, int cap_override,
+                          int sd, bool refresh, bool split_dir, int cus, int cap_override,
                           const XcdInfo& xi, bool agent, std::vector<int32_t>& qitems,
                           std::vector<int2>& qrange, std::vector<KindLaunch>& out);
 
@@ -111,6 +119,9 @@ struct otfs_plan {
   int max_paths = 0, cus = 256;
   int tile_elems = 0, max_grid_req = 0;
   int stage_bytes = otfs::kDefaultStageBytes;   // LDS budget for staged windows, 0 = off
+  int64_t wait_us = -1;   // bound of the kernels' waits (-1: the default 20 s)
+  int win_w_req = 0, win_rc_req = 0;   // windowed form (0: off)
+  std::vector<int> winw;               // per frame: strip width of the windowed form, or 0
   // tiling (host) and schedule (chosen at bind)
   std::vector<otfs::WorkItem> items;
   std::vector<int> tile_base, tiles;

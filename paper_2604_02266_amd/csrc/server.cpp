@@ -406,7 +406,7 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   std::vector<FrameDev> geo(n);
   for (int i = 0; i < n; ++i) geo[i] = act[i]->geo;
   std::vector<KindLaunch> launches;
-  if (plan_launches(frames, geo, tile_base, tiles, false, S->opts.refresh_every > 0,
+  if (plan_launches(frames, geo, tile_base, tiles, kDNone, S->opts.refresh_every > 0,
                     (S->opts.flags & OTFS_SPLIT_DIRECTION) != 0, S->cus, 0, S->xcd, (S->opts.flags & OTFS_AGENT_BARRIER) != 0, qitems, qrange,
                     launches) != OTFS_OK) {
     set_failed(S, otfs_last_error());
@@ -430,12 +430,12 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   Bases B{nullptr, nullptr, nullptr, nullptr};
   for (const KindLaunch& L : launches) {
     if (e != hipSuccess) break;
-    e = launch_cg_fused(L.kind, false, S->opts.refresh_every > 0, dframes,
+    e = launch_cg_fused(L.kind, kDNone, S->opts.refresh_every > 0, dframes,
                         reinterpret_cast<const WorkItem*>(P + C.items),
                         reinterpret_cast<const int32_t*>(P + C.qitems),
                         reinterpret_cast<const int2*>(P + C.qrange) + L.qbase, qhead + L.qbase,
                         L.ngroups, L.grid, S->step_iters, B, L.xcd_local, abort_flag,
-                        L.lds_bytes, S->s);
+                        L.lds_bytes, -1, S->s);
   }
   out.resize(n);
   if (e == hipSuccess)
@@ -494,7 +494,7 @@ bool scheduler_init(otfs_server* S) {
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess && v > 0)
     S->cus = v;
   // the tile cap of a frame: workgroups of the direct kind resident at once
-  S->cap = std::max(1, fused_blocks_per_cu(kKindDirect, false, S->opts.refresh_every > 0, 0)) * S->cus;
+  S->cap = std::max(1, fused_blocks_per_cu(kKindDirect, kDNone, S->opts.refresh_every > 0, 0)) * S->cus;
   return true;
 }
 
@@ -601,8 +601,8 @@ extern "C" otfs_status otfs_server_create(int device, void* pool_dev, size_t poo
   otfs_cg_opts o{};
   otfs_status st = validate_opts(opts, &o);
   if (st != OTFS_OK) return st;
-  if (o.flags & (OTFS_D_STORED_BF16 | OTFS_Y_BF16))
-    return fail(OTFS_E_UNSUPPORTED, "the bf16 flags are not supported by the server");
+  if (o.flags & (OTFS_D_STORED_BF16 | OTFS_D_STORED_C64 | OTFS_Y_BF16))
+    return fail(OTFS_E_UNSUPPORTED, "the stored-D and bf16 flags are not supported by the server");
   if (device >= 0) {
     if (!pool_dev) return fail(OTFS_E_INVAL, "pool_dev is null");
     if ((reinterpret_cast<uintptr_t>(pool_dev) & 255u) != 0)

@@ -369,27 +369,52 @@ def test_cg_bf16_stored_mode(otfs):
         assert st["status"][i] in (O_CONV, O_CAP)
 
 
-def _full_config(otfs, name, sample, tol):
+def test_wait_limit_gives_up_cleanly(otfs):
+    # The host shortens the bound of the kernel's own waits to nothing: waits that are not
+    # satisfied at once give up, the launch-wide abort word ends every other wait, the
+    # affected frames report OTFS_FRAME_TIMEOUT and every workgroup exits normally.  The
+    # same plan with the default bound then solves the batch correctly.
     import torch
-    frames = list(W.iter_frames(name))
-    say("full size", name, len(frames), "frames")
+    frames = _mixed_frames(51, 12, [(256, 64), (128, 32), (512, 16)], (3, 8), 12, 4)
     ops, xs, y = oracle_batch(frames)
-    plan = otfs.Plan([f.spec for f in frames], max_iters=frames[0].spec.max_iters,
-                     rel_tol=frames[0].spec.tol)
+    plan = otfs.Plan([f.spec for f in frames], tile_elems=1024, flags=otfs.NO_LDS_RESIDENT)
+    assert plan.info().grid > len(frames)
+    say("wait limit 0")
+    plan.set_wait_limit(0)
     x, sym, st = _run(otfs, plan, y)
-    assert np.all(np.isin(st["status"], [O_CONV, O_CAP]))
-    xsplit, ysplit, ssplit = split(x, frames), split(y, frames), split(sym, frames)
-    for i in sample:
-        sp = frames[i].spec
-        xr, it_r, rel_r = O.cg_lmmse(ysplit[i], ops[i], sp.lam, sp.max_iters, sp.tol)
-        assert O.nmse(xsplit[i], xr) <= tol, (name, i)
-        check_decisions(ssplit[i], xsplit[i], xr, sp.qam)
-    return plan
+    say("  statuses", list(st["status"]))
+    assert np.all(np.isin(st["status"], [O_CONV, O_CAP, 5]))
+    assert np.count_nonzero(st["status"] == 5) >= 1
+    say("default wait limit again")
+    plan.set_wait_limit(-1)
+    _cg_check(_run(otfs, plan, y), frames, ops, y, NMSE_TOL)
 
 
-def test_full_size_batch64_512x128_sampled(otfs):
-    _full_config(otfs, "batch64_512x128", [0, 31, 63], NMSE_TOL)
-
-
-def test_full_size_uneven256_sampled(otfs):
-    _full_config(otfs, "uneven256", [0, 1, 2, 3, 128, 255], NMSE_TOL)
+def test_cg_stored_c64_table(otfs):
+    # the SS table of Eq. ds_repr kept in complex64: same results as the on-the-fly
+    # coefficients up to the rounding of the wrap factors, on every wrap case
+    rng = np.random.default_rng(61)
+    specs = _edge_specs(rng)
+    say("stored c64 apply parity", [(s.M, s.N, s.P) for s in specs])
+    plan = otfs.Plan(specs, flags=otfs.D_STORED_C64)
+    E = plan.total_elems
+    x = _rand_c(rng, E)
+    y = _rand_c(rng, E)
+    yh = plan.apply_H(to_dev(x)).cpu().numpy()
+    xh = plan.apply_HH(to_dev(y)).cpu().numpy()
+    o = 0
+    for s in specs:
+        op = O.TwistedConvChannel(s.M, s.N, s.h, s.tau, s.nu)
+        sl = slice(o, o + s.E)
+        scale = np.abs(s.h).sum()
+        assert np.abs(yh[sl] - op.apply(x[sl].astype(np.complex128))).max() <= \
+            1e-5 * scale * np.abs(x[sl]).max(), (s.M, s.N)
+        assert np.abs(xh[sl] - op.apply_adjoint(y[sl].astype(np.complex128))).max() <= \
+            1e-5 * scale * np.abs(y[sl]).max(), (s.M, s.N)
+        o += s.E
+    frames = _mixed_frames(62, 6, [(128, 32), (64, 16), (256, 16)], (2, 12), 10, 4)
+    ops, xs, yy = oracle_batch(frames)
+    say("cg stored c64 table, refresh every 10")
+    plan = otfs.Plan([f.spec for f in frames], refresh_every=10, tile_elems=1024,
+                     flags=otfs.D_STORED_C64)
+    _cg_check(_run(otfs, plan, yy), frames, ops, yy, NMSE_TOL)

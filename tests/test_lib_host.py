@@ -67,10 +67,24 @@ def test_invalid_options_are_rejected():
         assert ei.value.status == otfs.E_INVAL and msg in str(ei.value)
     # every documented flag is accepted
     for f in (otfs.NO_LDS_RESIDENT, otfs.SPLIT_DIRECTION, otfs.AGENT_BARRIER,
-              otfs.TIME_KERNEL):
+              otfs.TIME_KERNEL, otfs.D_STORED_C64, otfs.D_STORED_BF16):
         _plan(fr, flags=f)
     with pytest.raises(otfs.OtfsError):
-        _plan(fr, flags=1 << 7)
+        _plan(fr, flags=1 << 8)
+    # the two stored tables exclude each other
+    with pytest.raises(otfs.OtfsError) as ei:
+        _plan(fr, flags=otfs.D_STORED_C64 | otfs.D_STORED_BF16)
+    assert ei.value.status == otfs.E_INVAL and "exclude" in str(ei.value)
+
+
+def test_stored_tables_size_the_workspace():
+    # P x E entries of 4 (bf16 pair) or 8 (complex64) bytes on top of the on-the-fly plan
+    fr = [_F(64, 16, [1, 2, 3], [0, 1, -1], np.array([1.0, 0.5, 0.25]))]
+    base = _plan(fr).workspace_bytes()[0]
+    bf = _plan(fr, flags=otfs.D_STORED_BF16).workspace_bytes()[0]
+    c64 = _plan(fr, flags=otfs.D_STORED_C64).workspace_bytes()[0]
+    assert bf - base >= 3 * 1024 * 4 and bf - base < 3 * 1024 * 4 + 512
+    assert c64 - base >= 3 * 1024 * 8 and c64 - base < 3 * 1024 * 8 + 512
 
 
 def test_empty_batch_and_unbound_use(L):
