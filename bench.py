@@ -3,9 +3,15 @@
 
 One step = one fused CG-LMMSE solve (Algorithm 1 with the relative-residual stop) of the
 whole batch of the named workload, every iteration applying H and H^H on the fly, with
-hard decisions.  Inputs (the received frames y) are synthesised on the GPU before the
-timed region: QAM symbols from the seeded generator, y = H x + w with the library's own
-otfs_apply_H and the generator's noise.  Prints one JSON line.
+hard decisions.  The headline workload is the largest one-GPU batch: 128 frames of
+(M, N) = (1024, 256), P = 16, 64-QAM, 30 dB, complex64 with the FP64 true-residual
+refresh every 10 iterations.
+
+The received frames y = H x + w are made by the FP64 oracle (complex128, rounded once to
+complex64) in worker processes before this process touches the GPU; the GPU solves
+exactly those y, inputs resident in HBM before the timed region.  The oracle's CG on a
+spread sample of the frames is the cpu_baseline leg (timed on this host's cores) and the
+reference for the line's NMSE and decision checks.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -13,6 +19,7 @@ import argparse
 import hashlib
 import json
 import math
+import multiprocessing
 import os
 import sys
 import time
@@ -22,21 +29,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "equalized OTFS symbols/sec (CG-LMMSE) @NMSE≤1e-5; p99 frame latency"
 PEAK_HBM_GBS = 8000.0
+NMSE_TARGET = 1e-5
+DECISION_FP32_SLACK = 2.0 ** -20   # rounding allowance of an FP32 decision (signal units)
 KERNEL_SRC = os.path.join(ROOT, "paper_2604_02266_amd", "csrc", "kernels.hip")
+MAX_WORKERS = 16          # the CPU share of one GPU on the benchmark hosts
+# FP64 refresh period per workload (the 128 x (1024, 256) configuration asks for 10)
+REFRESH = {"batch128_1024x256": 10}
+SECONDARY = "batch64_512x128"
+SWEEP_RATES = (2000, 5000, 10000, 20000, 30000, 40000, 50000)
 
 # Algorithmic bytes per element (complex64 vectors, 8 B per element; hard decisions 1 B),
-# counted on the three-phase schedule of Algorithm 1 with the direction formed where the
-# H product reads it (what the benchmark batch runs):
+# counted on the three-phase schedule of Algorithm 1:
 #   init    b = H^H y -> c, p, x = 0              read y (8)            write c, p, x (24)
 #   per iteration
 #     P1: x += alpha p, p' = c + beta p, t = H p'  read x, c, p (24)     write x, p', t (24)
 #     P2: a = H^H t + lam p'                      read t, p' (16)       write a (8)
 #     P3: c -= alpha a                            read c, a (16)        write c (8)
 #   finish  x += alpha p, decisions               read x, p (16)        write x (8), sym (1)
+#   refresh (every k iterations) c = H^H (y - H x) - lam x: 40 B per element
 # Gathered re-reads of a vector inside a pass, index tables and coefficients are not
-# counted.  (Batches with more than 8 paths per frame form p' in a pass of its own, which
-# moves 8 B more per element and iteration; those bytes are not counted either.)
-BYTES_INIT, BYTES_ITER, BYTES_FINISH = 32.0, 96.0, 25.0
+# counted.
+BYTES_INIT, BYTES_ITER, BYTES_FINISH, BYTES_REFRESH = 32.0, 96.0, 25.0, 40.0
 
 
 def kernel_source_sha() -> str:
@@ -44,139 +57,269 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def qam_points_torch(torch, sym, Q):
-    m = int(round(math.sqrt(Q)))
-    s = math.sqrt(2.0 * (Q - 1) / 3.0)
-    i_i = torch.div(sym, m, rounding_mode="floor")
-    i_q = sym - i_i * m
-    re = (2 * i_i - (m - 1)).to(torch.float32) / s
-    im = (2 * i_q - (m - 1)).to(torch.float32) / s
-    return torch.complex(re, im)
+# ----------------------------------------------------------------------------------------
+# CPU side: the oracle in worker processes (forked before this process touches the GPU)
+# ----------------------------------------------------------------------------------------
+def _worker_init():
+    # one BLAS thread per worker process (the library was loaded before the fork, so the
+    # environment variables alone would come too late): the workers already fill the cores
+    for v in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
+        os.environ[v] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
 
 
-def _cpu_worker(args):
-    os.environ["OMP_NUM_THREADS"] = "1"
-    os.environ["MKL_NUM_THREADS"] = "1"
-    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+def _job_received(frame):
     import oracle as O
-    frame = args
-    op, x, y = O.received_frame(frame)
+    _, _, y = O.received_frame(frame)
+    return y
+
+
+def _job_solve(args):
+    """The oracle as it stands: its operator and its FP64 CG on the given y, timed."""
+    import oracle as O
+    frame, y = args
+    sp = frame.spec
     t0 = time.perf_counter()
-    O.cg_lmmse(y, op, frame.spec.lam, frame.spec.max_iters, frame.spec.tol)
-    return time.perf_counter() - t0, frame.spec.E
+    op = O.TwistedConvChannel(sp.M, sp.N, sp.h, sp.tau, sp.nu)
+    x, it, rel = O.cg_lmmse(y, op, sp.lam, sp.max_iters, sp.tol)
+    return x, it, rel, time.perf_counter() - t0
 
 
-def _warm(_):
-    import oracle  # noqa: F401
-    return 0
+def spread(n, k):
+    """k indices spread evenly over range(n)."""
+    k = min(k, n)
+    return sorted({int(round(i * (n - 1) / max(k - 1, 1))) for i in range(k)})
 
 
-def cpu_baseline(frames, nsample):
-    """The FP64 oracle on a bounded sample of the workload's frames, one frame per worker
-    process, wall clock over the whole sample (y synthesis excluded)."""
-    from concurrent.futures import ProcessPoolExecutor
-    sample = frames[:nsample]
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    workers = max(1, min(cores, len(sample), 16))
-    import multiprocessing
-    with ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("fork")) as ex:
-        list(ex.map(_warm, range(workers)))                  # imports outside the timing
-        t0 = time.perf_counter()
-        res = list(ex.map(_cpu_worker, sample))
-        wall = time.perf_counter() - t0
-    syms = sum(e for _, e in res)
-    return {"value": syms / wall, "unit": "symbols/s", "cores": workers, "kind": "oracle",
-            "sample": f"{len(sample)} of {len(frames)} frames, FP64 NumPy CG with the same stop "
-                      f"rule, {workers} processes, {wall:.1f} s wall, "
-                      f"{sum(t for t, _ in res):.1f} s CPU"}
+def cpu_phase(pool, workers, frames, sample, timed):
+    """Oracle-made y for every frame, then the oracle's CG on the sample frames (the
+    cpu_baseline leg when timed)."""
+    ys = pool.map(_job_received, frames, chunksize=1)
+    t0 = time.perf_counter()
+    res = pool.map(_job_solve, [(frames[i], ys[i]) for i in sample], chunksize=1)
+    wall = time.perf_counter() - t0
+    refs = {i: r for i, r in zip(sample, res)}
+    cpu = None
+    if timed:
+        syms = sum(frames[i].spec.E for i in sample)
+        per = [r[3] for r in res]
+        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        cpu = {"value": syms / wall, "unit": "symbols/s", "cores": workers, "kind": "oracle",
+               "host_cpus": cores,
+               "single_worker_value": frames[sample[0]].spec.E / (sum(per) / len(per)),
+               "sample": f"{len(sample)} of {len(frames)} frames spread over the batch (their "
+                         f"own operator and FP64 NumPy CG with the same stop rule, on the same "
+                         f"y as the GPU), one frame per worker process, {workers} workers on "
+                         f"{cores} host CPUs: {wall:.1f} s wall, {sum(per):.1f} s CPU; "
+                         f"single_worker_value = symbols per frame / mean CPU s per frame"}
+    return ys, refs, cpu
 
 
-def load_traffic(workload, launch_bytes):
+# ----------------------------------------------------------------------------------------
+# GPU side
+# ----------------------------------------------------------------------------------------
+def iters_refreshes(it, k, max_iters):
+    if k <= 0:
+        return 0
+    return int(min(it, max_iters - 1) // k)
+
+
+def launch_bytes(specs, iters, refresh):
+    import numpy as np
+    tot = 0.0
+    for sp, it in zip(specs, iters):
+        nref = iters_refreshes(int(it), refresh, sp.max_iters)
+        tot += sp.E * (BYTES_INIT + BYTES_ITER * float(it) + BYTES_FINISH + BYTES_REFRESH * nref)
+    return float(tot)
+
+
+def check_against_oracle(O, np, frames, offs, x, sym, refs):
+    """Worst NMSE over the sample frames, and the decisions that differ from the oracle's:
+    all of them, and those not explained by the estimates (the oracle's estimate farther
+    from a boundary than the GPU's estimate is from it).  None without oracle results."""
+    if not refs:
+        return None
+    worst, diff, unexplained, n = 0.0, 0, 0, 0
+    for i, r in refs.items():
+        sp = frames[i].spec
+        xg = x[offs[i]:offs[i + 1]]
+        sg = sym[offs[i]:offs[i + 1]]
+        worst = max(worst, O.nmse(xg, r[0]))
+        # both decisions in the kernel's precision (the FP32 rule)
+        ref_sym = O.qam_decide(r[0].astype(np.complex64), sp.qam, np.float32)
+        d = np.nonzero(sg != ref_sym)[0]
+        diff += int(d.size)
+        if d.size:
+            margin = O.decision_margin(r[0][d], sp.qam)
+            err = np.abs(xg[d].astype(np.complex128) - r[0][d])
+            unexplained += int(np.count_nonzero(margin >= err + DECISION_FP32_SLACK))
+        n += sp.E
+    return {"frames": len(refs), "nmse_worst": worst, "nmse_ok": bool(worst <= NMSE_TARGET),
+            "decisions_compared": n, "decisions_differing": diff,
+            "decisions_differing_unexplained": unexplained}
+
+
+def time_solves(plan, y, xhat, dec, stats, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.lmmse_cg(y, xhat, dec, stats)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.lmmse_cg(y, xhat, dec, stats)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_times(otfs, specs, y, xhat, dec, stats, reps, refresh, torch):
+    """Fused-kernel durations from HIP events on the launch stream, and host-side time of
+    each whole solve (launch to completion)."""
+    sp0 = specs[0]
+    tplan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol, refresh_every=refresh,
+                      flags=otfs.TIME_KERNEL)
+    kms, solve_ms = [], []
+    for i in range(reps + 1):
+        t1 = time.perf_counter()
+        tplan.lmmse_cg(y, xhat, dec, stats)
+        k = tplan.kernel_ms()
+        if i > 0:
+            kms.append(k)
+            solve_ms.append((time.perf_counter() - t1) * 1e3)
+    del tplan
+    return kms, solve_ms
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
+    """Device-to-device copy of nbytes with torch: read + write bytes / median time."""
+    import numpy as np
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / float(np.median(ts)) / 1e9
+
+
+def solve_block(otfs, O, np, torch, name, frames, ys, refs, steps, warmup, refresh, plain,
+                copy_gbs):
+    """Time the fused solve of one workload and check it against the oracle's sample."""
+    specs = [f.spec for f in frames]
+    sp0 = specs[0]
+    offs = otfs.frame_offsets(specs)
+    dev = torch.device("cuda")
+    plan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol, refresh_every=refresh)
+    E = plan.total_elems
+    y = torch.from_numpy(np.concatenate(ys).astype(np.complex64)).to(dev)
+    xhat = torch.empty_like(y)
+    dec = torch.empty(E, dtype=torch.uint8, device=dev)
+    stats = plan.new_stats()
+    torch.cuda.synchronize()
+    wall = time_solves(plan, y, xhat, dec, stats, steps, warmup, torch)
+    value = E * steps / wall
+    st = otfs.stats_numpy(stats)
+    iters = st["iters"].astype(np.float64)
+    xh = xhat.cpu().numpy()
+    dh = dec.cpu().numpy()
+    sym_tx = np.concatenate([f.sym for f in frames]).astype(np.int64)
+    ser = float(np.mean(dh.astype(np.int64) != sym_tx))
+    parity = check_against_oracle(O, np, frames, offs, xh, dh, refs)
+    lb = launch_bytes(specs, iters, refresh)
+    kms, solve_ms = kernel_times(otfs, specs, y, xhat, dec, stats, steps, refresh, torch)
+    kavg = float(np.mean(kms))
+    achieved = lb / (kavg * 1e-3) / 1e9
+    out = {
+        "value": value, "ms_per_step": wall * 1e3 / steps,
+        "config": {"workload": name, "frames": len(specs), "M": sp0.M, "N": sp0.N, "P": sp0.P,
+                   "qam": sp0.qam, "snr_db": sp0.snr_db, "max_iters": sp0.max_iters,
+                   "rel_tol": sp0.tol, "refresh_every": refresh, "precision": "complex64"},
+        "latency_ms": {"batch_p50": float(np.percentile(solve_ms, 50)),
+                       "batch_p99": float(np.percentile(solve_ms, 99)),
+                       "note": "whole-batch solve, every frame done by its end"},
+        "iterations": {"mean": float(iters.mean()), "min": int(iters.min()),
+                       "max": int(iters.max()),
+                       "converged_frames": int(np.sum(st["status"] == otfs.FRAME_CONVERGED))},
+        "ser_vs_transmitted": ser,
+        "parity_vs_oracle": parity,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": load_traffic(name, refresh),
+                     "kernel": "k_cg_fused", "kernel_ms": kavg,
+                     "algorithmic_bytes_per_launch": lb,
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+    }
+    if plain:
+        out["plain_form"] = plain_block(otfs, O, np, torch, frames, ys, refs, refresh, offs)
+    del plan, y, xhat, dec, stats
+    torch.cuda.empty_cache()
+    return out
+
+
+def plain_block(otfs, O, np, torch, frames, ys, refs, refresh, offs, reps=3):
+    """The plain form (one frame at a time, four unfused launches per iteration) on the
+    same y, with a tiling made for one frame at a time; one warm-up, median of reps."""
+    specs = [f.spec for f in frames]
+    sp0 = specs[0]
+    tile = max(512, max(sp.E for sp in specs) // 256)
+    plan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol, tile_elems=tile)
+    y = torch.from_numpy(np.concatenate(ys).astype(np.complex64)).to("cuda")
+    xhat = torch.empty_like(y)
+    dec = torch.empty(plan.total_elems, dtype=torch.uint8, device="cuda")
+    stats = plan.new_stats()
+    plan.lmmse_cg_plain(y, xhat, dec, stats)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        plan.lmmse_cg_plain(y, xhat, dec, stats)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    tp = float(np.median(ts))
+    parity = check_against_oracle(O, np, frames, offs, xhat.cpu().numpy(), dec.cpu().numpy(), refs)
+    del plan, y, xhat, dec, stats
+    return {"value": plan_elems(specs) / tp, "unit": "symbols/s", "ms_per_step": tp * 1e3,
+            "runs": reps, "tile_elems": tile,
+            "nmse_worst": None if parity is None else parity["nmse_worst"],
+            "note": "no FP64 refresh in the plain form" if refresh else ""}
+
+
+def plan_elems(specs):
+    return float(sum(sp.E for sp in specs))
+
+
+def load_traffic(workload, refresh):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha() or int(t.get("refresh_every", 0)) != refresh:
         return None
     return t.get("traffic_bytes_per_launch")
 
 
-def serving_leg(otfs, W, workload, torch, step_iters=5, seed=1004):
-    """Frames of `workload` offered to the server: first all at once (throughput), then as
-    a Poisson stream at half that rate (latency from submit to completion)."""
-    import numpy as np
-    frames = list(W.iter_frames(workload))
-    specs = [f.spec for f in frames]
-    sp0 = specs[0]
-    # received frames, synthesised on the GPU and handed to the server as host buffers
-    plan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol)
-    offs = otfs.frame_offsets(specs)
-    dev = torch.device("cuda")
-    sym = torch.from_numpy(np.concatenate([f.sym for f in frames])).to(dev)
-    x = torch.empty(plan.total_elems, dtype=torch.complex64, device=dev)
-    for i, f in enumerate(frames):
-        x[offs[i]:offs[i + 1]] = qam_points_torch(torch, sym[offs[i]:offs[i + 1]], f.spec.qam)
-    noise = torch.from_numpy(np.concatenate([f.noise for f in frames]).astype(np.complex64))
-    y = (plan.apply_H(x).cpu() + noise).numpy()
-    del plan, x, sym
-    ys = [y[offs[i]:offs[i + 1]] for i in range(len(specs))]
-    total = float(offs[-1])
-
-    def run(srv, arrivals):
-        t0 = time.perf_counter()
-        tickets = []
-        for i, (sp, yy) in enumerate(zip(specs, ys)):
-            wait = arrivals[i] - (time.perf_counter() - t0)
-            if wait > 0:
-                time.sleep(wait)
-            tickets.append(srv.submit(sp, yy))
-        lat = [srv.wait(t, sp, timeout=120.0)[3] for t, sp in zip(tickets, specs)]
-        return time.perf_counter() - t0, np.array(lat) * 1e3
-
-    pool = 8 << 30
-    with otfs.Server(pool, max_iters=sp0.max_iters, rel_tol=sp0.tol,
-                     step_iters=step_iters) as srv:
-        run(srv, np.zeros(len(specs)))                       # warm-up
-        wall, lat_burst = run(srv, np.zeros(len(specs)))
-        rate = len(specs) / wall
-        gaps = np.random.default_rng(seed).exponential(2.0 / rate, len(specs))
-        wall_p, lat_p = run(srv, np.cumsum(gaps) - gaps[0])
-        st = srv.stats()
-    return {"workload": workload, "frames": len(specs), "step_iters": step_iters,
-            "pool_bytes": pool, "pool_bytes_peak": int(st.pool_bytes_peak),
-            "burst": {"value": total / wall, "unit": "symbols/s", "frames_per_s": rate,
-                      "latency_ms_p50": float(np.percentile(lat_burst, 50)),
-                      "latency_ms_p99": float(np.percentile(lat_burst, 99))},
-            "poisson_half_rate": {"offered_frames_per_s": rate / 2,
-                                  "value": total / wall_p, "unit": "symbols/s",
-                                  "latency_ms_p50": float(np.percentile(lat_p, 50)),
-                                  "latency_ms_p99": float(np.percentile(lat_p, 99))},
-            "note": "host buffers in and out (submit copies y, poll copies x_hat)"}
-
-
-def serving_sweep(otfs, W, workload, torch, rates, nframes, pool_bytes, step_iters=5,
+# ----------------------------------------------------------------------------------------
+# serving: Poisson arrival sweep
+# ----------------------------------------------------------------------------------------
+def serving_sweep(otfs, np, torch, frames, ys, rates, nframes, pool_bytes, step_iters=5,
                   seed=1004):
     """Poisson arrival streams of `nframes` frames (the workload's frames, cycled) at each
     offered rate: achieved offered rate, completed symbols/s and p50 / p99 / p99.9 latency
     from submit to completion.  Results are polled while frames are being submitted, so
     host memory stays bounded."""
-    import numpy as np
     from collections import deque
-    frames = list(W.iter_frames(workload))
     specs = [f.spec for f in frames]
     sp0 = specs[0]
-    plan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol)
-    offs = otfs.frame_offsets(specs)
-    dev = torch.device("cuda")
-    sym = torch.from_numpy(np.concatenate([f.sym for f in frames])).to(dev)
-    x = torch.empty(plan.total_elems, dtype=torch.complex64, device=dev)
-    for i, f in enumerate(frames):
-        x[offs[i]:offs[i + 1]] = qam_points_torch(torch, sym[offs[i]:offs[i + 1]], f.spec.qam)
-    noise = torch.from_numpy(np.concatenate([f.noise for f in frames]).astype(np.complex64))
-    y = (plan.apply_H(x).cpu() + noise).numpy()
-    del plan, x, sym
-    ys = [y[offs[i]:offs[i + 1]] for i in range(len(specs))]
     rng = np.random.default_rng(seed)
     out = []
     with otfs.Server(pool_bytes, max_iters=sp0.max_iters, rel_tol=sp0.tol,
@@ -184,7 +327,7 @@ def serving_sweep(otfs, W, workload, torch, rates, nframes, pool_bytes, step_ite
         warm = [srv.submit(sp, yy) for sp, yy in zip(specs, ys)]      # warm-up
         for tk, sp in zip(warm, specs):
             srv.wait(tk, sp, timeout=120.0)
-        for rate in rates:
+        for ri, rate in enumerate(rates):
             arrivals = np.cumsum(rng.exponential(1.0 / rate, nframes))
             arrivals -= arrivals[0]
             pending, lat, syms = deque(), [], 0
@@ -216,27 +359,40 @@ def serving_sweep(otfs, W, workload, torch, rates, nframes, pool_bytes, step_ite
                         "latency_ms_p50": float(np.percentile(lat, 50)),
                         "latency_ms_p99": float(np.percentile(lat, 99)),
                         "latency_ms_p999": float(np.percentile(lat, 99.9))})
-            print(json.dumps(out[-1]), file=sys.stderr, flush=True)
-    return {"workload": workload, "frames_per_point": nframes, "step_iters": step_iters,
-            "pool_bytes": pool_bytes, "points": out,
-            "note": "host buffers in and out (submit copies y, poll copies x_hat)"}
+            print(f"[serving] {json.dumps(out[-1])}", file=sys.stderr, flush=True)
+        st = srv.stats()
+    # the knee: the highest offered rate whose completed rate keeps up (within 5 %)
+    knee = None
+    for p in out:
+        if p["completed_frames_per_s"] >= 0.95 * p["offered_frames_per_s"]:
+            knee = p
+    return {"workload": "serving_uneven", "frames_per_point": nframes, "step_iters": step_iters,
+            "pool_bytes": pool_bytes, "pool_bytes_peak": int(st.pool_bytes_peak),
+            "points": out,
+            "knee": None if knee is None else {"offered_frames_per_s": knee["offered_frames_per_s"],
+                                               "value": knee["value"],
+                                               "latency_ms_p99": knee["latency_ms_p99"]},
+            "note": "host buffers in and out (submit copies y, poll copies x_hat); Poisson "
+                    "arrivals, frames of the uneven-batch shapes cycled"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch64_512x128")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-frames", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batch128_1024x256")
+    ap.add_argument("--refresh", type=int, default=None,
+                    help="FP64 refresh period (default: the workload's own, else none)")
+    ap.add_argument("--cpu-frames", type=int, default=MAX_WORKERS,
+                    help="oracle sample size (frames spread over the batch)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle: y made on the GPU (apply_H + noise), no parity line")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop leg")
-    ap.add_argument("--serving-workload", default="serving_uneven")
-    ap.add_argument("--serving-sweep", default="", metavar="RATES",
-                    help="instead of the benchmark, sweep the serving loop over Poisson "
-                         "arrival rates (comma-separated frames/s) and print that JSON line")
-    ap.add_argument("--sweep-frames", type=int, default=10000)
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 64 x (512,128) block")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--sweep-rates", default=",".join(str(r) for r in SWEEP_RATES))
+    ap.add_argument("--sweep-frames", type=int, default=5000)
     ap.add_argument("--sweep-pool-gib", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="also run one plain device-to-device copy of BYTES bytes (reference "
@@ -250,127 +406,116 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
-    import paper_2604_02266_amd as otfs
     import workloads as W
 
-    if args.serving_sweep:
-        rates = [float(r) for r in args.serving_sweep.split(",") if r]
-        res = serving_sweep(otfs, W, args.serving_workload, torch, rates, args.sweep_frames,
-                            args.sweep_pool_gib << 30)
-        print(json.dumps({"serving_sweep": res}))
-        return
-
+    refresh = REFRESH.get(args.workload, 0) if args.refresh is None else args.refresh
     frames = list(W.iter_frames(args.workload))
-    specs = [f.spec for f in frames]
-    sp0 = specs[0]
-    # the CPU leg runs first, before this process touches the GPU (its workers are forked)
-    cpu = None if args.no_cpu else cpu_baseline(frames, args.cpu_frames)
+    blocks = [(args.workload, frames, refresh)]
+    if not args.no_secondary and args.workload != SECONDARY:
+        blocks.append((SECONDARY, list(W.iter_frames(SECONDARY)), REFRESH.get(SECONDARY, 0)))
+    serve_frames = None if args.no_serving else list(W.iter_frames("serving_uneven"))
 
-    plan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol)
-    E = plan.total_elems
-    dev = torch.device("cuda")
+    # ---- CPU phase: oracle-made inputs and the oracle's solves, before the GPU is touched ----
+    cpu = None
+    data = {}
+    serve_ys = None
+    if not args.no_cpu:
+        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        workers = max(1, min(cores or 1, MAX_WORKERS))
+        print(f"[bench] oracle phase: {workers} workers", file=sys.stderr, flush=True)
+        with multiprocessing.get_context("fork").Pool(workers, initializer=_worker_init) as pool:
+            for bi, (name, frs, _) in enumerate(blocks):
+                sample = spread(len(frs), args.cpu_frames)
+                ys, refs, c = cpu_phase(pool, workers, frs, sample, timed=(bi == 0))
+                data[name] = (ys, refs)
+                if bi == 0:
+                    cpu = c
+                print(f"[bench] oracle phase done for {name}", file=sys.stderr, flush=True)
+            if serve_frames is not None:
+                serve_ys = pool.map(_job_received, serve_frames, chunksize=4)
 
-    # inputs, resident before timing
-    sym = torch.from_numpy(np.concatenate([f.sym for f in frames])).to(dev)
-    x = torch.empty(E, dtype=torch.complex64, device=dev)
-    offs = otfs.frame_offsets(specs)
-    for i, f in enumerate(frames):
-        x[offs[i]:offs[i + 1]] = qam_points_torch(torch, sym[offs[i]:offs[i + 1]], f.spec.qam)
-    noise = torch.from_numpy(np.concatenate([f.noise for f in frames]).astype(np.complex64)).to(dev)
-    y = plan.apply_H(x)
-    y += noise
-    xhat = torch.empty_like(y)
-    dec = torch.empty(E, dtype=torch.uint8, device=dev)
-    stats = plan.new_stats()
-    torch.cuda.synchronize()
+    import torch
+
+    import oracle as O
+    import paper_2604_02266_amd as otfs
+
+    if args.no_cpu:   # inputs made on the GPU: the library's H applied to the symbols + noise
+        for name, frs, _ in blocks:
+            data[name] = (gpu_made_y(otfs, np, torch, frs), {})
+        if serve_frames is not None:
+            serve_ys = gpu_made_y(otfs, np, torch, serve_frames)
 
     if args.calibrate_copy > 0:
         n = args.calibrate_copy // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
 
-    for _ in range(args.warmup):
-        plan.lmmse_cg(y, xhat, dec, stats)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.lmmse_cg(y, xhat, dec, stats)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    value = E * args.steps / wall
+    copy_gbs = copy_bandwidth(torch)
+    results = []
+    for bi, (name, frs, rf) in enumerate(blocks):
+        ys, refs = data[name]
+        print(f"[bench] gpu block {name}", file=sys.stderr, flush=True)
+        results.append(solve_block(otfs, O, np, torch, name, frs, ys, refs, args.steps,
+                                   args.warmup, rf, plain=(bi == 0 and not args.no_plain),
+                                   copy_gbs=copy_gbs))
 
-    st = otfs.stats_numpy(stats)
-    iters = st["iters"].astype(np.float64)
-    sizes = np.diff(offs).astype(np.float64)
-    launch_bytes = float(np.sum(sizes * (BYTES_INIT + BYTES_ITER * iters + BYTES_FINISH)))
-    ser = float(np.mean(dec.cpu().numpy() != sym.cpu().numpy().astype(np.uint8)))
-
-    # fused-kernel duration from HIP events on the launch stream, and per-solve latency
-    tplan = otfs.Plan(specs, max_iters=sp0.max_iters, rel_tol=sp0.tol, flags=otfs.TIME_KERNEL)
-    kms, solve_ms = [], []
-    for i in range(args.steps + 1):
-        t1 = time.perf_counter()
-        tplan.lmmse_cg(y, xhat, dec, stats)
-        k = tplan.kernel_ms()
-        if i > 0:
-            kms.append(k)
-            solve_ms.append((time.perf_counter() - t1) * 1e3)
-    kavg = float(np.mean(kms))
-    achieved = launch_bytes / (kavg * 1e-3) / 1e9
-    del tplan
-
+    main_res = results[0]
+    par = main_res["parity_vs_oracle"]
+    if par is not None and not par["nmse_ok"]:
+        print(f"[bench] WARNING: NMSE {par['nmse_worst']:.3e} exceeds {NMSE_TARGET}",
+              file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main_res["value"],
         "unit": "symbols/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "complex64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "frames": len(specs), "M": sp0.M, "N": sp0.N,
-                   "P": sp0.P, "qam": sp0.qam, "snr_db": sp0.snr_db,
-                   "max_iters": sp0.max_iters, "rel_tol": sp0.tol},
-        "latency_ms": {"batch_p50": float(np.percentile(solve_ms, 50)),
-                       "batch_p99": float(np.percentile(solve_ms, 99)),
-                       "note": "whole-batch solve, every frame done by its end"},
-        "iterations": {"mean": float(iters.mean()), "min": int(iters.min()),
-                       "max": int(iters.max()),
-                       "converged_frames": int(np.sum(st["status"] == otfs.FRAME_CONVERGED))},
-        "ser_vs_transmitted": ser,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": load_traffic(args.workload, launch_bytes),
-                     "kernel": "k_cg_fused", "kernel_ms": kavg,
-                     "algorithmic_bytes_per_launch": launch_bytes},
+        "config": main_res["config"],
     }
-
-    if not args.no_plain:
-        t1 = time.perf_counter()
-        plan.lmmse_cg_plain(y, xhat, dec, stats)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t1
-        out["plain_form"] = {"value": E / tp, "unit": "symbols/s", "ms_per_step": tp * 1e3}
-
-    if not args.no_serving:
-        del plan, y, xhat, dec, stats, x, noise, sym
-        torch.cuda.empty_cache()
-        out["serving"] = serving_leg(otfs, W, args.serving_workload, torch)
-
+    for k in ("latency_ms", "iterations", "ser_vs_transmitted", "parity_vs_oracle", "roofline",
+              "plain_form"):
+        if k in main_res:
+            out[k] = main_res[k]
+    if len(results) > 1:
+        sec = results[1]
+        out["secondary"] = {k: sec[k] for k in ("value", "ms_per_step", "config", "iterations",
+                                                 "parity_vs_oracle", "roofline")}
+    if serve_frames is not None:
+        rates = [float(r) for r in args.sweep_rates.split(",") if r]
+        out["serving"] = serving_sweep(otfs, np, torch, serve_frames, serve_ys, rates,
+                                       args.sweep_frames, args.sweep_pool_gib << 30)
     if cpu is not None:
         out["cpu_baseline"] = cpu
-
     print(json.dumps(out), flush=True)
+
+
+def gpu_made_y(otfs, np, torch, frames):
+    """y = H x + w with the library's H (for runs without the oracle, e.g. under a
+    profiler): QAM points from the generator's symbol indices, the generator's noise."""
+    specs = [f.spec for f in frames]
+    plan = otfs.Plan(specs, max_iters=1, rel_tol=0.0)
+    offs = otfs.frame_offsets(specs)
+    x = np.empty(plan.total_elems, dtype=np.complex64)
+    for i, f in enumerate(frames):
+        m = int(round(math.sqrt(f.spec.qam)))
+        s = math.sqrt(2.0 * (f.spec.qam - 1) / 3.0)
+        ii, qq = np.divmod(np.asarray(f.sym, dtype=np.int64), m)
+        x[offs[i]:offs[i + 1]] = ((2 * ii - (m - 1)) + 1j * (2 * qq - (m - 1))) / s
+    y = plan.apply_H(torch.from_numpy(x).to("cuda")).cpu().numpy()
+    y = y + np.concatenate([f.noise for f in frames]).astype(np.complex64)
+    del plan
+    return [y[offs[i]:offs[i + 1]] for i in range(len(frames))]
 
 
 if __name__ == "__main__":
