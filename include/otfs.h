@@ -228,6 +228,49 @@ otfs_status otfs_lmmse_cg(otfs_plan_t* plan, const void* y_dev, void* xhat_dev, 
 otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y_dev, void* xhat_dev,
                                 uint8_t* sym_dev, otfs_frame_stats* stats_dev, void* stream);
 
+/* ------------------------------------------------------------------------------------ */
+/* Bits and bit errors (Eq. demod: decided symbols demapped to bits)                      */
+/* ------------------------------------------------------------------------------------ */
+/* Bit errors of hard decisions against the transmitted symbol indices, per frame.  The
+ * bits of a square-QAM index i_I * sqrt(Q) + i_Q are a reflected Gray code per axis
+ * (g = i XOR (i >> 1), log2 sqrt(Q) bits each, in-phase bits first; the paper leaves the
+ * map unspecified).  sym_dev, sym_tx_dev: total_elems uint8; errs_dev: nframes uint64
+ * (overwritten); frames with qam = 0 get 0. */
+otfs_status otfs_bit_errors(const otfs_plan_t* plan, const uint8_t* sym_dev,
+                            const uint8_t* sym_tx_dev, uint64_t* errs_dev, void* stream);
+
+/* The fused solve run one iteration per launch, recording after every iteration the bit
+ * errors of the current estimates' decisions against sym_tx_dev: errs_dev[(xi - 1) *
+ * nframes + f] for xi = 1 .. max_iters (a frame that stopped keeps its final decisions).
+ * This is the measurement behind the BER-driven iteration budget of Sec. IV-C (Eq.
+ * ber_convergence).  The results (x_hat, decisions, stats) are those of otfs_lmmse_cg.
+ * sym_dev is required (it holds the decisions of the last recorded iteration). */
+otfs_status otfs_lmmse_cg_trace(otfs_plan_t* plan, const void* y_dev, void* xhat_dev,
+                                uint8_t* sym_dev, otfs_frame_stats* stats_dev,
+                                const uint8_t* sym_tx_dev, uint64_t* errs_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* Channel from a pilot frame                                                             */
+/* ------------------------------------------------------------------------------------ */
+/* Replace every frame's paths, on the device, by the dominant paths estimated from its
+ * received pilot frame (Sec. III "Channel estimation", Sec. IV-A "Hadamard product",
+ * Sec. IV-B "Dominant path determination"): the pilot is one impulse at
+ * (K0, L0) = (M/2, N/2); the effective channel is estimated on the received grid as
+ * h[k, l] = Y[k, l] e^{-j 2 pi K0 (l - L0) / (MN)} (Eqs. heff_exp, heff_hadamard), bin (k, l)
+ * standing for the path (tau, nu) = (k - K0, l - L0); the paths are the bins with
+ * |h| > theta (Eq. heff_thres; tested as |h|^2 > theta^2 in FP32 on h rounded to FP32), in
+ * vector order q = l*M + k, gain h_p = h[k_p, l_p].  The first P of them are kept, P being
+ * the path count given for that frame at otfs_plan (its capacity; the given paths are
+ * only placeholders then).  The plan's path tables, delay-ramp tables (and, with a stored
+ * D, the SS table) are rebuilt on the device; the next otfs_apply_* / otfs_lmmse_cg* calls
+ * on the stream use them, with no host round trip.  The plan must be bound; frames with
+ * LDS-staged or windowed gathers return OTFS_E_UNSUPPORTED.
+ * ypilot_dev: total_elems complex64, one received pilot frame per frame, in batch layout;
+ * theta >= 0 (the paper uses 0.08); npaths_dev: nframes int32 receiving the number of
+ * bins above theta per frame (may exceed the capacity), nullable. */
+otfs_status otfs_plan_paths_from_pilot(otfs_plan_t* plan, const void* ypilot_dev, float theta,
+                                       int32_t* npaths_dev, void* stream);
+
 /* Bound of the fused kernel's in-kernel waits (per-frame barriers and neighbour waits), in
  * microseconds: a wait that is not satisfied within it gives up, raises the launch-wide
  * abort word (every other wait of the launch then gives up too), and the frames concerned
@@ -288,6 +331,12 @@ typedef struct {
   uint64_t pool_bytes_in_use, pool_bytes_peak;
 } otfs_server_stats_t;
 otfs_status otfs_server_stats(otfs_server_t* srv, otfs_server_stats_t* out);
+
+/* Tile size (elements per workgroup band) for frames of shape M x N submitted from now
+ * on; 0 restores the built-in rule (8192).  A frame's tiling depends only on its own
+ * shape, so its result is the same alone and among other frames.  Used to apply the
+ * autotuner's per-shape serving tiles. */
+otfs_status otfs_server_set_tiling(otfs_server_t* srv, int32_t M, int32_t N, int32_t tile_elems);
 
 /* Stop the scheduler (frames still queued or running are dropped) and free host state. */
 otfs_status otfs_server_free(otfs_server_t* srv);

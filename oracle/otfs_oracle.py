@@ -16,9 +16,11 @@ directly, slowly and without fusion:
 * conjugate gradient (Hestenes-Stiefel) on the normal equations, the iteration of
   Algorithm 1 (Sec. IV-C), with a per-frame relative-residual stop test after the residual
   update;
-* hard QAM decisions (Eq. demod), per axis and by brute force;
+* hard QAM decisions (Eq. demod), per axis and by brute force, their bits (a Gray map per
+  axis) and bit-error counts;
+* the BER-driven iteration budget (Eq. ber_convergence) over per-iteration CG estimates;
 * the point-pilot channel estimate (Eq. heff) and its Hadamard form (Eq. heff_exp,
-  Eq. heff_hadamard).
+  Eq. heff_hadamard), and the dominant-path set by thresholding (Eq. heff_thres).
 
 Conventions (readings of the paper where it leaves a choice open):
 * A frame is X[k, l], delay bin k in [0, M), Doppler bin l in [0, N).  The vector form
@@ -45,7 +47,8 @@ __all__ = [
     "dense_H_eq_Hdd", "dense_H_shift_ops", "dzt_matrix", "dzt", "idzt", "dense_H_timedomain",
     "cg_lmmse", "lmmse_dense", "qam_side", "qam_scale", "qam_points", "qam_decide",
     "qam_decide_bruteforce", "decision_margin", "pilot_estimate_direct",
-    "pilot_estimate_hadamard", "received_frame", "nmse",
+    "pilot_estimate_hadamard", "pilot_frame", "threshold_paths", "received_frame", "nmse",
+    "gray_bits", "bit_errors", "cg_lmmse_trace", "ber_convergence",
 ]
 
 
@@ -402,6 +405,65 @@ def decision_margin(x, Q: int) -> np.ndarray:
     return np.minimum(axis(x.real), axis(x.imag))
 
 
+def gray_bits(idx, Q: int) -> np.ndarray:
+    """Bits of square-QAM symbol indices i_I * m + i_Q (Eq. demod's demapping to bits, which
+    the paper leaves unspecified; reading: a reflected Gray code per axis).  Each axis
+    index i becomes g = i XOR (i >> 1) on log2(m) bits, most significant first; a symbol's
+    bits are the in-phase axis's followed by the quadrature axis's.  Returns uint8 of shape
+    (len(idx), 2 log2(m))."""
+    m = qam_side(Q)
+    b = int(round(math.log2(m)))
+    idx = np.asarray(idx, dtype=np.int64).reshape(-1)
+    out = np.zeros((idx.size, 2 * b), dtype=np.uint8)
+    for axis, val in enumerate((idx // m, idx % m)):
+        g = val ^ (val >> 1)
+        for j in range(b):
+            out[:, axis * b + j] = (g >> (b - 1 - j)) & 1
+    return out
+
+
+def bit_errors(sym_hat, sym_tx, Q: int) -> int:
+    """Number of differing bits between decided and transmitted symbols (gray_bits)."""
+    return int(np.count_nonzero(gray_bits(sym_hat, Q) != gray_bits(sym_tx, Q)))
+
+
+def cg_lmmse_trace(y, op: TwistedConvChannel, lam: float, iters: int):
+    """The estimates after each of `iters` conjugate-gradient steps (the method of cg_lmmse
+    with a fixed count, Algorithm 1's form): a list whose entry k-1 is x after step k."""
+    apply_A = _normal_operator(op, lam)
+    b = op.apply_adjoint(np.asarray(y, dtype=np.complex128))
+    x = np.zeros_like(b)
+    r = b.copy()
+    rho = float(np.vdot(r, r).real)
+    out = []
+    if rho == 0.0:
+        return [x.copy() for _ in range(iters)]
+    d = r.copy()
+    for _ in range(iters):
+        q = apply_A(d)
+        gamma = rho / float(np.vdot(d, q).real)
+        x = x + gamma * d
+        r = r - gamma * q
+        out.append(x.copy())
+        rho_new = float(np.vdot(r, r).real)
+        d = r + (rho_new / rho) * d
+        rho = rho_new
+    return out
+
+
+def ber_convergence(ber, eta: float = 1e-2, zeta: float = 1e-12) -> int:
+    """Convergence iteration of a BER curve (Eq. ber_convergence): with ber[k-1] the BER
+    after k iterations, the signed relative change r_k = (BER_{k-1} - BER_k) /
+    max(BER_{k-1}, zeta); the BER has converged at the first k >= 2 with r_k < eta (a rise
+    or a negligible fall).  Returns that k, or len(ber) when no k qualifies."""
+    ber = [float(v) for v in ber]
+    for k in range(2, len(ber) + 1):
+        prev, cur = ber[k - 2], ber[k - 1]
+        if (prev - cur) / max(prev, zeta) < eta:
+            return k
+    return len(ber)
+
+
 # ----------------------------------------------------------------------------------------
 # Point-pilot channel estimate (Eq. heff; Eq. heff_exp with Eq. heff_hadamard)
 # ----------------------------------------------------------------------------------------
@@ -424,6 +486,39 @@ def pilot_estimate_hadamard(y_pilot, M, N) -> np.ndarray:
     l = np.arange(N)[None, :]
     Et = np.exp(-2j * np.pi * K0 * (l - L0) / (M * N))
     return Y * Et
+
+
+def pilot_frame(M, N) -> np.ndarray:
+    """The pilot frame: one unit impulse at (K0, L0) = (M/2, N/2) in the DD grid (Sec. III,
+    channel estimation), in vector order."""
+    d = np.zeros((M, N), dtype=np.complex128)
+    d[M // 2, N // 2] = 1.0
+    return vec(d)
+
+
+def threshold_paths(h_grid, theta: float, dtype=np.float64):
+    """Dominant paths of an estimated effective channel (Eq. heff_thres): the bins whose
+    magnitude exceeds theta, with gain h_p = h_hat[k_p, l_p].
+
+    h_grid: the Hadamard-form estimate on the received grid (pilot_estimate_hadamard),
+    entry (k, l) standing for the path at shifts (tau, nu) = (k - K0, l - L0).  The test
+    |h| > theta is taken as |h|^2 > theta^2 in `dtype` on the estimate rounded to that
+    precision (a float decision has to be taken in one precision to compare two
+    implementations).  Returns (tau, nu, h) in vector order q = l*M + k."""
+    H = np.asarray(h_grid)
+    M, N = H.shape
+    K0, L0 = M // 2, N // 2
+    tau, nu, gain = [], [], []
+    for l in range(N):
+        for k in range(M):
+            v = H[k, l]
+            re, im = dtype(np.real(v)), dtype(np.imag(v))
+            if re * re + im * im > dtype(theta) * dtype(theta):
+                tau.append(k - K0)
+                nu.append(l - L0)
+                gain.append(v)
+    return (np.array(tau, dtype=np.int64), np.array(nu, dtype=np.int64),
+            np.array(gain, dtype=np.complex128))
 
 
 # ----------------------------------------------------------------------------------------

@@ -115,6 +115,9 @@ def lib() -> ctypes.CDLL:
         "otfs_lmmse_cg_plain": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "otfs_plan_kernel_ms": (st, [_vp, ctypes.POINTER(ctypes.c_float)]),
         "otfs_plan_set_wait_limit": (st, [_vp, ctypes.c_int64]),
+        "otfs_plan_paths_from_pilot": (st, [_vp, _vp, ctypes.c_float, _vp, _vp]),
+        "otfs_bit_errors": (st, [_vp, _vp, _vp, _vp, _vp]),
+        "otfs_lmmse_cg_trace": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "otfs_server_create": (st, [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(CgOpts),
                                     ctypes.c_int32, ctypes.POINTER(_vp)]),
         "otfs_submit": (st, [_vp, ctypes.POINTER(FrameDesc), _vp,
@@ -122,6 +125,7 @@ def lib() -> ctypes.CDLL:
         "otfs_poll": (st, [_vp, ctypes.c_uint64, _vp, _vp, ctypes.POINTER(FrameStats),
                            ctypes.POINTER(ctypes.c_uint64)]),
         "otfs_server_stats": (st, [_vp, ctypes.POINTER(ServerStats)]),
+        "otfs_server_set_tiling": (st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "otfs_server_frame_bytes": (st, [_vp, ctypes.POINTER(FrameDesc),
                                          ctypes.POINTER(ctypes.c_size_t),
                                          ctypes.POINTER(ctypes.c_size_t)]),
@@ -190,9 +194,21 @@ class Plan:
     def __init__(self, frames: Sequence, max_iters: int = 50, rel_tol: float = 1e-6,
                  refresh_every: int = 0, flags: int = 0, tile_elems: int = 0,
                  max_grid: int = 0, stage_bytes: Optional[int] = None,
-                 window: Optional[Sequence[int]] = None, bind: bool = True):
+                 window: Optional[Sequence[int]] = None, bind: bool = True,
+                 tune: bool = True):
         self._lib = lib()
         self.frames = list(frames)
+        # launch shape stored by the autotuner for this batch signature, unless the caller
+        # chose one
+        self.tuned = None
+        if tune and not tile_elems and stage_bytes is None and window is None and self.frames:
+            from . import autotune
+            self.tuned = autotune.lookup(self.frames, refresh_every, flags)
+            if self.tuned is not None:
+                tile_elems = int(self.tuned["tile_elems"])
+                stage_bytes = int(self.tuned["stage_bytes"]) or None
+                if self.tuned["split_direction"]:
+                    flags |= SPLIT_DIRECTION
         self.opts = make_opts(max_iters, rel_tol, refresh_every, flags)
         descs = _Descs(self.frames)
         h = _vp()
@@ -314,6 +330,45 @@ class Plan:
     def lmmse_cg_plain(self, y, xhat=None, sym=None, stats=None, stream=None):
         return self._solve(self._lib.otfs_lmmse_cg_plain, y, xhat, sym, stats, stream)
 
+    def paths_from_pilot(self, ypilot, theta: float = 0.08, npaths=None, stream=None):
+        """otfs_plan_paths_from_pilot: the frames' paths from their received pilot frames
+        (complex64, batch layout).  Returns the int32 tensor of per-frame counts above
+        theta."""
+        torch = _torch()
+        ypilot = self._vec(ypilot, "ypilot")
+        if npaths is None:
+            npaths = torch.zeros(max(self.nframes, 1), dtype=torch.int32, device="cuda")
+        _check(self._lib.otfs_plan_paths_from_pilot(self._h, _vp(_ptr(ypilot)), float(theta),
+                                                    _vp(_ptr(npaths)), _vp(_stream_ptr(stream))))
+        return npaths
+
+    def bit_errors(self, sym, sym_tx, errs=None, stream=None):
+        """otfs_bit_errors: per-frame bit errors (Gray map) of decisions vs transmitted."""
+        torch = _torch()
+        sym = self._vec(sym, "sym", torch.uint8)
+        sym_tx = self._vec(sym_tx, "sym_tx", torch.uint8)
+        if errs is None:
+            errs = torch.zeros(max(self.nframes, 1), dtype=torch.int64, device="cuda")
+        _check(self._lib.otfs_bit_errors(self._h, _vp(_ptr(sym)), _vp(_ptr(sym_tx)),
+                                         _vp(_ptr(errs)), _vp(_stream_ptr(stream))))
+        return errs
+
+    def lmmse_cg_trace(self, y, sym_tx, xhat=None, sym=None, stats=None, stream=None):
+        """otfs_lmmse_cg_trace: returns (xhat, sym, errs) with errs of shape
+        (max_iters, nframes): bit errors after each iteration."""
+        torch = _torch()
+        y = self._y(y)
+        xhat = self._vec(xhat, "xhat")
+        sym = self._vec(sym, "sym", torch.uint8)
+        sym_tx = self._vec(sym_tx, "sym_tx", torch.uint8)
+        errs = torch.zeros((self.opts.max_iters, max(self.nframes, 1)), dtype=torch.int64,
+                           device="cuda")
+        _check(self._lib.otfs_lmmse_cg_trace(self._h, _vp(_ptr(y)), _vp(_ptr(xhat)),
+                                             _vp(_ptr(sym)), _vp(_ptr(stats)),
+                                             _vp(_ptr(sym_tx)), _vp(_ptr(errs)),
+                                             _vp(_stream_ptr(stream))))
+        return xhat, sym, errs
+
     def set_wait_limit(self, wait_us: int):
         _check(self._lib.otfs_plan_set_wait_limit(self._h, int(wait_us)))
 
@@ -331,7 +386,7 @@ class Server:
 
     def __init__(self, pool_bytes: int, max_iters: int = 50, rel_tol: float = 1e-6,
                  refresh_every: int = 0, flags: int = 0, step_iters: int = 10,
-                 device: Optional[int] = None):
+                 device: Optional[int] = None, tune: bool = True):
         self._lib = lib()
         self.opts = make_opts(max_iters, rel_tol, refresh_every, flags)
         self.pool = None
@@ -350,6 +405,14 @@ class Server:
                                             ctypes.byref(h)))
         self._h = h
         self.device = device
+        if tune:   # per-shape tiles stored by the autotuner
+            from . import autotune
+            for shape, te in autotune.serving_tiles().items():
+                M, N = (int(v) for v in shape.split("x"))
+                self.set_tiling(M, N, te)
+
+    def set_tiling(self, M: int, N: int, tile_elems: int):
+        _check(self._lib.otfs_server_set_tiling(self._h, int(M), int(N), int(tile_elems)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

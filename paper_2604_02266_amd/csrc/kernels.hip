@@ -129,22 +129,46 @@ __device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, uint32_t i) 
 __device__ __forceinline__ float2 buf_ld2b(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vb, sb, 0));
 }
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// Two adjacent complex64 elements moved as one 16-byte access (the paired gathers).
+template <int POLICY = 0>
+__device__ __forceinline__ u32x4 buf_ld4b(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+  return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, vb, sb, POLICY));
+}
+__device__ __forceinline__ void unpack2(u32x4 v, float2& a, float2& b) {
+  a = __builtin_bit_cast(float2, u32x2{v.x, v.y});
+  b = __builtin_bit_cast(float2, u32x2{v.z, v.w});
+}
+__device__ __forceinline__ u32x4 pack2(float2 a, float2 b) {
+  const u32x2 x = __builtin_bit_cast(u32x2, a), y = __builtin_bit_cast(u32x2, b);
+  return u32x4{x.x, x.y, y.x, y.y};
+}
 struct SrcBuf {   // complex64 vector
   __amdgpu_buffer_rsrc_t r;
   static constexpr int kNV = 1;
   static constexpr bool kStageable = true;
+  static constexpr bool kPairs = true;
   using Raw = float2;
+  using Raw2 = u32x4;
   __device__ __forceinline__ Raw load(uint32_t i) const { return buf_ld2(r, i); }
   __device__ __forceinline__ Raw load_b(uint32_t vb, uint32_t sb) const { return buf_ld2b(r, vb, sb); }
   __device__ __forceinline__ float2 value(Raw v) const { return v; }
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int) const { return r; }
   __device__ __forceinline__ float2 combine(const float2* v) const { return v[0]; }
   __device__ __forceinline__ void own(uint32_t i, float2* v) const { v[0] = buf_ld2(r, i); }
+  // pairs: the elements at byte offsets vb + sb and vb + sb + 8
+  __device__ __forceinline__ Raw2 load2_b(uint32_t vb, uint32_t sb) const { return buf_ld4b(r, vb, sb); }
+  __device__ __forceinline__ void value2(const Raw2& v, float2& a, float2& b) const { unpack2(v, a, b); }
+  __device__ __forceinline__ void own2(uint32_t i, float2* a, float2* b) const {
+    unpack2(buf_ld4b(r, i * 8u, 0), a[0], b[0]);
+  }
 };
 struct SrcBf16 {  // complex stored as a bf16 pair per element (not staged)
   __amdgpu_buffer_rsrc_t r;
   static constexpr int kNV = 1;
   static constexpr bool kStageable = false;
+  static constexpr bool kPairs = false;
   using Raw = uint32_t;
   __device__ __forceinline__ Raw load(uint32_t i) const {
     return __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0);
@@ -176,6 +200,24 @@ struct SrcDir {   // the new direction c + beta p, formed from c and the old p
     v[0] = buf_ld2(c, i);
     v[1] = buf_ld2(p, i);
   }
+  static constexpr bool kPairs = true;
+  struct Raw2 {
+    u32x4 c, p;
+  };
+  __device__ __forceinline__ Raw2 load2_b(uint32_t vb, uint32_t sb) const {
+    return Raw2{buf_ld4b(c, vb, sb), buf_ld4b(p, vb, sb)};
+  }
+  __device__ __forceinline__ void value2(const Raw2& v, float2& a, float2& b) const {
+    float2 c0, c1, p0, p1;
+    unpack2(v.c, c0, c1);
+    unpack2(v.p, p0, p1);
+    a = axpyf(beta, p0, c0);
+    b = axpyf(beta, p1, c1);
+  }
+  __device__ __forceinline__ void own2(uint32_t i, float2* a, float2* b) const {
+    unpack2(buf_ld4b(c, i * 8u, 0), a[0], b[0]);
+    unpack2(buf_ld4b(p, i * 8u, 0), a[1], b[1]);
+  }
 };
 struct SrcLds {   // complex64 vector in LDS
   LdsC v;
@@ -185,6 +227,58 @@ struct SrcLds {   // complex64 vector in LDS
     return v.ld((int)((vb + sb) >> 3));
   }
   __device__ __forceinline__ float2 value(Raw x) const { return x; }
+};
+struct SrcC128 {  // complex128 vector (16 B per element; offsets given for complex64)
+  __amdgpu_buffer_rsrc_t r;
+  using Raw = u32x4;
+  __device__ __forceinline__ Raw load_b(uint32_t vb, uint32_t sb) const {
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, 2u * vb, 2u * sb, 0));
+  }
+  __device__ __forceinline__ double2 value(Raw v) const { return __builtin_bit_cast(double2, v); }
+};
+
+// Arithmetic of a band application: FP32 (the CG passes) or FP64 (the true-residual
+// refresh), each with the delay-ramp and wrap tables of its precision.
+struct ArithF32 {
+  using C = float2;
+  static constexpr uint32_t kTabBytes = 8;
+  __device__ static __forceinline__ C zero() { return make_float2(0.f, 0.f); }
+  __device__ static __forceinline__ C conj(C a) { return make_float2(a.x, -a.y); }
+  __device__ static __forceinline__ C mul(C a, C b) { return cmulf(a, b); }
+  __device__ static __forceinline__ void mac(C& acc, C c, C v) { cmacf(acc, c, v); }
+  __device__ static __forceinline__ C from(float2 v) { return v; }
+  __device__ static __forceinline__ const void* rtab(const FrameDev& F) { return F.rtab; }
+  __device__ static __forceinline__ const void* wtab(const FrameDev& F) { return F.wtab; }
+  __device__ static __forceinline__ C tab(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vb, sb, 0));
+  }
+  __device__ static __forceinline__ C tab_s(const void* t, int i) {   // wave-uniform index
+    return __builtin_bit_cast(float2, ((kptr<const u64>)t)[i]);
+  }
+  __device__ static __forceinline__ C tab_g(const void* t, int i) {
+    return __builtin_bit_cast(float2, ((gptr<const u64>)t)[i]);
+  }
+};
+struct ArithF64 {
+  using C = double2;
+  static constexpr uint32_t kTabBytes = 16;
+  __device__ static __forceinline__ C zero() { return make_double2(0.0, 0.0); }
+  __device__ static __forceinline__ C conj(C a) { return make_double2(a.x, -a.y); }
+  __device__ static __forceinline__ C mul(C a, C b) { return cmuld(a, b); }
+  __device__ static __forceinline__ void mac(C& acc, C c, C v) { cmacd(acc, c, v); }
+  __device__ static __forceinline__ C from(float2 v) { return make_double2((double)v.x, (double)v.y); }
+  __device__ static __forceinline__ C from(double2 v) { return v; }
+  __device__ static __forceinline__ const void* rtab(const FrameDev& F) { return F.rtab64; }
+  __device__ static __forceinline__ const void* wtab(const FrameDev& F) { return F.wtab64; }
+  __device__ static __forceinline__ C tab(__amdgpu_buffer_rsrc_t r, uint32_t vb, uint32_t sb) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vb, sb, 0));
+  }
+  __device__ static __forceinline__ C tab_s(const void* t, int i) {
+    return __builtin_bit_cast(double2, ((kptr<const u32x4>)t)[i]);
+  }
+  __device__ static __forceinline__ C tab_g(const void* t, int i) {
+    return __builtin_bit_cast(double2, ((gptr<const u32x4>)t)[i]);
+  }
 };
 // The stored coefficient table D_{p,q} (Eq. D_definition, the SS table of Eq. ds_repr):
 // one entry per (path, output element), P x E, as a bf16 pair or a complex64 value.
@@ -210,7 +304,6 @@ struct DTab<kDC64> {
   __device__ __forceinline__ float2 value(Raw w) const { return __builtin_bit_cast(float2, w); }
 };
 
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 // A complex64 vector read and written element-wise through a buffer resource (one 32-bit
 // offset per element, shared by every vector accessed at that element).
 // NT: non-temporal cache policy (streamed data that should not displace gather sources
@@ -226,6 +319,15 @@ struct CVec {
   __device__ __forceinline__ void st(uint32_t i, float2 v) const {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, 0,
                                           NT ? 2 : 0);
+  }
+  // elements i and i + 1 as one 16-byte access
+  template <bool NT = false>
+  __device__ __forceinline__ void ld2(uint32_t i, float2& a, float2& b) const {
+    unpack2(buf_ld4b<NT ? 2 : 0>(r, i * 8u, 0), a, b);
+  }
+  template <bool NT = false>
+  __device__ __forceinline__ void st2(uint32_t i, float2 a, float2 b) const {
+    __builtin_amdgcn_raw_buffer_store_b128(pack2(a, b), r, i * 8u, 0, NT ? 2 : 0);
   }
 };
 #ifndef OTFS_NT
@@ -247,14 +349,22 @@ __device__ __forceinline__ SrcDir src_dir(const float2* c, const float2* p, floa
 
 // Output views of a band application (see apply_band).
 struct NoPre {};
+// pre(q) / put(q, v, pre, own) handle output element q; pre2 / put2 the pair q, q + 1 of
+// the paired gathers (q even), in the same operations per element.
 template <bool NT = false>
 struct OutStore {   // out = v
   CVec o;
   static constexpr bool kOwn = false;
   using Pre = NoPre;
+  using Pre2 = NoPre;
   __device__ __forceinline__ Pre pre(uint32_t) const { return Pre{}; }
   __device__ __forceinline__ void put(uint32_t q, float2 v, const Pre&, const float2*) const {
     o.st<NT>(q, v);
+  }
+  __device__ __forceinline__ Pre2 pre2(uint32_t) const { return Pre2{}; }
+  __device__ __forceinline__ void put2(uint32_t q, float2 v0, float2 v1, const Pre2&,
+                                       const float2*, const float2*) const {
+    o.st2<NT>(q, v0, v1);
   }
 };
 struct OutInit {    // b = H^H y: c = p = b, x = 0, partial ||b||^2
@@ -269,6 +379,18 @@ struct OutInit {    // b = H^H y: c = p = b, x = 0, partial ||b||^2
     x.st(q, make_float2(0.f, 0.f));
     *acc = fmaf(v.x, v.x, *acc);
     *acc = fmaf(v.y, v.y, *acc);
+  }
+  using Pre2 = NoPre;
+  __device__ __forceinline__ Pre2 pre2(uint32_t) const { return Pre2{}; }
+  __device__ __forceinline__ void put2(uint32_t q, float2 v0, float2 v1, const Pre2&,
+                                       const float2*, const float2*) const {
+    c.st2(q, v0, v1);
+    p.st2(q, v0, v1);
+    x.st2(q, make_float2(0.f, 0.f), make_float2(0.f, 0.f));
+    *acc = fmaf(v0.x, v0.x, *acc);
+    *acc = fmaf(v0.y, v0.y, *acc);
+    *acc = fmaf(v1.x, v1.x, *acc);
+    *acc = fmaf(v1.y, v1.y, *acc);
   }
 };
 struct OutA {       // t = H p', p_new = c + beta p_old, x += alpha p_old (deferred updates)
@@ -287,6 +409,20 @@ struct OutA {       // t = H p', p_new = c + beta p_old, x += alpha p_old (defer
     pn.st(q, axpyf(beta, own[1], own[0]));
     if (xp) x.st(q, axpyf(alpha, own[1], pr.x));
   }
+  struct Pre2 {
+    float2 x0, x1;
+  };
+  __device__ __forceinline__ Pre2 pre2(uint32_t q) const {
+    Pre2 r{make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+    if (xp) x.ld2(q, r.x0, r.x1);
+    return r;
+  }
+  __device__ __forceinline__ void put2(uint32_t q, float2 v0, float2 v1, const Pre2& pr,
+                                       const float2* own0, const float2* own1) const {
+    t.st2(q, v0, v1);
+    pn.st2(q, axpyf(beta, own0[1], own0[0]), axpyf(beta, own1[1], own1[0]));
+    if (xp) x.st2(q, axpyf(alpha, own0[1], pr.x0), axpyf(alpha, own1[1], pr.x1));
+  }
 };
 struct OutB {       // a = H^H t + lam p', partial Re(p'^H a)
   CVec a, pn;
@@ -302,6 +438,23 @@ struct OutB {       // a = H^H t + lam p', partial Re(p'^H a)
     a.st<kNtB>(q, av);
     *acc = fmaf(pr.p.x, av.x, *acc);
     *acc = fmaf(pr.p.y, av.y, *acc);
+  }
+  struct Pre2 {
+    float2 p0, p1;
+  };
+  __device__ __forceinline__ Pre2 pre2(uint32_t q) const {
+    Pre2 r;
+    pn.ld2<kNtB>(q, r.p0, r.p1);
+    return r;
+  }
+  __device__ __forceinline__ void put2(uint32_t q, float2 v0, float2 v1, const Pre2& pr,
+                                       const float2*, const float2*) const {
+    const float2 a0 = axpyf(lam, pr.p0, v0), a1 = axpyf(lam, pr.p1, v1);
+    a.st2<kNtB>(q, a0, a1);
+    *acc = fmaf(pr.p0.x, a0.x, *acc);
+    *acc = fmaf(pr.p0.y, a0.y, *acc);
+    *acc = fmaf(pr.p1.x, a1.x, *acc);
+    *acc = fmaf(pr.p1.y, a1.y, *acc);
   }
 };
 
@@ -565,10 +718,14 @@ constexpr int kPathsGeneral = OTFS_PATHS_GENERAL;   // the same where rows are p
 #endif
 constexpr int kFdRows = OTFS_FD_ROWS;     // H pass forming the direction in its gathers
 constexpr int kFdPaths = OTFS_FD_PATHS;
-#ifndef OTFS_FUSED_MIN_WAVES
-#define OTFS_FUSED_MIN_WAVES 4
+#ifndef OTFS_PAIR_PATHS
+#define OTFS_PAIR_PATHS 4
 #endif
-constexpr int kRows64 = 2;   // rows per thread chunk in the FP64 refresh gathers
+// paths in flight together in the paired gathers (each gather holds twice the registers)
+constexpr int kPairPaths = OTFS_PAIR_PATHS;
+#ifndef OTFS_FUSED_MIN_WAVES
+#define OTFS_FUSED_MIN_WAVES 2
+#endif
 #ifndef OTFS_ELEM_CHUNK
 #define OTFS_ELEM_CHUNK 8
 #endif
@@ -586,9 +743,10 @@ constexpr int kElemChunkFd = OTFS_ELEM_CHUNK_FD;   // the same in the direct-fd 
 constexpr int kResRows = OTFS_RES_ROWS;    // rows per chunk of the LDS-resident gathers
 constexpr int kResPaths = OTFS_RES_PATHS;  // paths per step of the LDS-resident gathers
 
-template <int R, int U, bool ADJ, int SD, bool UNI, class Src, class Pref, class Sink>
+template <int R, int U, bool ADJ, int SD, bool UNI, class A, class Src, class Pref, class Sink>
 __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int le, const Src& src,
                                                 Pref pref, Sink sink) {
+  using C = typename A::C;
   constexpr bool STORED = SD != kDNone;
   const int M = F.M, N = F.N, P = F.P;
   const int TX = M < kBlock ? M : kBlock;
@@ -601,25 +759,25 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
   if (ty >= TY) return;
   const int64_t E = (int64_t)M * N;
   const uint32_t M8 = 8u * (uint32_t)M, E8 = 8u * (uint32_t)E;   // E8 < 2^31
+  constexpr uint32_t TS = A::kTabBytes / 8u;                      // table entry / 8 bytes
   const int nrows = le - lb - ty > 0 ? (le - lb - ty + TY - 1) / TY : 0;
   const KPairs paths = kpairs(F.paths);
-  const KPairs wtab_s = kpairs(F.wtab);
-  const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(F.rtab, (int64_t)P * M * 8);
-  const GPairs wtab = gpairs(F.wtab);
+  const void* wt = A::wtab(F);
+  const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(A::rtab(F), (int64_t)P * M * A::kTabBytes);
   const DTab<SD> dtab{F.dtab};
   for (int k = tx; k < M; k += TX) {
     for (int r0 = 0; r0 < nrows; r0 += R) {
       int l[R];
       uint32_t l8[R];   // byte offset of row l
-      float2 wl[R];
-      float2 acc[R];
+      C wl[R];
+      C acc[R];
       decltype(pref(0u)) pf[R];   // the outputs' own loads, issued with the gathers
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         l[i] = lb + ty + min(r0 + i, nrows - 1) * TY;
         l8[i] = (uint32_t)l[i] * M8;
-        if (!STORED) wl[i] = UNI ? wtab_s.f(l[i]) : wtab.f(l[i]);
-        acc[i] = make_float2(0.f, 0.f);
+        if (!STORED) wl[i] = UNI ? A::tab_s(wt, l[i]) : A::tab_g(wt, l[i]);
+        acc[i] = A::zero();
         pf[i] = pref((uint32_t)(l[i] * M + k));
       }
       // NP paths at once: all NP*R gathers are issued before any is consumed
@@ -627,7 +785,7 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
         constexpr int NP = decltype(npc)::value;
         uint32_t kk8[NP], dn8[NP];
         bool lo[NP], hi[NP];   // delay wrap: the source column is K + M (lo) or K - M (hi)
-        float2 cf[NP], wn[NP];
+        C cf[NP], wn[NP];
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
           const int2 tn = paths.i2(p0 + u);
@@ -639,11 +797,10 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
           const int sh = ADJ ? tn.y : -tn.y;
           dn8[u] = (uint32_t)((sh < 0 ? sh : sh - N) * M8);
           if (!STORED) {
-            const float2 r = __builtin_bit_cast(
-                float2, __builtin_amdgcn_raw_buffer_load_b64(
-                            rtab, ADJ ? kk8[u] : 8u * (uint32_t)k, (uint32_t)(p0 + u) * M8, 0));
-            cf[u] = ADJ ? make_float2(r.x, -r.y) : r;
-            if (!ADJ) wn[u] = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
+            const C r = A::tab(rtab, TS * (ADJ ? kk8[u] : 8u * (uint32_t)k),
+                               TS * (uint32_t)(p0 + u) * M8);
+            cf[u] = ADJ ? A::conj(r) : r;
+            if (!ADJ) wn[u] = A::tab_s(wt, tn.y < 0 ? tn.y + N : tn.y);
           }
         }
         typename Src::Raw v[NP][R];
@@ -666,26 +823,33 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
         }
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
-          if (STORED) {
+          if constexpr (STORED) {
 #pragma unroll
             for (int i = 0; i < R; ++i) {
               const float2 dd = dtab.value(d[u][i]);
-              cmacf(acc[i], ADJ ? make_float2(dd.x, -dd.y) : dd, src.value(v[u][i]));
-            }
-          } else if (__builtin_amdgcn_ballot_w64(lo[u] || hi[u]) != 0) {
-            // a wave holding a delay wrap of this path (few of them): wrapped lanes take
-            // W^n, n = -1 (lo) or +1 (hi); for H also the path part conj(W[nu])^n
-            const float2 cw = ADJ ? cf[u]
-                                  : cmulf(cf[u], make_float2(wn[u].x, hi[u] ? -wn[u].y : wn[u].y));
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-              const float2 w = make_float2(wl[i].x, hi[u] ? wl[i].y : -wl[i].y);
-              const float2 c = (lo[u] || hi[u]) ? cmulf(cw, w) : cf[u];
-              cmacf(acc[i], c, src.value(v[u][i]));
+              A::mac(acc[i], ADJ ? A::conj(dd) : dd, A::from(src.value(v[u][i])));
             }
           } else {
+            if (__builtin_amdgcn_ballot_w64(lo[u] || hi[u]) != 0) {
+              // a wave holding a delay wrap of this path (few of them): wrapped lanes take
+              // W^n, n = -1 (lo) or +1 (hi); for H also the path part conj(W[nu])^n
+              C cw = cf[u];
+              if (!ADJ) {
+                C wv = wn[u];
+                if (hi[u]) wv.y = -wv.y;
+                cw = A::mul(cf[u], wv);
+              }
 #pragma unroll
-            for (int i = 0; i < R; ++i) cmacf(acc[i], cf[u], src.value(v[u][i]));
+              for (int i = 0; i < R; ++i) {
+                C w = wl[i];
+                if (!hi[u]) w.y = -w.y;
+                const C c = (lo[u] || hi[u]) ? A::mul(cw, w) : cf[u];
+                A::mac(acc[i], c, A::from(src.value(v[u][i])));
+              }
+            } else {
+#pragma unroll
+              for (int i = 0; i < R; ++i) A::mac(acc[i], cf[u], A::from(src.value(v[u][i])));
+            }
           }
         }
       };
@@ -705,17 +869,178 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
   }
 }
 
-template <int R, int U, bool ADJ, int SD, class Src, class Pref, class Sink>
+template <int R, int U, bool ADJ, int SD, class Src, class Pref, class Sink, class A = ArithF32>
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
-                                           Pref pref, Sink sink) {
+                                           Pref pref, Sink sink, A = A{}) {
   const int TX = F.M < kBlock ? F.M : kBlock;
   // the per-lane row arithmetic of the general form holds more registers: fewer paths
   // in flight there
   if ((TX & 63) == 0)
-    band_apply_rows<R, U, ADJ, SD, true>(F, lb, le, src, pref, sink);
+    band_apply_rows<R, U, ADJ, SD, true, A>(F, lb, le, src, pref, sink);
   else
-    band_apply_rows<R, (U < kPathsGeneral ? U : kPathsGeneral), ADJ, SD, false>(F, lb, le, src,
-                                                                                  pref, sink);
+    band_apply_rows<R, (U < kPathsGeneral ? U : kPathsGeneral), ADJ, SD, false, A>(F, lb, le, src,
+                                                                                     pref, sink);
+}
+
+// Frames whose gathers run in pairs: M a multiple of 128 (every wave in one row), and the
+// frame at an even element offset in batch-wide buffers (16-byte aligned pairs).
+__device__ __forceinline__ bool pairs_ok(const FrameDev& F) {
+#ifdef OTFS_NO_PAIRS
+  return false;
+#else
+  return (F.M & 127) == 0 && (F.off & 1) == 0;
+#endif
+}
+
+// ---------------------------------------------------------------------------------------
+// Paired band application (frames with M a multiple of 128, synthesised coefficients).
+//
+// The same sums as band_apply_rows, but each lane owns two adjacent delay columns k, k + 1
+// (k even) and every access moves 16 bytes: one gather brings the two source elements
+// <k -+ tau>_M and <k + 1 -+ tau>_M of a row, one table read the two coefficients of H
+// (R_p[k], R_p[k + 1]), one store the two outputs.  A wave reads or writes 1 KiB per
+// instruction instead of 512 B, which halves the vector-memory instructions for the same
+// bytes (the gathers are bound by the rate at which those instructions issue, not by the
+// bytes they move).  The one lane of a row whose two sources straddle the row's wrap point
+// (source columns M - 1 and 0, or for H^H coefficients R_p[M - 1] and R_p[0]) takes its
+// second element from a fix-up read at column 0, issued only by the waves holding such a
+// lane, together with the main reads.  Wrap factors apply per element exactly as in
+// band_apply_rows (each element has its own wrap count), so each output element is formed
+// by the same operations in the same path order.
+// ---------------------------------------------------------------------------------------
+template <int R, int U, bool ADJ, class Src, class Pref, class Sink>
+__device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int le, const Src& src,
+                                                 Pref pref, Sink sink) {
+  const int M = F.M, N = F.N, P = F.P;
+  const int M2 = M >> 1;
+  const int TX = M2 < kBlock ? M2 : kBlock;   // a multiple of 64: every wave in one row
+  const int TY = kBlock / TX;
+  const int tx = threadIdx.x % TX;
+  const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TX);
+  if (ty >= TY) return;
+  const int64_t E = (int64_t)M * N;
+  const uint32_t M8 = 8u * (uint32_t)M, E8 = 8u * (uint32_t)E;   // E8 < 2^31
+  const int nrows = le - lb - ty > 0 ? (le - lb - ty + TY - 1) / TY : 0;
+  const KPairs paths = kpairs(F.paths);
+  const KPairs wtab_s = kpairs(F.wtab);
+  const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(F.rtab, (int64_t)P * M * 8);
+  for (int k = 2 * tx; k < M; k += 2 * TX) {
+    for (int r0 = 0; r0 < nrows; r0 += R) {
+      int l[R];
+      uint32_t l8[R];
+      float2 wl[R];
+      float2 acc0[R], acc1[R];
+      decltype(pref(0u)) pf[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        l[i] = lb + ty + min(r0 + i, nrows - 1) * TY;
+        l8[i] = (uint32_t)l[i] * M8;
+        wl[i] = wtab_s.f(l[i]);
+        acc0[i] = make_float2(0.f, 0.f);
+        acc1[i] = make_float2(0.f, 0.f);
+        pf[i] = pref((uint32_t)(l[i] * M + k));
+      }
+      auto step = [&](auto npc, int p0) {
+        constexpr int NP = decltype(npc)::value;
+        uint32_t kk8[NP], dn8[NP];
+        bool lo0[NP], hi0[NP], lo1[NP], hi1[NP], split[NP];
+        u32x4 cf2[NP];
+        float2 wn[NP];
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+          const int2 tn = paths.i2(p0 + u);
+          const int K = ADJ ? k + tn.x : k - tn.x;   // source column of element 0 (unwrapped)
+          lo0[u] = K < 0;
+          hi0[u] = K >= M;
+          lo1[u] = K + 1 < 0;
+          hi1[u] = K + 1 >= M;
+          const int s0 = lo0[u] ? K + M : (hi0[u] ? K - M : K);
+          split[u] = s0 == M - 1;
+          kk8[u] = 8u * (uint32_t)s0;
+          const int sh = ADJ ? tn.y : -tn.y;
+          dn8[u] = (uint32_t)((sh < 0 ? sh : sh - N) * M8);
+          // H: R_p[k], R_p[k + 1]; H^H: R_p at the two source columns (conjugated below)
+          cf2[u] = buf_ld4b(rtab, ADJ ? kk8[u] : 8u * (uint32_t)k, (uint32_t)(p0 + u) * M8);
+          if (!ADJ) wn[u] = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
+        }
+        typename Src::Raw2 v[NP][R];
+        typename Src::Raw fx[NP][R];   // fix-up: second element of a straddling pair
+        float2 cfx[NP];
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const uint32_t x = l8[i] + dn8[u];
+            const uint32_t rs = min(x, x + E8);
+            v[u][i] = src.load2_b(kk8[u], rs);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+          if (__builtin_amdgcn_ballot_w64(split[u]) != 0) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+              const uint32_t x = l8[i] + dn8[u];
+              const uint32_t rs = min(x, x + E8);
+              fx[u][i] = src.load_b(0u, rs);
+            }
+            if (ADJ) cfx[u] = __builtin_bit_cast(
+                float2, __builtin_amdgcn_raw_buffer_load_b64(rtab, 0u, (uint32_t)(p0 + u) * M8, 0));
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+          float2 c0, c1;
+          unpack2(cf2[u], c0, c1);
+          const bool sp = __builtin_amdgcn_ballot_w64(split[u]) != 0;
+          if (ADJ) {
+            if (sp && split[u]) c1 = cfx[u];
+            c0 = make_float2(c0.x, -c0.y);
+            c1 = make_float2(c1.x, -c1.y);
+          }
+          float2 e0[R], e1[R];
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            src.value2(v[u][i], e0[i], e1[i]);
+            if (sp && split[u]) e1[i] = src.value(fx[u][i]);
+          }
+          if (__builtin_amdgcn_ballot_w64(lo0[u] || hi0[u] || lo1[u] || hi1[u]) != 0) {
+            // waves holding a delay wrap of this path: wrapped elements take W^n
+            float2 cw0 = c0, cw1 = c1;
+            if (!ADJ) {
+              cw0 = cmulf(c0, make_float2(wn[u].x, hi0[u] ? -wn[u].y : wn[u].y));
+              cw1 = cmulf(c1, make_float2(wn[u].x, hi1[u] ? -wn[u].y : wn[u].y));
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+              const float2 w0 = make_float2(wl[i].x, hi0[u] ? wl[i].y : -wl[i].y);
+              const float2 w1 = make_float2(wl[i].x, hi1[u] ? wl[i].y : -wl[i].y);
+              cmacf(acc0[i], (lo0[u] || hi0[u]) ? cmulf(cw0, w0) : c0, e0[i]);
+              cmacf(acc1[i], (lo1[u] || hi1[u]) ? cmulf(cw1, w1) : c1, e1[i]);
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+              cmacf(acc0[i], c0, e0[i]);
+              cmacf(acc1[i], c1, e1[i]);
+            }
+          }
+        }
+      };
+      int p = 0;
+      for (; p + U <= P; p += U) step(std::integral_constant<int, U>{}, p);
+      if constexpr (U > 2) {
+        if (p + 2 <= P) {
+          step(std::integral_constant<int, 2>{}, p);
+          p += 2;
+        }
+      }
+      for (; p < P; ++p) step(std::integral_constant<int, 1>{}, p);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (r0 + i < nrows) sink((uint32_t)(l[i] * M + k), acc0[i], acc1[i], pf[i]);
+    }
+  }
 }
 
 // band_apply with nothing to prefetch: sink(q, v)
@@ -876,6 +1201,26 @@ __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, fl
   if constexpr (STAGED && SD == kDNone && Src::kStageable) {
     staged_apply<ADJ>(F, lb, le, lds, src, out);
   } else {
+    if constexpr (SD == kDNone && Src::kPairs) {
+      if (pairs_ok(F)) {
+        struct PreOwn2 {
+          typename Out::Pre2 pre;
+          float2 own0[Src::kNV], own1[Src::kNV];
+        };
+        band_apply_pairs<R, (UP < kPairPaths ? UP : kPairPaths), ADJ>(
+            F, lb, le, src,
+            [&](uint32_t u) {
+              PreOwn2 po;
+              po.pre = out.pre2(u);
+              if (Out::kOwn) src.own2(u, po.own0, po.own1);
+              return po;
+            },
+            [&](uint32_t q, float2 v0, float2 v1, const PreOwn2& po) {
+              out.put2(q, v0, v1, po.pre, po.own0, po.own1);
+            });
+        return;
+      }
+    }
     struct PreOwn {
       typename Out::Pre pre;
       float2 own[Src::kNV];
@@ -1088,54 +1433,6 @@ __device__ __forceinline__ void win_apply_any(const FrameDev& F, int k0, float2*
 #endif
 }
 
-// FP64 version (coefficients from the FP64 tables) for the true-residual refresh.
-template <int R, bool ADJ, class Src, class Sink>
-__device__ __forceinline__ void band_apply64(const FrameDev& F, int lb, int le, Src src,
-                                             Sink sink) {
-  const int M = F.M, N = F.N, P = F.P;
-  const int TX = M < kBlock ? M : kBlock;
-  const int TY = kBlock / TX;
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  if (ty >= TY) return;
-  const int nrows = le - lb - ty > 0 ? (le - lb - ty + TY - 1) / TY : 0;
-  for (int k = tx; k < M; k += TX) {
-    for (int r0 = 0; r0 < nrows; r0 += R) {
-      double2 acc[R];
-#pragma unroll
-      for (int i = 0; i < R; ++i) acc[i] = make_double2(0.0, 0.0);
-      for (int p = 0; p < P; ++p) {
-        const int2 tn = F.paths[p];
-        const int K = ADJ ? k + tn.x : k - tn.x;
-        const int n = K < 0 ? -1 : (K >= M ? 1 : 0);
-        const int kk = K - n * M;
-        const double2 r = F.rtab64[p * M + (ADJ ? kk : k)];
-        const double2 cf = ADJ ? make_double2(r.x, -r.y) : r;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          if (r0 + i < nrows) {
-            const int l = lb + ty + (r0 + i) * TY;
-            int ls = ADJ ? l + tn.y : l - tn.y;
-            ls += ls < 0 ? N : 0;
-            ls -= ls >= N ? N : 0;
-            const double2 v = src(ls * M + kk);
-            double2 c = cf;
-            if (n != 0) {
-              double2 w = F.wtab64[ADJ ? l : ls];
-              if (n < 0) w.y = -w.y;
-              c = cmuld(c, w);
-            }
-            cmacd(acc[i], c, v);
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (r0 + i < nrows) sink((lb + ty + (r0 + i) * TY) * M + k, acc[i]);
-    }
-  }
-}
-
-
 // ---------------------------------------------------------------------------------------
 // hard decisions (Eq. demod): nearest square-QAM level per axis, ties to the upper level
 // ---------------------------------------------------------------------------------------
@@ -1222,8 +1519,12 @@ __device__ void finish_tile(const FrameDev& F, const WorkItem& wi, const FrameVe
 //   C: alpha = c_norm / Re(p^H a); c -= alpha a, partial ||c||^2;            | barrier
 //   then every workgroup forms the same c_norm' in the same order, tests the stop rule
 //   and sets beta = c_norm' / c_norm.  x += alpha p stays pending until the next A (or
-//   the finish).  Every k-th iteration (refresh_every) c is replaced by the FP64 true
-//   residual H^H (y - H x) - lam x (two more passes, two more barriers).
+//   the finish).
+// FP64 true-residual refresh: after every k-th iteration (refresh_every) the C pass also
+// applies x += alpha p, and the frame leaves the launch with its state marked `refresh`.
+// The refresh launches (k_refresh_u, k_refresh_c) then replace c by the true residual
+// H^H (y - H x) - lam x formed in FP64 and leave its FP64 partial norms; the next fused
+// launch resumes the frame with the stop test on that norm.
 // ---------------------------------------------------------------------------------------
 struct LaunchCtx {
   unsigned* abort_flag;
@@ -1232,11 +1533,11 @@ struct LaunchCtx {
 };
 
 // FDIR: the H pass forms p' = c + beta p inside its gathers (direct-fd kind).
-template <int SD, bool REFRESH, bool STAGED, bool FDIR = false>
+template <int SD, bool STAGED, bool FDIR = false>
 __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
-                        const LaunchCtx& L, float* red, double* redd, int* sflag, float2* lds) {
-  // the bf16 table reads and the FP64 refresh leave fewer registers for gathers in flight
-  constexpr int RR = (SD != kDNone || REFRESH) ? 2 : kRows;
+                        const LaunchCtx& L, float* red, int* sflag, float2* lds) {
+  // the stored-table reads leave fewer registers for gathers in flight
+  constexpr int RR = SD != kDNone ? 2 : kRows;
   const FrameVecs V = frame_vecs(F, B);
   FrameState s = *F.st;
   if (s.status != OTFS_FRAME_RUNNING) return;
@@ -1309,11 +1610,40 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     }
   }
 
+  // After the C pass of iteration s.iter: the stop test on the residual norm cn_new, then
+  // beta for the next direction.  xpend: x += alpha p of that iteration is still to do.
+  // Returns false when the frame is finished (its tile already finalised).
+  auto next = [&](float cn_new, bool xpend, float2* pcur) -> bool {
+    s.rel = sqrtf(cn_new / s.cn0);
+    int st = OTFS_FRAME_RUNNING;
+    if (!isfinite(cn_new))
+      st = OTFS_FRAME_NONFINITE;
+    else if (F.tol > 0.f && s.rel <= F.tol)
+      st = OTFS_FRAME_CONVERGED;
+    else if (s.iter >= F.max_iters)
+      st = OTFS_FRAME_CAPPED;
+    if (st != OTFS_FRAME_RUNNING) {
+      finish_tile(F, wi, V, s, pcur, xpend, st);
+      return false;
+    }
+    s.beta = cn_new / s.cn;
+    s.cn = cn_new;
+    s.pending = (xpend ? 1 : 0) | 2;
+    return true;
+  };
+  if (s.refresh) {   // resume after the refresh launches: the true residual's norm
+    s.refresh = 0;
+    if (!next((float)tile_sum_d(F.part_d, T), false, F.p0)) return;
+  }
+
   for (int step = 0; step < budget; ++step) {
     const int xi = s.iter + 1;
     float2* const pold_g = s.pbuf ? F.p1 : F.p0;
     float2* const pnew_g = s.pbuf ? F.p0 : F.p1;
     const CVec pov = cvec(pold_g, E), pnv = cvec(pnew_g, E);
+    // the refresh launches follow this iteration: x += alpha p is applied in the C pass
+    const bool refresh_due =
+        F.refresh_every > 0 && xi % F.refresh_every == 0 && xi < F.max_iters;
     // iteration 1 has no pending update: beta = 0 gives p_new = c = b exactly
     const bool xp = (s.pending & 1) != 0;
     const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
@@ -1331,6 +1661,27 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
                                                          OutA{tv, pnv, xv, al, be, xp});
     } else {
       // A1: p' = c + beta p_old and x += alpha p_old over the band, stored once
+      if (pairs_ok(F)) {   // two elements per lane and access (16-byte loads and stores)
+        constexpr int EP = kElemChunk / 2;
+        for (uint32_t u = u0 + 2u * threadIdx.x; u < u1; u += 2u * kBlock * EP) {
+          float2 c0[EP], c1[EP], p0[EP], p1[EP], x0[EP], x1[EP];
+#pragma unroll
+          for (int j = 0; j < EP; ++j) {
+            const uint32_t w = min(u + (uint32_t)(2 * j * kBlock), u1 - 2u);
+            cv.ld2<kNtElem>(w, c0[j], c1[j]);
+            pov.ld2<kNtElem>(w, p0[j], p1[j]);
+            if (xp) xv.ld2<kNtElem>(w, x0[j], x1[j]);
+          }
+#pragma unroll
+          for (int j = 0; j < EP; ++j) {
+            const uint32_t w = u + (uint32_t)(2 * j * kBlock);
+            if (w < u1) {
+              pnv.st2<kNtP>(w, axpyf(be, p0[j], c0[j]), axpyf(be, p1[j], c1[j]));
+              if (xp) xv.st2<kNtElemSt>(w, axpyf(al, p0[j], x0[j]), axpyf(al, p1[j], x1[j]));
+            }
+          }
+        }
+      } else
       for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * kElemChunk) {
         float2 c[kElemChunk], po[kElemChunk], xo[kElemChunk];
 #pragma unroll
@@ -1383,6 +1734,30 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
       // EC elements per thread at a time, all loads issued first (past the band's end the
       // last element is re-read and nothing is stored)
       constexpr int EC = FDIR ? kElemChunkFd : kElemChunk;
+      if (pairs_ok(F)) {   // two elements per lane and access; the same sums per element
+        constexpr int EP = EC / 2;
+        for (uint32_t u = u0 + 2u * threadIdx.x; u < u1; u += 2u * kBlock * EP) {
+          float2 a0[EP], a1[EP], c0[EP], c1[EP];
+#pragma unroll
+          for (int j = 0; j < EP; ++j) {
+            const uint32_t w = min(u + (uint32_t)(2 * j * kBlock), u1 - 2u);
+            av.ld2<kNtElem>(w, a0[j], a1[j]);
+            cv.ld2<kNtElem>(w, c0[j], c1[j]);
+          }
+#pragma unroll
+          for (int j = 0; j < EP; ++j) {
+            const uint32_t w = u + (uint32_t)(2 * j * kBlock);
+            if (w < u1) {
+              const float2 n0 = axpyf(-alpha, a0[j], c0[j]), n1 = axpyf(-alpha, a1[j], c1[j]);
+              cv.st2<kNtElemSt>(w, n0, n1);
+              acc = fmaf(n0.x, n0.x, acc);
+              acc = fmaf(n0.y, n0.y, acc);
+              acc = fmaf(n1.x, n1.x, acc);
+              acc = fmaf(n1.y, n1.y, acc);
+            }
+          }
+        }
+      } else
       for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * EC) {
         float2 a[EC], c[EC];
 #pragma unroll
@@ -1402,58 +1777,26 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
           }
         }
       }
+      if (refresh_due) {   // x += alpha p' before the refresh launches read x
+        for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock)
+          xv.st(u, axpyf(alpha, pnv.ld(u), xv.ld(u)));
+      }
       const float bs = block_sum(acc, red);
       if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
     }
     if (!bar()) return fail_timeout();
-    float cn_new = tile_sum(F.part_cc, T);
+    const float cn_new = tile_sum(F.part_cc, T);
     s.iter = xi;
     s.alpha = alpha;
-    bool xpend = true;                               // x += alpha p_new still to do
-
-    // ---- FP64 true-residual refresh ----
-    if (REFRESH && F.refresh_every > 0 && xi % F.refresh_every == 0 && xi < F.max_iters &&
-        isfinite(cn_new)) {
-      // R1: u = y - H (x + alpha p) in FP64 (x itself is not written while others read it)
-      band_apply64<kRows64, false>(
-          F, lb, le,
-          [&](int i) {
-            const float2 xe = axpyf(alpha, pnv.ld((uint32_t)i), xv.ld((uint32_t)i));
-            return make_double2((double)xe.x, (double)xe.y);
-          },
-          [&](int q, double2 v) {
-            const float2 yv = load_y(V.y, q, V.ybf16);
-            F.u[q] = make_double2((double)yv.x - v.x, (double)yv.y - v.y);
-          });
-      if (!bar()) return fail_timeout();
-      // R2: c = H^H u - lam x, with x += alpha p applied here
-      double acc = 0.0;
-      band_apply64<kRows64, true>(
-          F, lb, le, [&](int i) { return F.u[i]; },
-          [&](int q, double2 v) {
-            const float2 xn = axpyf(alpha, pnv.ld((uint32_t)q), xv.ld((uint32_t)q));
-            xv.st((uint32_t)q, xn);
-            const float2 cf = make_float2((float)(v.x - (double)lam * (double)xn.x),
-                                          (float)(v.y - (double)lam * (double)xn.y));
-            cv.st((uint32_t)q, cf);
-            acc = fma((double)cf.x, (double)cf.x, acc);
-            acc = fma((double)cf.y, (double)cf.y, acc);
-          });
-      const double bs = block_sum_d(acc, redd);
-      if (threadIdx.x == 0) F.part_d[wi.tile] = bs;
-      if (!bar()) return fail_timeout();
-      cn_new = (float)tile_sum_d(F.part_d, T);
-      xpend = false;
+    if (refresh_due) {
+      if (!isfinite(cn_new)) return finish_tile(F, wi, V, s, pnew_g, false, OTFS_FRAME_NONFINITE);
+      // leave the launch: the refresh launches form the true residual of x
+      s.refresh = 1;
+      s.pending = 0;
+      if (wi.tile == 0 && threadIdx.x == 0) *F.st = s;
+      return;
     }
-
-    s.rel = sqrtf(cn_new / s.cn0);
-    if (!isfinite(cn_new)) return finish_tile(F, wi, V, s, pnew_g, xpend, OTFS_FRAME_NONFINITE);
-    if (F.tol > 0.f && s.rel <= F.tol)
-      return finish_tile(F, wi, V, s, pnew_g, xpend, OTFS_FRAME_CONVERGED);
-    if (xi >= F.max_iters) return finish_tile(F, wi, V, s, pnew_g, xpend, OTFS_FRAME_CAPPED);
-    s.beta = cn_new / s.cn;
-    s.cn = cn_new;
-    s.pending = (xpend ? 1 : 0) | 2;
+    if (!next(cn_new, true, pnew_g)) return;
   }
   // iteration budget of this launch used up: keep the state for the next launch
   if (wi.tile == 0 && threadIdx.x == 0) *F.st = s;
@@ -1477,7 +1820,6 @@ struct OwnCPX {      // own elements the H pass needs besides the window
   float2 c, p, x;
 };
 
-template <bool REFRESH>
 __device__ void cg_item_win(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                             const LaunchCtx& L, float* red, int* sflag, float2* lds) {
   const FrameVecs V = frame_vecs(F, B);
@@ -1805,16 +2147,25 @@ __device__ __forceinline__ int xcc_id() {
 #ifndef OTFS_WIN_MIN_WAVES
 #define OTFS_WIN_MIN_WAVES 2
 #endif
-template <int SD, bool REFRESH, int KIND>
-__global__ __launch_bounds__(kBlock, KIND == kKindWindowed ? OTFS_WIN_MIN_WAVES
-                                                           : OTFS_FUSED_MIN_WAVES) void k_cg_fused(const FrameDev* __restrict__ frames,
+// Waves per SIMD the compiler must leave room for: the direct kinds take the whole
+// register file of a CU for one 512-thread workgroup (256 VGPRs per lane: the paired
+// gathers keep 16 reads of 16 bytes in flight per lane), the LDS kinds keep two per CU.
+#ifndef OTFS_LDS_MIN_WAVES
+#define OTFS_LDS_MIN_WAVES 4
+#endif
+constexpr int fused_min_waves(int kind) {
+  return kind == kKindWindowed ? OTFS_WIN_MIN_WAVES
+                               : ((kind == kKindDirect || kind == kKindDirectFD) ? OTFS_FUSED_MIN_WAVES
+                                                                                : OTFS_LDS_MIN_WAVES);
+}
+template <int SD, int KIND>
+__global__ __launch_bounds__(kBlock, fused_min_waves(KIND)) void k_cg_fused(const FrameDev* __restrict__ frames,
                                                      const WorkItem* __restrict__ items,
                                                      const int32_t* __restrict__ qitems,
                                                      const int2* __restrict__ qrange,
                                                      unsigned* __restrict__ qhead, int ngroups,
                                                      int budget, Bases B, LaunchCtx L) {
   __shared__ float red[kWaves];
-  __shared__ double redd[kWaves];
   __shared__ int sflag;
   __shared__ int s_item;
   extern __shared__ float2 stage_lds[];
@@ -1843,11 +2194,10 @@ __global__ __launch_bounds__(kBlock, KIND == kKindWindowed ? OTFS_WIN_MIN_WAVES
     if constexpr (KIND == kKindResident)
       cg_item_resident(F, budget, B, red, stage_lds);
     else if constexpr (KIND == kKindWindowed)
-      cg_item_win<REFRESH>(F, wi, budget, B, L, red, &sflag, stage_lds);
+      cg_item_win(F, wi, budget, B, L, red, &sflag, stage_lds);
     else
-      cg_item<SD, REFRESH, KIND == kKindStaged, KIND == kKindDirectFD>(F, wi, budget, B, L,
-                                                                          red, redd, &sflag,
-                                                    stage_lds);
+      cg_item<SD, KIND == kKindStaged, KIND == kKindDirectFD>(F, wi, budget, B, L, red, &sflag,
+                                                              stage_lds);
     __syncthreads();
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1855,6 +2205,79 @@ __global__ __launch_bounds__(kBlock, KIND == kKindWindowed ? OTFS_WIN_MIN_WAVES
 
 __global__ void k_xcc_probe(int* out) {
   if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
+}
+
+// ---------------------------------------------------------------------------------------
+// FP64 true-residual refresh of the frames whose state is marked `refresh` (they left the
+// fused launch after the C pass of every k-th iteration, with x already updated).  One
+// workgroup per tile; no cross-tile synchronisation inside a launch: the two launches are
+// ordered by the stream.
+//   k_refresh_u: u = y - H x, formed in FP64 from the FP32 x (FP64 tables, FP64 sums);
+//   k_refresh_c: c = H^H u - lam x, rounded to FP32, and the FP64 partial of ||c||^2.
+// k_refresh_u also clears the frame's barrier and neighbour counters for the next fused
+// launch of the same solve.
+// ---------------------------------------------------------------------------------------
+constexpr int kRefRows = 2;    // rows per thread chunk in the FP64 gathers
+constexpr int kRefPaths = 4;   // paths in flight together
+__global__ __launch_bounds__(kBlock) void k_refresh_u(const FrameDev* __restrict__ frames,
+                                                      const WorkItem* __restrict__ items, Bases B,
+                                                      unsigned* qhead, int nq) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const WorkItem wi = items[blockIdx.x];
+  const FrameDev& F = frames[wi.frame];
+  if (blockIdx.x == 0 && (int)threadIdx.x < nq) qhead[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) {
+    F.prog[wi.tile] = 0u;
+    if (wi.tile == 0) *F.bar = 0u;
+  }
+  if (F.st->refresh == 0 || F.st->status != OTFS_FRAME_RUNNING) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    return;
+  }
+  const FrameVecs V = frame_vecs(F, B);
+  const int64_t E = (int64_t)F.M * F.N;
+  const __amdgpu_buffer_rsrc_t u = buf_rsrc(F.u, E * 16);
+  band_apply<kRefRows, kRefPaths, false, kDNone>(
+      F, wi.l_begin, wi.l_end, SrcBuf{buf_rsrc(V.x, E * 8)},
+      [&](uint32_t q) { return load_y(V.y, q, V.ybf16); },
+      [&](int q, double2 v, float2 yv) {
+        const double2 r = make_double2((double)yv.x - v.x, (double)yv.y - v.y);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), u, (uint32_t)q * 16u,
+                                               0, 0);
+      },
+      ArithF64{});
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+__global__ __launch_bounds__(kBlock) void k_refresh_c(const FrameDev* __restrict__ frames,
+                                                      const WorkItem* __restrict__ items, Bases B) {
+  __shared__ double redd[kWaves];
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const WorkItem wi = items[blockIdx.x];
+  const FrameDev& F = frames[wi.frame];
+  if (F.st->refresh == 0 || F.st->status != OTFS_FRAME_RUNNING) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    return;
+  }
+  const FrameVecs V = frame_vecs(F, B);
+  const int64_t E = (int64_t)F.M * F.N;
+  const double lam = (double)F.lam;
+  const CVec cv = cvec(F.c, E), xv = cvec(V.x, E);
+  double acc = 0.0;
+  band_apply<kRefRows, kRefPaths, true, kDNone>(
+      F, wi.l_begin, wi.l_end, SrcC128{buf_rsrc(F.u, E * 16)},
+      [&](uint32_t q) { return xv.ld(q); },
+      [&](int q, double2 v, float2 x) {
+        const float2 cf = make_float2((float)(v.x - lam * (double)x.x),
+                                      (float)(v.y - lam * (double)x.y));
+        cv.st((uint32_t)q, cf);
+        acc = fma((double)cf.x, (double)cf.x, acc);
+        acc = fma((double)cf.y, (double)cf.y, acc);
+      },
+      ArithF64{});
+  const double bs = block_sum_d(acc, redd);
+  if (threadIdx.x == 0) F.part_d[wi.tile] = bs;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1898,6 +2321,7 @@ __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsign
     s.cn = s.cn0 = s.alpha = s.beta = s.rel = 0.f;
     s.init = 0;
     s.cn_hist[0] = s.cn_hist[1] = 0.f;
+    s.refresh = 0;
     *F.st = s;
   }
 }
@@ -1953,6 +2377,189 @@ __global__ __launch_bounds__(kBlock) void k_build_d(const FrameDev* __restrict__
             f32_to_bf16(c.x) | (f32_to_bf16(c.y) << 16);
     }
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// Bits of the hard decisions (Eq. demod demaps each decided symbol to its bits; the map is
+// a reflected Gray code per axis, g = i XOR (i >> 1), in-phase bits above quadrature bits)
+// and bit-error counts against the transmitted symbol indices.  One workgroup per work
+// item; every frame's count is the sum of its tiles' integer partials (exact, any order).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t gray_sym(uint32_t idx, uint32_t m, uint32_t b) {
+  const uint32_t iI = idx / m, iQ = idx - iI * m;
+  return ((iI ^ (iI >> 1)) << b) | (iQ ^ (iQ >> 1));
+}
+__device__ __forceinline__ uint32_t log2u(uint32_t m) { return 31u - __builtin_clz(m); }
+
+__device__ void tile_bit_errors(const FrameDev& F, const WorkItem& wi, const uint8_t* sym,
+                                const uint8_t* tx, unsigned long long* err, int* red) {
+  const uint32_t m = (uint32_t)F.qside, b = log2u(m);
+  const int M = F.M;
+  uint32_t cnt = 0;
+  auto one = [&](int64_t q) { cnt += __popc(gray_sym(sym[q], m, b) ^ gray_sym(tx[q], m, b)); };
+  const int cols = wi.k_end - wi.k_begin;
+  if (cols == M) {
+    for (int64_t q = (int64_t)wi.l_begin * M + threadIdx.x; q < (int64_t)wi.l_end * M; q += kBlock)
+      one(q);
+  } else {
+    const int tx0 = (int)threadIdx.x % cols, ty = (int)threadIdx.x / cols;
+    for (int l = wi.l_begin + ty; l < wi.l_end; l += kBlock / cols) one((int64_t)l * M + wi.k_begin + tx0);
+  }
+  for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (int)cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    for (int i = 0; i < kWaves; ++i) tot += (unsigned)red[i];
+    atomicAdd(err, tot);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bit_errors(const FrameDev* __restrict__ frames,
+                                                       const WorkItem* __restrict__ items,
+                                                       const uint8_t* sym, const uint8_t* tx,
+                                                       unsigned long long* errs) {
+  __shared__ int red[kWaves];
+  const WorkItem wi = items[blockIdx.x];
+  const FrameDev& F = frames[wi.frame];
+  if (F.qside <= 0) return;
+  tile_bit_errors(F, wi, sym + F.off, tx + F.off, errs + F.index, red);
+}
+
+// Bit errors of the estimates after the current iteration (CG trace): a frame still
+// running holds x with its last update x += alpha p' pending, so its decisions are taken on
+// x + alpha p'; a finished frame's x and decisions are final.  The decisions are written to
+// the caller's buffer (sym), then counted against tx into errs[F.index].
+__global__ __launch_bounds__(kBlock) void k_trace_errors(const FrameDev* __restrict__ frames,
+                                                         const WorkItem* __restrict__ items,
+                                                         Bases B, const uint8_t* tx,
+                                                         unsigned long long* errs) {
+  __shared__ int red[kWaves];
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const WorkItem wi = items[blockIdx.x];
+  const FrameDev& F = frames[wi.frame];
+  if (F.qside <= 0) return;
+  const FrameVecs V = frame_vecs(F, B);
+  const FrameState s = *F.st;
+  const bool pend = s.status == OTFS_FRAME_RUNNING && (s.pending & 1) != 0;
+  const float2* pcur = s.pbuf ? F.p1 : F.p0;
+  const int M = F.M;
+  for (int64_t q = (int64_t)wi.l_begin * M + threadIdx.x; q < (int64_t)wi.l_end * M; q += kBlock) {
+    float2 xv = V.x[q];
+    if (pend) xv = axpyf(s.alpha, pcur[q], xv);
+    V.sym[q] = decide(xv, F.qscale, F.qside);
+  }
+  __syncthreads();
+  tile_bit_errors(F, wi, V.sym, tx + F.off, errs + F.index, red);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------------------
+// Structured-sparse channel from a received pilot frame (Sec. IV-A "Hadamard product" and
+// Sec. IV-B "Dominant path determination"), one workgroup per frame.
+//
+// The pilot is one impulse at (K0, L0) = (M/2, N/2).  The estimate of the effective channel
+// on the received grid is h[k, l] = Y[k, l] E_twist[k, l] with
+// E_twist[k, l] = e^{-j 2 pi K0 (l - L0) / (MN)} (Eqs. heff_exp, heff_hadamard); bin (k, l)
+// stands for the path with shifts (tau, nu) = (k - K0, l - L0).  The dominant paths are the
+// bins with |h| > theta (Eq. heff_thres), tested as |h|^2 > theta^2 in FP32 on the
+// estimate rounded to FP32.  The workgroup walks the frame in vector order, kBlock bins at
+// a time, and compacts the selected bins in that order (wave ballots and a prefix over the
+// waves); the first F.pcap become the frame's paths: the table of shifts, P, the shift
+// ranges, and the delay-ramp tables R_p[k] = h_p e^{j 2 pi nu_p (k - tau_p) / (MN)} (FP32,
+// and FP64 where the frame keeps them for the refresh), each phase from its integer
+// numerator reduced modulo MN before one FP64 sine / cosine.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double2 unit_phasor(int64_t num, int64_t mn) {
+  num %= mn;
+  if (num < 0) num += mn;
+  double sn, cs;
+  sincospi(2.0 * ((double)num / (double)mn), &sn, &cs);
+  return make_double2(cs, sn);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pilot_paths(FrameDev* __restrict__ frames,
+                                                        const float2* __restrict__ ypilot,
+                                                        float theta, int32_t* npaths) {
+  __shared__ int wcount[kWaves];
+  __shared__ float2 s_gain[kMaxPathsDev];
+  __shared__ int2 s_tn[kMaxPathsDev];
+  FrameDev& F = frames[blockIdx.x];
+  const int M = F.M, N = F.N, K0 = M / 2, L0 = N / 2;
+  const int64_t E = (int64_t)M * N, MN = E;
+  const int cap = min(F.pcap, kMaxPathsDev);
+  const GPairs yp = gpairs(ypilot + F.off);
+  const float th2 = __fmul_rn(theta, theta);
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  int base = 0;
+  for (int64_t q0 = 0; q0 < E; q0 += kBlock) {
+    const int64_t q = q0 + threadIdx.x;
+    bool sel = false;
+    float2 h = make_float2(0.f, 0.f);
+    int k = 0, l = 0;
+    if (q < E) {
+      l = (int)(q / M);
+      k = (int)(q - (int64_t)l * M);
+      const double2 tw = unit_phasor(-(int64_t)K0 * (l - L0), MN);
+      const float2 y = yp.f(q);
+      h = make_float2((float)((double)y.x * tw.x - (double)y.y * tw.y),
+                      (float)((double)y.x * tw.y + (double)y.y * tw.x));
+      sel = __fadd_rn(__fmul_rn(h.x, h.x), __fmul_rn(h.y, h.y)) > th2;
+    }
+    const uint64_t m = __builtin_amdgcn_ballot_w64(sel);
+    const int before = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (lane == 0) wcount[wave] = __popcll(m);
+    __syncthreads();
+    int woff = 0, total = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      const int c = wcount[w];
+      woff += w < wave ? c : 0;
+      total += c;
+    }
+    const int idx = base + woff + before;
+    if (sel && idx < cap) {
+      s_tn[idx] = make_int2(k - K0, l - L0);
+      s_gain[idx] = h;
+    }
+    base += total;
+    __syncthreads();
+  }
+  const int P = base < cap ? base : cap;
+  int2* const paths = const_cast<int2*>(F.paths);
+  float2* const rtab = const_cast<float2*>(F.rtab);
+  double2* const rtab64 = const_cast<double2*>(F.rtab64);
+  if ((int)threadIdx.x < P) paths[threadIdx.x] = s_tn[threadIdx.x];
+  for (int i = threadIdx.x; i < P * M; i += kBlock) {
+    const int p = i / M, k = i - p * M;
+    const int2 tn = s_tn[p];
+    const double2 ph = unit_phasor((int64_t)tn.y * (k - tn.x), MN);
+    const double hr = (double)s_gain[p].x, hi = (double)s_gain[p].y;
+    const double2 r = make_double2(hr * ph.x - hi * ph.y, hr * ph.y + hi * ph.x);
+    rtab[i] = make_float2((float)r.x, (float)r.y);
+    if (rtab64) rtab64[i] = r;
+  }
+  if (threadIdx.x == 0) {
+    // shift ranges, widened to contain 0 as the host forms them
+    int tlo = 0, thi = 0, vlo = 0, vhi = 0;
+    for (int p = 0; p < P; ++p) {
+      tlo = min(tlo, s_tn[p].x);
+      thi = max(thi, s_tn[p].x);
+      vlo = min(vlo, s_tn[p].y);
+      vhi = max(vhi, s_tn[p].y);
+    }
+    F.P = P;
+    F.tau_lo = tlo;
+    F.tau_hi = thi;
+    F.nu_lo = vlo;
+    F.nu_hi = vhi;
+    if (npaths) npaths[blockIdx.x] = base;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2175,86 +2782,78 @@ static uint64_t wait_ticks(int64_t wait_us) {
   return (uint64_t)wait_us * wallclock_ticks_per_us();
 }
 
-template <int SD, bool REFRESH, int KIND>
+template <int SD, int KIND>
 static void launch_fused_t(const FrameDev* frames, const WorkItem* items, const int32_t* qitems,
                            const int2* qrange, unsigned* qhead, int ngroups, int grid, int budget,
                            const Bases& bases, const LaunchCtx& L, int lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_fused<SD, REFRESH, KIND>), dim3(grid), dim3(kBlock), lds_bytes, s,
-                     frames, items, qitems, qrange, qhead, ngroups, budget, bases, L);
+  hipLaunchKernelGGL((k_cg_fused<SD, KIND>), dim3(grid), dim3(kBlock), lds_bytes, s, frames, items,
+                     qitems, qrange, qhead, ngroups, budget, bases, L);
 }
 
-// the instantiation of a launch kind: resident and staged frames use neither the stored
-// D nor (resident) the refresh, which the host guarantees
-template <int SD>
-static const void* fused_fn_sd(bool refresh) {
-  return refresh ? reinterpret_cast<const void*>(&k_cg_fused<SD, true, kKindDirect>)
-                 : reinterpret_cast<const void*>(&k_cg_fused<SD, false, kKindDirect>);
-}
-static const void* fused_fn(int kind, int sd, bool refresh) {
-  if (kind == kKindResident) return reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindResident>);
-  if (kind == kKindWindowed)
-    return (sd != kDNone || refresh)
-               ? nullptr
-               : reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindWindowed>);
-  if (kind == kKindDirectFD)
-    return (sd != kDNone || refresh)
-               ? nullptr
-               : reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindDirectFD>);
-  if (kind == kKindStaged)
-    return refresh ? reinterpret_cast<const void*>(&k_cg_fused<kDNone, true, kKindStaged>)
-                   : reinterpret_cast<const void*>(&k_cg_fused<kDNone, false, kKindStaged>);
-  if (sd == kDBf16) return fused_fn_sd<kDBf16>(refresh);
-  if (sd == kDC64) return fused_fn_sd<kDC64>(refresh);
-  return fused_fn_sd<kDNone>(refresh);
+// the instantiation of a launch kind: only the direct kind reads a stored D (the host
+// guarantees it)
+static const void* fused_fn(int kind, int sd) {
+  switch (kind) {
+    case kKindResident: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindResident>);
+    case kKindWindowed: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindWindowed>);
+    case kKindDirectFD: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindDirectFD>);
+    case kKindStaged: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindStaged>);
+    default: break;
+  }
+  if (sd == kDBf16) return reinterpret_cast<const void*>(&k_cg_fused<kDBf16, kKindDirect>);
+  if (sd == kDC64) return reinterpret_cast<const void*>(&k_cg_fused<kDC64, kKindDirect>);
+  return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindDirect>);
 }
 
-template <int SD>
-static void launch_direct_sd(bool refresh, const FrameDev* frames, const WorkItem* items,
-                             const int32_t* qitems, const int2* qrange, unsigned* qhead,
-                             int ngroups, int grid, int budget, const Bases& bases,
-                             const LaunchCtx& L, hipStream_t s) {
-  if (refresh)
-    launch_fused_t<SD, true, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
-  else
-    launch_fused_t<SD, false, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
-}
-
-hipError_t launch_cg_fused(int kind, int sd, bool refresh, const FrameDev* frames,
-                           const WorkItem* items, const int32_t* qitems, const int2* qrange,
-                           unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
-                           bool xcd_local, unsigned* abort_flag, int lds_bytes, int64_t wait_us,
-                           hipStream_t s) {
+hipError_t launch_cg_fused(int kind, int sd, const FrameDev* frames, const WorkItem* items,
+                           const int32_t* qitems, const int2* qrange, unsigned* qhead, int ngroups,
+                           int grid, int budget, Bases bases, bool xcd_local, unsigned* abort_flag,
+                           int lds_bytes, int64_t wait_us, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  if (kind != kKindDirect && sd != kDNone) return hipErrorInvalidValue;
   LaunchCtx L{abort_flag, wait_ticks(wait_us), xcd_local ? 1 : 0};
-  if (kind == kKindResident) {
-    launch_fused_t<kDNone, false, kKindResident>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-  } else if (kind == kKindWindowed) {
-    if (sd != kDNone || refresh) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(fused_fn(kind, sd, refresh),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (kind == kKindWindowed || kind == kKindStaged) {
+    hipError_t e = hipFuncSetAttribute(fused_fn(kind, sd), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       lds_bytes);
     if (e != hipSuccess) return e;
-    launch_fused_t<kDNone, false, kKindWindowed>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-  } else if (kind == kKindDirectFD) {
-    if (sd != kDNone || refresh) return hipErrorInvalidValue;
-    launch_fused_t<kDNone, false, kKindDirectFD>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
-  } else if (kind == kKindStaged) {
-    if (refresh) launch_fused_t<kDNone, true, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-    else launch_fused_t<kDNone, false, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
-  } else if (sd == kDBf16) {
-    launch_direct_sd<kDBf16>(refresh, frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
-  } else if (sd == kDC64) {
-    launch_direct_sd<kDC64>(refresh, frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
-  } else {
-    launch_direct_sd<kDNone>(refresh, frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, s);
+  }
+  switch (kind) {
+    case kKindResident:
+      launch_fused_t<kDNone, kKindResident>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+      break;
+    case kKindWindowed:
+      launch_fused_t<kDNone, kKindWindowed>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+      break;
+    case kKindDirectFD:
+      launch_fused_t<kDNone, kKindDirectFD>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+      break;
+    case kKindStaged:
+      launch_fused_t<kDNone, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+      break;
+    default:
+      if (sd == kDBf16)
+        launch_fused_t<kDBf16, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+      else if (sd == kDC64)
+        launch_fused_t<kDC64, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
+      else
+        launch_fused_t<kDNone, kKindDirect>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, 0, s);
   }
   return hipGetLastError();
 }
 
-int fused_blocks_per_cu(int kind, int sd, bool refresh, int lds_bytes) {
+hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nitems, Bases bases,
+                          unsigned* qhead, int nq, hipStream_t s) {
+  if (nitems <= 0 || nq > kBlock) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_refresh_u, dim3(nitems), dim3(kBlock), 0, s, frames, items, bases, qhead,
+                     nq);
+  hipLaunchKernelGGL(k_refresh_c, dim3(nitems), dim3(kBlock), 0, s, frames, items, bases);
+  return hipGetLastError();
+}
+
+int fused_blocks_per_cu(int kind, int sd, int lds_bytes) {
   int n = 0;
   if (kind == kKindDirect || kind == kKindDirectFD) lds_bytes = 0;
-  const void* fn = fused_fn(kind, sd, refresh);
-  if (!fn) return 0;
+  const void* fn = fused_fn(kind, sd);
   if (lds_bytes > 0)
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kBlock, lds_bytes) != hipSuccess)
@@ -2280,6 +2879,39 @@ hipError_t launch_plain_frame(const FrameDev* frames_dev, int f, const WorkItem*
     hipLaunchKernelGGL(k_plain_dir, g, b, 0, s, frames_dev, f, it, xi);
   }
   hipLaunchKernelGGL(k_plain_finish, g, b, 0, s, frames_dev, f, it, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_bit_errors(const FrameDev* frames, const WorkItem* items, int nitems,
+                             const uint8_t* sym, const uint8_t* tx, unsigned long long* errs,
+                             int nframes, bool clear, hipStream_t s) {
+  if (clear && nframes > 0)
+    hipLaunchKernelGGL(k_fill_u64, dim3((nframes + 255) / 256), dim3(256), 0, s, errs,
+                       (int64_t)nframes);
+  if (nitems > 0)
+    hipLaunchKernelGGL(k_bit_errors, dim3(nitems), dim3(kBlock), 0, s, frames, items, sym, tx, errs);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_errors(const FrameDev* frames, const WorkItem* items, int nitems, Bases B,
+                               const uint8_t* tx, unsigned long long* errs, hipStream_t s) {
+  if (nitems > 0)
+    hipLaunchKernelGGL(k_trace_errors, dim3(nitems), dim3(kBlock), 0, s, frames, items, B, tx, errs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0,
+                       s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pilot_paths(FrameDev* frames, int nframes, const float2* ypilot, float theta,
+                              int32_t* npaths, hipStream_t s) {
+  if (nframes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pilot_paths, dim3(nframes), dim3(kBlock), 0, s, frames, ypilot, theta,
+                     npaths);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ constexpr int kWaves = kBlock / 64;  // wave64
 // Coefficients D_{p,q}: synthesised on the fly from the delay-ramp and wrap tables, or read
 // from a stored P x E table (the SS representation of Eq. ds_repr) in bf16 or complex64.
 constexpr int kDNone = 0, kDBf16 = 1, kDC64 = 2;
+constexpr int kMaxPathsDev = 64;   // largest P of a frame
 inline int stored_mode(uint32_t flags) {
   return (flags & OTFS_D_STORED_C64) ? kDC64 : ((flags & OTFS_D_STORED_BF16) ? kDBf16 : kDNone);
 }
@@ -37,6 +38,7 @@ struct FrameState {
   float rel;         // sqrt(cn / cn0)
   int32_t init;      // 1 once b = H^H y has been formed
   float cn_hist[2];  // plain form: ||c||^2 by iteration parity
+  int32_t refresh;   // 1: left the fused launch for the FP64 refresh (x already updated)
 };
 
 // Everything a kernel needs to know about one frame.  Built on the host, uploaded once
@@ -88,6 +90,9 @@ struct FrameDev {
   // all Doppler rows, and each gather pass streams the source rows through an LDS window
   // win_rc output rows at a time
   int32_t win_w, win_rc;
+  // path capacity: the P given at otfs_plan; a path table estimated on the device from a
+  // pilot frame (otfs_plan_paths_from_pilot) may set P to anything in [0, pcap]
+  int32_t pcap;
 };
 
 // One workgroup's share of one frame: Doppler rows [l_begin, l_end) of delay columns
@@ -162,14 +167,19 @@ constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKindDirectFD
 constexpr int kFusedDirMaxPaths = 8;
 // frames of at least this many elements stream t (see FrameDev::stream_t)
 constexpr int64_t kStreamTElems = 131072;
-hipError_t launch_cg_fused(int kind, int sd, bool refresh, const FrameDev* frames,
-                           const WorkItem* items, const int32_t* qitems, const int2* qrange,
-                           unsigned* qhead, int ngroups, int grid, int budget, Bases bases,
-                           bool xcd_local, unsigned* abort_flag, int lds_bytes, int64_t wait_us,
-                           hipStream_t s);
+hipError_t launch_cg_fused(int kind, int sd, const FrameDev* frames, const WorkItem* items,
+                           const int32_t* qitems, const int2* qrange, unsigned* qhead, int ngroups,
+                           int grid, int budget, Bases bases, bool xcd_local, unsigned* abort_flag,
+                           int lds_bytes, int64_t wait_us, hipStream_t s);
 // Workgroups of the fused kernel of a launch kind that fit on one CU at once (occupancy)
 // with lds_bytes of dynamic LDS.
-int fused_blocks_per_cu(int kind, int sd, bool refresh, int lds_bytes);
+int fused_blocks_per_cu(int kind, int sd, int lds_bytes);
+// FP64 true-residual refresh of the frames whose state is marked `refresh`, over all
+// nitems work items (one workgroup each): two launches, u = y - H x, then
+// c = H^H u - lam x with the FP64 partial norms in part_d.  Also clears every frame's
+// barrier and neighbour counters and the nq queue cursors for the next fused launch.
+hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nitems, Bases bases,
+                          unsigned* qhead, int nq, hipStream_t s);
 
 // out[b] = XCC id of workgroup b, for b < nblocks.
 hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
@@ -178,6 +188,26 @@ hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
 hipError_t launch_plain_frame(const FrameDev* frames_dev, int frame, const WorkItem* items_dev,
                               int item_begin, int ntiles, int max_iters, Bases bases,
                               hipStream_t s);
+
+// Paths of every frame from its received pilot frame (one workgroup per frame): the
+// estimate Y (Hadamard) E_twist of Eq. heff_hadamard, the bins with |h|^2 > theta^2 (FP32
+// test) in vector order, the first F.pcap of them made the frame's paths on the device
+// (path table, P, shift ranges, FP32 and, where present, FP64 delay-ramp tables).
+// ypilot: batch-wide complex64 pilot frames (frame at + off).  npaths[f] (nullable)
+// receives the number of bins above the threshold.
+hipError_t launch_pilot_paths(FrameDev* frames, int nframes, const float2* ypilot, float theta,
+                              int32_t* npaths, hipStream_t s);
+
+// Bit errors of the decisions sym against the transmitted indices tx (batch buffers), per
+// frame, added to errs[frame] (cleared first when clear); frames without QAM are skipped.
+hipError_t launch_bit_errors(const FrameDev* frames, const WorkItem* items, int nitems,
+                             const uint8_t* sym, const uint8_t* tx, unsigned long long* errs,
+                             int nframes, bool clear, hipStream_t s);
+// Decisions and bit errors of the current estimates (x with a running frame's pending
+// update applied) into B.sym and errs[frame].
+hipError_t launch_trace_errors(const FrameDev* frames, const WorkItem* items, int nitems, Bases B,
+                               const uint8_t* tx, unsigned long long* errs, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 
 // Build the stored D table of every frame (sd = kDBf16 or kDC64).
 hipError_t launch_build_d(int sd, const FrameDev* frames, const WorkItem* items, int nitems,

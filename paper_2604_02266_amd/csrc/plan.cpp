@@ -168,6 +168,7 @@ void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const 
   d->stream_t = (int64_t)fr.M * fr.N >= kStreamTElems ? 1 : 0;
   d->win_w = geo.win_w;
   d->win_rc = geo.win_rc;
+  d->pcap = fr.P;
 }
 
 int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opts& o,
@@ -213,7 +214,7 @@ otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vecto
   // The H pass forms the direction inside its gathers when the direct frames have few
   // paths: the gathers then read two vectors, which costs more than the separate
   // direction pass saves once P is large (measured on the 16-path batches).
-  bool fdir = sd == kDNone && !refresh && !split_dir;
+  bool fdir = sd == kDNone && !split_dir;
   for (size_t f = 0; f < frames.size(); ++f)
     if (frame_kind(geo[f]) == kKindDirect && frames[f].P > kFusedDirMaxPaths) fdir = false;
   auto kind_of = [&](size_t f) {
@@ -232,7 +233,7 @@ otfs_status plan_launches(const std::vector<HostFrame>& frames, const std::vecto
       lds = std::max(lds, frame_lds_bytes(frames[f], geo[f]));
     }
     if (fs.empty()) continue;
-    const int bpc = std::max(1, fused_blocks_per_cu(kind, sd, refresh, lds));
+    const int bpc = std::max(1, fused_blocks_per_cu(kind, sd, lds));
     int cap = bpc * cus;
     if (cap_override > 0) cap = std::min(cap, cap_override);
     KindLaunch L;
@@ -283,6 +284,13 @@ void wrap_factors(const HostFrame& f, std::vector<double2>& out) {
 // number of 64-byte lines), so that the frames running together on one XCD do not start on
 // the same memory-channel pattern; measured 2-3 % on the 64-frame batch.
 constexpr int kFramePad = OTFS_FRAME_PAD;
+static_assert(kFramePad % 2 == 0, "frame pad keeps pairs aligned");
+// Element offset of frame f (at batch offset off) inside the workspace vectors: the batch
+// offset plus f pads, rounded up to an even element.
+static size_t frame_vec_offset(int64_t off, size_t f) {
+  const size_t e = (size_t)off + f * (size_t)kFramePad;
+  return e + (e & 1);
+}
 #ifndef OTFS_WG_PER_CU
 #define OTFS_WG_PER_CU 2
 #endif
@@ -520,7 +528,8 @@ void compute_layout(otfs_plan_t* pl) {
   L.prog = take(nitems * sizeof(unsigned));
   L.st = take(nf * sizeof(FrameState));
   L.abort = take(sizeof(unsigned));
-  const size_t Ep = E + pl->frames.size() * (size_t)kFramePad;   // frames staggered
+  // frames staggered, each starting at an even element (16-byte aligned pairs)
+  const size_t Ep = E + pl->frames.size() * (size_t)(kFramePad + 1);
   L.c = take(Ep * sizeof(float2));
   L.p0 = take(Ep * sizeof(float2));
   L.p1 = take(Ep * sizeof(float2));
@@ -734,7 +743,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
     wrap_factors(fr, w64);
     for (int p = 0; p < fr.P; ++p) paths.push_back(make_int2(fr.tau[p], fr.nu[p]));
     const size_t E = (size_t)fr.M * fr.N;
-    const size_t eo = (size_t)fr.off + f * (size_t)kFramePad;
+    const size_t eo = frame_vec_offset(fr.off, f);
     d.c = reinterpret_cast<float2*>(base + L.c) + eo;
     d.p0 = reinterpret_cast<float2*>(base + L.p0) + eo;
     d.p1 = reinterpret_cast<float2*>(base + L.p1) + eo;
@@ -851,19 +860,34 @@ extern "C" otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y, voi
   return apply_common(plan, true, y, x, stream);
 }
 
-// the launch sequence of one fused solve: reset, persistent kernel (optionally timed)
+// Number of fused launches of one solve: with the FP64 refresh every k iterations, frames
+// leave the fused launch after iterations k, 2k, ... below the cap for the refresh
+// launches, so the solve is floor((max_iters - 1) / k) + 1 fused segments.
+static int fused_segments(const otfs_cg_opts& o) {
+  return o.refresh_every > 0 ? (o.max_iters - 1) / o.refresh_every + 1 : 1;
+}
+
+// the launch sequence of one fused solve: reset, then per segment the persistent kernel of
+// every launch kind followed by the refresh launches (optionally timed as a whole)
 static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s, bool timed) {
   hipError_t e = launch_reset(plan->d_frames, (int)plan->frames.size(), plan->d_abort,
                               plan->d_qhead, kKinds * kMaxGroups, s);
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_begin, s)) != hipSuccess) return e;
-  for (const KindLaunch& L : plan->launches) {
-    e = launch_cg_fused(L.kind, stored_mode(plan->opts.flags),
-                        plan->opts.refresh_every > 0, plan->d_frames, plan->d_items,
-                        plan->d_qitems, plan->d_qrange + L.qbase, plan->d_qhead + L.qbase,
-                        L.ngroups, L.grid, plan->opts.max_iters, B, L.xcd_local, plan->d_abort,
-                        L.lds_bytes, plan->wait_us, s);
-    if (e != hipSuccess) return e;
+  const int nseg = fused_segments(plan->opts);
+  for (int seg = 0; seg < nseg; ++seg) {
+    for (const KindLaunch& L : plan->launches) {
+      e = launch_cg_fused(L.kind, stored_mode(plan->opts.flags), plan->d_frames, plan->d_items,
+                          plan->d_qitems, plan->d_qrange + L.qbase, plan->d_qhead + L.qbase,
+                          L.ngroups, L.grid, plan->opts.max_iters, B, L.xcd_local,
+                          plan->d_abort, L.lds_bytes, plan->wait_us, s);
+      if (e != hipSuccess) return e;
+    }
+    if (seg + 1 < nseg) {
+      e = launch_refresh(plan->d_frames, plan->d_items, (int)plan->items.size(), B,
+                         plan->d_qhead, kKinds * kMaxGroups, s);
+      if (e != hipSuccess) return e;
+    }
   }
   if (timed && (e = hipEventRecord(plan->ev_end, s)) != hipSuccess) return e;
   return hipSuccess;
@@ -935,6 +959,80 @@ extern "C" otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y, voi
                            plan->tiles[f], plan->opts.max_iters, B, s);
     if (e != hipSuccess) return hip_fail(e, "plain CG launch");
   }
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_bit_errors(const otfs_plan_t* plan, const uint8_t* sym,
+                                       const uint8_t* sym_tx, uint64_t* errs, void* stream) {
+  otfs_status st = check_bound(plan);
+  if (st != OTFS_OK) return st;
+  if (plan->frames.empty()) return OTFS_OK;
+  if (!sym || !sym_tx || !errs) return fail(OTFS_E_INVAL, "sym, sym_tx and errs must be non-null");
+  hipError_t e = launch_bit_errors(plan->d_frames, plan->d_items, (int)plan->items.size(), sym,
+                                   sym_tx, reinterpret_cast<unsigned long long*>(errs),
+                                   (int)plan->frames.size(), true, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "bit errors");
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_lmmse_cg_trace(otfs_plan_t* plan, const void* y, void* xhat,
+                                           uint8_t* sym, otfs_frame_stats* stats,
+                                           const uint8_t* sym_tx, uint64_t* errs, void* stream) {
+  otfs_status st = check_bound(plan);
+  if (st != OTFS_OK) return st;
+  if (plan->frames.empty()) return OTFS_OK;
+  if (!y || !xhat || !sym || !sym_tx || !errs)
+    return fail(OTFS_E_INVAL, "y, xhat, sym, sym_tx and errs must be non-null");
+  if (y == xhat) return fail(OTFS_E_INVAL, "y and xhat must be distinct buffers");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Bases B{y, static_cast<float2*>(xhat), sym, stats};
+  const int nf = (int)plan->frames.size(), ni = (int)plan->items.size();
+  auto* ue = reinterpret_cast<unsigned long long*>(errs);
+  hipError_t e = launch_reset(plan->d_frames, nf, plan->d_abort, plan->d_qhead, kKinds * kMaxGroups, s);
+  if (e == hipSuccess) e = launch_fill_u64(ue, (int64_t)plan->opts.max_iters * nf, s);
+  for (int it = 0; it < plan->opts.max_iters && e == hipSuccess; ++it) {
+    if (it > 0) {   // counters and cursors of the next one-iteration launch
+      e = plan->opts.refresh_every > 0
+              ? launch_refresh(plan->d_frames, plan->d_items, ni, B, plan->d_qhead,
+                               kKinds * kMaxGroups, s)
+              : launch_step_reset(plan->d_frames, nf, plan->d_abort, plan->d_qhead,
+                                  kKinds * kMaxGroups, s);
+    }
+    for (const KindLaunch& L : plan->launches) {
+      if (e != hipSuccess) break;
+      e = launch_cg_fused(L.kind, stored_mode(plan->opts.flags), plan->d_frames, plan->d_items,
+                          plan->d_qitems, plan->d_qrange + L.qbase, plan->d_qhead + L.qbase,
+                          L.ngroups, L.grid, 1, B, L.xcd_local, plan->d_abort, L.lds_bytes,
+                          plan->wait_us, s);
+    }
+    if (e == hipSuccess)
+      e = launch_trace_errors(plan->d_frames, plan->d_items, ni, B, sym_tx, ue + (size_t)it * nf, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "CG trace");
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_plan_paths_from_pilot(otfs_plan_t* plan, const void* ypilot,
+                                                  float theta, int32_t* npaths, void* stream) {
+  otfs_status st = check_bound(plan);
+  if (st != OTFS_OK) return st;
+  if (plan->frames.empty()) return OTFS_OK;
+  if (!ypilot) return fail(OTFS_E_INVAL, "ypilot must be non-null");
+  if (!(theta >= 0.f) || !std::isfinite(theta))
+    return fail(OTFS_E_INVAL, "theta must be finite and >= 0");
+  for (const FrameDev& d : plan->h_frames)
+    if (d.skc > 0 || d.win_w > 0)
+      return fail(OTFS_E_UNSUPPORTED,
+                  "frames with LDS-staged or windowed gathers keep the windows planned on the "
+                  "host from their given paths");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_pilot_paths(plan->d_frames, (int)plan->frames.size(),
+                                    static_cast<const float2*>(ypilot), theta, npaths, s);
+  if (e != hipSuccess) return hip_fail(e, "pilot path estimation");
+  const int sd = stored_mode(plan->opts.flags);
+  if (sd != kDNone &&
+      (e = launch_build_d(sd, plan->d_frames, plan->d_items, (int)plan->items.size(), s)) != hipSuccess)
+    return hip_fail(e, "build D");
   return OTFS_OK;
 }
 

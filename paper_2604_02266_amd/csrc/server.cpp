@@ -34,6 +34,9 @@ using Clock = std::chrono::steady_clock;
 #define OTFS_SERVE_TILE 8192
 #endif
 constexpr int kServeTileElems = OTFS_SERVE_TILE;   // frame-local tiling rule (independent of the mix)
+}  // namespace
+int serve_tile_elems() { return kServeTileElems; }
+namespace {
 constexpr int kMaxActive = 2048;        // frames admitted at once
 constexpr int kMaxItems = 65536;        // tiles of the admitted frames
 constexpr size_t kAlign = 256;
@@ -252,6 +255,10 @@ struct Request {
 
 using namespace otfs;
 
+namespace otfs {
+int serve_tile_elems();
+}
+
 struct otfs_server {
   int device = -1;
   bool dry = false;
@@ -282,6 +289,13 @@ struct otfs_server {
   int active_tiles = 0;
   // counters
   uint64_t submitted = 0, completed = 0, steps = 0, peak = 0;
+  // per-shape tile sizes (otfs_server_set_tiling); other shapes use serve_tile_elems()
+  std::map<std::pair<int, int>, int> tile_of_shape;
+  int tile_elems(const otfs::HostFrame& f) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = tile_of_shape.find({f.M, f.N});
+    return it == tile_of_shape.end() ? otfs::serve_tile_elems() : it->second;
+  }
 };
 
 namespace otfs {
@@ -430,13 +444,17 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   Bases B{nullptr, nullptr, nullptr, nullptr};
   for (const KindLaunch& L : launches) {
     if (e != hipSuccess) break;
-    e = launch_cg_fused(L.kind, kDNone, S->opts.refresh_every > 0, dframes,
-                        reinterpret_cast<const WorkItem*>(P + C.items),
+    e = launch_cg_fused(L.kind, kDNone, dframes, reinterpret_cast<const WorkItem*>(P + C.items),
                         reinterpret_cast<const int32_t*>(P + C.qitems),
                         reinterpret_cast<const int2*>(P + C.qrange) + L.qbase, qhead + L.qbase,
                         L.ngroups, L.grid, S->step_iters, B, L.xcd_local, abort_flag,
                         L.lds_bytes, -1, S->s);
   }
+  // frames that reached a refresh point in this step get their FP64 true residual before
+  // the next step resumes them
+  if (e == hipSuccess && S->opts.refresh_every > 0)
+    e = launch_refresh(dframes, reinterpret_cast<const WorkItem*>(P + C.items), (int)items.size(),
+                       B, qhead, kKinds * kMaxGroups, S->s);
   out.resize(n);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out.data(), dstats, n * sizeof(otfs_frame_stats), hipMemcpyDeviceToHost, S->s);
@@ -494,7 +512,7 @@ bool scheduler_init(otfs_server* S) {
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess && v > 0)
     S->cus = v;
   // the tile cap of a frame: workgroups of the direct kind resident at once
-  S->cap = std::max(1, fused_blocks_per_cu(kKindDirect, kDNone, S->opts.refresh_every > 0, 0)) * S->cus;
+  S->cap = std::max(1, fused_blocks_per_cu(kKindDirect, kDNone, 0)) * S->cus;
   return true;
 }
 
@@ -655,7 +673,7 @@ extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* fram
   const size_t E = (size_t)frame->M * frame->N;
   std::vector<WorkItem> items;
   std::vector<int> tb, tl;
-  make_tiles(std::vector<HostFrame>{r->hf}, kServeTileElems, items, tb, tl);
+  make_tiles(std::vector<HostFrame>{r->hf}, S->tile_elems(r->hf), items, tb, tl);
   r->tiles = tl[0];
   r->items = items;
   int band = 1;
@@ -685,6 +703,19 @@ extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* fram
   return OTFS_OK;
 }
 
+extern "C" otfs_status otfs_server_set_tiling(otfs_server_t* S, int32_t M, int32_t N,
+                                              int32_t tile_elems) {
+  if (!S) return fail(OTFS_E_INVAL, "server is null");
+  if (M < 1 || N < 1 || tile_elems < 0)
+    return fail(OTFS_E_INVAL, "need M, N >= 1 and tile_elems >= 0");
+  std::lock_guard<std::mutex> g(S->mu);
+  if (tile_elems == 0)
+    S->tile_of_shape.erase({M, N});
+  else
+    S->tile_of_shape[{M, N}] = tile_elems;
+  return OTFS_OK;
+}
+
 extern "C" otfs_status otfs_server_frame_bytes(otfs_server_t* S, const otfs_frame_desc* frame,
                                                size_t* frame_bytes, size_t* control_bytes) {
   if (!S || !frame) return fail(OTFS_E_INVAL, "null argument");
@@ -693,7 +724,7 @@ extern "C" otfs_status otfs_server_frame_bytes(otfs_server_t* S, const otfs_fram
   if (st != OTFS_OK) return st;
   std::vector<WorkItem> items;
   std::vector<int> tb, tl;
-  make_tiles(std::vector<HostFrame>{hf}, kServeTileElems, items, tb, tl);
+  make_tiles(std::vector<HostFrame>{hf}, S->tile_elems(hf), items, tb, tl);
   if (frame_bytes) *frame_bytes = slot_layout(hf, tl[0], S->opts.refresh_every > 0).total;
   if (control_bytes) *control_bytes = S->slot_base;
   return OTFS_OK;

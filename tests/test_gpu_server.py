@@ -52,7 +52,7 @@ def test_server_matches_oracle_and_plan(otfs):
         ops.append(op)
         ys.append(np.asarray(y, np.complex64))
     say("server vs oracle", [(f.spec.M, f.spec.N, f.spec.P) for f in frames])
-    with otfs.Server(256 << 20, max_iters=MAX_ITERS, rel_tol=TOL, step_iters=7) as srv:
+    with otfs.Server(256 << 20, max_iters=MAX_ITERS, rel_tol=TOL, step_iters=7, tune=False) as srv:
         res = _serve(srv, frames, ys)
         ss = srv.stats()
     assert ss.completed == len(frames) and ss.pool_bytes_in_use == 0
@@ -127,3 +127,31 @@ def test_server_under_pool_pressure(otfs):
         ref = _serve(srv, frames, ys)
     for a, b in zip(res, ref):
         assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+
+
+def test_server_refresh_matches_plan(otfs):
+    # With the FP64 true-residual refresh every 5 iterations and steps of 7, frames reach
+    # their refresh points in the middle of a step; they wait for the refresh launches at
+    # the end of the step and resume in the next one.  Each result equals, bit for bit, the
+    # same frame solved by a plan with the server's tiling and the same refresh period.
+    import torch
+    frames = _frames(16, 5)
+    ys = [np.asarray(O.received_frame(fr)[2], np.complex64) for fr in frames]
+    say("server with refresh every 5", [(f.spec.M, f.spec.N, f.spec.P) for f in frames])
+    with otfs.Server(256 << 20, max_iters=MAX_ITERS, rel_tol=TOL, refresh_every=5, tune=False,
+                     step_iters=7) as srv:
+        res = _serve(srv, frames, ys)
+    for i, fr in enumerate(frames):
+        sp = fr.spec
+        xr, _, _ = O.cg_lmmse(ys[i].astype(np.complex128), O.received_frame(fr)[0], sp.lam,
+                              MAX_ITERS, TOL)
+        assert O.nmse(res[i][0], xr) <= NMSE_TOL, i
+        plan = otfs.Plan([sp], max_iters=MAX_ITERS, rel_tol=TOL, refresh_every=5,
+                         tile_elems=SERVE_TILE_ELEMS)
+        sym = torch.zeros(sp.E, dtype=torch.uint8, device="cuda")
+        stats = plan.new_stats()
+        xp = plan.lmmse_cg(to_dev(ys[i]), sym=sym, stats=stats)
+        torch.cuda.synchronize()
+        assert np.array_equal(xp.cpu().numpy().view(np.uint32), res[i][0].view(np.uint32)), i
+        assert np.array_equal(sym.cpu().numpy(), res[i][1]), i
+        assert int(otfs.stats_numpy(stats)["iters"][0]) == res[i][2].iters

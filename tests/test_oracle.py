@@ -133,6 +133,35 @@ def test_pilot_impulse_response_recovers_paths(M, N):
             assert abs(val) <= 1e-14
 
 
+@pytest.mark.parametrize("M,N", [(16, 8), (32, 16)])
+def test_threshold_selects_the_true_paths(M, N):
+    # Eq. heff_thres on a noiseless pilot: with every |h_p| above theta and the paths inside
+    # the estimate's support, the selected set is the channel's own path set, in vector
+    # order, with the channel's gains; it also agrees with thresholding the direct form of
+    # Eq. heff, and a larger theta selects a subset.
+    rng = np.random.default_rng(M + 7 * N)
+    fr = W.small_frame(rng, M, N, 6, (-(M // 2) + 1, M // 2 - 1), (-(N // 2) + 1, N // 2 - 1))
+    sp = fr.spec
+    h = sp.h / np.abs(sp.h) * (0.2 + rng.uniform(0, 1, sp.P))      # every |h_p| >= 0.2
+    op = O.TwistedConvChannel(M, N, h, sp.tau, sp.nu)
+    yp = op.apply(O.pilot_frame(M, N))
+    tau, nu, g = O.threshold_paths(O.pilot_estimate_hadamard(yp, M, N), 0.08)
+    order = np.argsort((np.asarray(sp.nu) + N // 2) * M + (np.asarray(sp.tau) + M // 2))
+    assert np.array_equal(tau, np.asarray(sp.tau)[order])
+    assert np.array_equal(nu, np.asarray(sp.nu)[order])
+    assert np.abs(g - h[order]).max() <= 1e-14
+    direct = O.pilot_estimate_direct(yp, M, N)
+    sel = sorted(((v + N // 2) * M + (t + M // 2)) for (t, v), val in direct.items()
+                 if abs(val) > 0.08)
+    assert sel == sorted(((nu + N // 2) * M + (tau + M // 2)).tolist())
+    t2, _, _ = O.threshold_paths(O.pilot_estimate_hadamard(yp, M, N), 0.5)
+    assert set(t2.tolist()) <= set(tau.tolist())
+    # noise well below theta selects nothing else
+    w = 0.01 * (rng.standard_normal(M * N) + 1j * rng.standard_normal(M * N)) / math.sqrt(2)
+    tau_n, nu_n, _ = O.threshold_paths(O.pilot_estimate_hadamard(yp + w, M, N), 0.08)
+    assert np.array_equal(tau_n, tau) and np.array_equal(nu_n, nu)
+
+
 def test_cg_single_path_closed_form():
     # P=1: H^H H = |h|^2 I, so one CG step lands on H^H y / (|h|^2 + lam)
     M, N = 16, 8
@@ -212,6 +241,50 @@ def test_qam_ties_go_to_upper_level_and_margin():
     assert O.qam_decide(np.array([0.0 + 0.0j]), Q)[0] == 2 * m + 2
     assert O.qam_decide(np.array([-1e-9 - 1e-9j]), Q)[0] == 1 * m + 1
     assert abs(O.decision_margin(np.array([0.05 + 1j / s]), Q)[0] - 0.05) <= 1e-12
+
+
+@pytest.mark.parametrize("Q", [4, 16, 64, 256])
+def test_gray_bits_neighbours_differ_in_one_bit(Q):
+    # the defining property of a Gray map, checked over the whole constellation by brute
+    # force: the nearest neighbours of every point (one level apart on one axis) differ in
+    # exactly one bit; the map is a bijection onto all bit patterns; and the per-axis code
+    # equals the reflected construction G(n) = [0 G(n-1), 1 reverse(G(n-1))]
+    m = O.qam_side(Q)
+    bits = O.gray_bits(np.arange(Q), Q)
+    assert len({tuple(r) for r in bits}) == Q
+    pts = O.qam_points(np.arange(Q), Q)
+    step = 2.0 / O.qam_scale(Q)
+    for a in range(Q):
+        for b in range(Q):
+            if abs(abs(pts[a] - pts[b]) - step) < 1e-9:
+                assert np.count_nonzero(bits[a] != bits[b]) == 1
+    codes = [[]]
+    for _ in range(int(round(math.log2(m)))):
+        codes = [[0] + c for c in codes] + [[1] + c for c in reversed(codes)]
+    for i in range(m):
+        assert list(O.gray_bits([i * m], Q)[0][:len(codes[0])]) == codes[i]
+    assert O.bit_errors([0, 1], [0, 1], Q) == 0
+
+
+def test_ber_convergence_rule():
+    # Eq. ber_convergence on hand-made curves: a negligible fall, a rise, a flat zero curve
+    # (zeta guards the division), and a curve that keeps falling fast
+    assert O.ber_convergence([0.1, 0.05, 0.0499, 0.04]) == 3
+    assert O.ber_convergence([0.1, 0.02, 0.03]) == 3
+    assert O.ber_convergence([0.0, 0.0, 0.0]) == 2
+    assert O.ber_convergence([0.5, 0.25, 0.125, 0.0625]) == 4
+    assert O.ber_convergence([0.2, 0.1999]) == 2
+
+
+def test_cg_trace_matches_fixed_count_solves():
+    # the per-iteration estimates are those of the (pinned) CG stopped after k steps
+    rng = np.random.default_rng(77)
+    fr = W.small_frame(rng, 16, 8, 3, (0, 4), (-2, 2), qam=16, snr_db=20.0)
+    op, _, y = O.received_frame(fr)
+    tr = O.cg_lmmse_trace(y, op, fr.spec.lam, 6)
+    for k in (1, 2, 6):
+        xk, it, _ = O.cg_lmmse(y, op, fr.spec.lam, k, 0.0)
+        assert it == k and np.abs(tr[k - 1] - xk).max() <= 1e-12
 
 
 def test_workload_generator_is_seeded_and_in_range():
