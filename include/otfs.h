@@ -271,6 +271,19 @@ otfs_status otfs_lmmse_cg_trace(otfs_plan_t* plan, const void* y_dev, void* xhat
 otfs_status otfs_plan_paths_from_pilot(otfs_plan_t* plan, const void* ypilot_dev, float theta,
                                        int32_t* npaths_dev, void* stream);
 
+/* The fused form for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation).  Binds the plan to the
+ * library's static scratch on the current device (a workspace of at most 64 MiB, one copy
+ * per GPU, held until the process ends), then runs otfs_lmmse_cg: same kernels, same
+ * results.  Calls no hipMalloc / hipFree.  The caller still passes y, x_hat, the
+ * decisions and the stats.  A plan whose otfs_plan_workspace_bytes() exceeds 64 MiB
+ * returns OTFS_E_NOMEM; OTFS_USE_GRAPH or OTFS_TIME_KERNEL return OTFS_E_UNSUPPORTED.
+ * Every call rebinds the plan (table uploads on `stream`, then a synchronisation of it).
+ * All calls on one GPU share the scratch: calls that overlap in time on one GPU race, and
+ * the plan stays bound to the scratch afterwards. */
+otfs_status otfs_lmmse_cg_noalloc(otfs_plan_t* plan, const void* y_dev, void* xhat_dev,
+                                  uint8_t* sym_dev, otfs_frame_stats* stats_dev, void* stream);
+
 /* Bound of the fused kernel's in-kernel waits (per-frame barriers and neighbour waits), in
  * microseconds: a wait that is not satisfied within it gives up, raises the launch-wide
  * abort word (every other wait of the launch then gives up too), and the frames concerned

@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
         "otfs_apply_HH": (st, [_vp, _vp, _vp, _vp]),
         "otfs_lmmse_cg": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "otfs_lmmse_cg_plain": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "otfs_lmmse_cg_noalloc": (st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "otfs_plan_kernel_ms": (st, [_vp, ctypes.POINTER(ctypes.c_float)]),
         "otfs_plan_set_wait_limit": (st, [_vp, ctypes.c_int64]),
         "otfs_plan_paths_from_pilot": (st, [_vp, _vp, ctypes.c_float, _vp, _vp]),
@@ -329,6 +330,10 @@ class Plan:
 
     def lmmse_cg_plain(self, y, xhat=None, sym=None, stats=None, stream=None):
         return self._solve(self._lib.otfs_lmmse_cg_plain, y, xhat, sym, stats, stream)
+
+    def lmmse_cg_noalloc(self, y, xhat=None, sym=None, stats=None, stream=None):
+        """otfs_lmmse_cg_noalloc: the plan is rebound to the library's static scratch."""
+        return self._solve(self._lib.otfs_lmmse_cg_noalloc, y, xhat, sym, stats, stream)
 
     def paths_from_pilot(self, ypilot, theta: float = 0.08, npaths=None, stream=None):
         """otfs_plan_paths_from_pilot: the frames' paths from their received pilot frames

@@ -2719,6 +2719,30 @@ __global__ __launch_bounds__(kBlock) void k_plain_finish(const FrameDev* __restr
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
+// Static scratch of otfs_lmmse_cg_noalloc (callers that cannot allocate device memory):
+// a plan workspace of at most kNoAllocBytes, one copy per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel or a copy: it uses the
+// device address that hipGetSymbolAddress returns, taken once per device with that device
+// current.
+// ---------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> guard(mu);
+  if (addr[device] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
 hipError_t launch_apply(bool adjoint, int sd, const FrameDev* frames, const WorkItem* items,

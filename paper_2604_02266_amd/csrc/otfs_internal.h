@@ -181,6 +181,13 @@ int fused_blocks_per_cu(int kind, int sd, int lds_bytes);
 hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nitems, Bases bases,
                           unsigned* qhead, int nq, hipStream_t s);
 
+// Static scratch of the entry point that allocates nothing: kNoAllocBytes per device.
+// *ptr = its device address on `device`, which must be the current device (found once per
+// device with hipGetSymbolAddress, then cached).
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // out[b] = XCC id of workgroup b, for b < nblocks.
 hipError_t launch_xcc_probe(int* out, int nblocks, hipStream_t s);
 

@@ -1036,6 +1036,29 @@ extern "C" otfs_status otfs_plan_paths_from_pilot(otfs_plan_t* plan, const void*
   return OTFS_OK;
 }
 
+extern "C" otfs_status otfs_lmmse_cg_noalloc(otfs_plan_t* plan, const void* y, void* xhat,
+                                             uint8_t* sym, otfs_frame_stats* stats, void* stream) {
+  if (!plan) return fail(OTFS_E_INVAL, "plan is null");
+  if (plan->opts.flags & (OTFS_USE_GRAPH | OTFS_TIME_KERNEL))
+    return fail(OTFS_E_UNSUPPORTED,
+                "otfs_lmmse_cg_noalloc runs without OTFS_USE_GRAPH and OTFS_TIME_KERNEL");
+  if (plan->L.total > kNoAllocBytes)
+    return fail(OTFS_E_NOMEM,
+                "the plan needs a workspace of %zu bytes; the static scratch holds %zu bytes",
+                plan->L.total, kNoAllocBytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  void* ws = nullptr;
+  if ((e = noalloc_scratch(dev, &ws)) != hipSuccess)
+    return hip_fail(e, "hipGetSymbolAddress (scratch)");
+  // every call rebinds: the scratch is shared by all calls on this device and holds the
+  // tables of whichever plan used it last
+  otfs_status st = otfs_plan_bind(plan, ws, kNoAllocBytes, stream);
+  if (st != OTFS_OK) return st;
+  return otfs_lmmse_cg(plan, y, xhat, sym, stats, stream);
+}
+
 extern "C" otfs_status otfs_plan_set_wait_limit(otfs_plan_t* plan, int64_t wait_us) {
   if (!plan) return fail(OTFS_E_INVAL, "plan is null");
   plan->wait_us = wait_us < 0 ? -1 : wait_us;
