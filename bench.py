@@ -254,7 +254,8 @@ def solve_block(otfs, O, np, torch, name, frames, ys, refs, steps, warmup, refre
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": load_traffic(name, refresh),
-                     "kernel": "k_cg_fused", "kernel_ms": kavg,
+                     "kernel": "k_cg_fused" + (" + k_refresh_u + k_refresh_c" if refresh else ""),
+                     "kernel_ms": kavg,
                      "algorithmic_bytes_per_launch": lb,
                      "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
     }
@@ -291,6 +292,35 @@ def plain_block(otfs, O, np, torch, frames, ys, refs, refresh, offs, reps=3):
             "runs": reps, "tile_elems": tile,
             "nmse_worst": None if parity is None else parity["nmse_worst"],
             "note": "no FP64 refresh in the plain form" if refresh else ""}
+
+
+PEAK_MFMA_FP32_TFLOPS = 157.3
+
+
+def dzt_block(otfs, np, torch, M, N, nframes, reps=10):
+    """The front end's DZT (Eq. zak as the batched GEMM of Eq. zak_gemm on FP32 MFMA) of a
+    batch of time-domain frames: 8 M N^2 real flops per frame, timed with HIP events."""
+    x = torch.randn(nframes * M * N, dtype=torch.complex64, device="cuda")
+    out = torch.empty_like(x)
+    otfs.dzt(x, M, N, out=out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        otfs.dzt(x, M, N, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    flops = 8.0 * M * N * N * nframes
+    del x, out
+    return {"workload": f"{nframes} x ({M},{N}) time-domain frames", "ms": ms,
+            "frames_per_s": nframes / (ms * 1e-3),
+            "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12,
+                         "peak": PEAK_MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flops / (ms * 1e-3) / 1e12 / PEAK_MFMA_FP32_TFLOPS,
+                         "kernel": "k_dzt (v_mfma_f32_16x16x4_f32)"}}
 
 
 def plan_elems(specs):
@@ -491,6 +521,8 @@ def main():
         sec = results[1]
         out["secondary"] = {k: sec[k] for k in ("value", "ms_per_step", "config", "iterations",
                                                  "parity_vs_oracle", "roofline")}
+    sp0 = frames[0].spec
+    out["front_end_dzt"] = dzt_block(otfs, np, torch, sp0.M, sp0.N, len(frames))
     if serve_frames is not None:
         rates = [float(r) for r in args.sweep_rates.split(",") if r]
         out["serving"] = serving_sweep(otfs, np, torch, serve_frames, serve_ys, rates,

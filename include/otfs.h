@@ -93,9 +93,9 @@ enum {
                                     too (default: in LDS when 5*M*N*8 bytes fit 40 KiB)      */
   OTFS_SPLIT_DIRECTION = 1u << 6, /* always form the direction p = c + beta p in a pass of its
                                     own before the H pass.  By default, when every frame
-                                    gathered straight from memory has P <= 8 (and neither the
-                                    stored-D mode nor the refresh is on), the H pass forms it
-                                    inside its gathers instead; the results are identical  */
+                                    gathered straight from memory has P <= 8 (and no stored
+                                    D), the H pass forms it inside its gathers instead; the
+                                    results are identical                                   */
   OTFS_D_STORED_C64 = 1u << 7    /* store D_{p,q} (Eq. D_definition) in complex64 in the
                                     workspace: the SS table of Eq. ds_repr as the paper keeps
                                     it (Sec. IV-B, "Efficient Data Structure"), P x total_elems
@@ -212,9 +212,13 @@ otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y_dev, void* x_de
 /* ------------------------------------------------------------------------------------ */
 /* LMMSE by conjugate gradient (Algorithm 1), all frames of the bound batch.              */
 /* ------------------------------------------------------------------------------------ */
-/* Fused form: one persistent launch runs every frame's whole iteration loop; frames are
- * split into row tiles, the workgroups of one frame meet at per-frame barriers, and each
- * frame stops on its own.  y_dev: total_elems complex64 (bf16 pairs with OTFS_Y_BF16);
+/* Fused form: one persistent launch (per kind of frame) runs every frame's iteration loop;
+ * frames are split into row tiles, the workgroups of one frame meet at per-frame barriers,
+ * and each frame stops on its own.  With refresh_every = k the loop is cut after every k-th
+ * iteration into segments, and two launches between segments form the FP64 true residual
+ * c = H^H (y - H x) - lam x.  The fused launches expect the GPU to themselves: a frame's
+ * tiles must all be resident at once, and work from other streams that keeps some of them
+ * waiting makes the frame report OTFS_FRAME_TIMEOUT after the wait bound.  y_dev: total_elems complex64 (bf16 pairs with OTFS_Y_BF16);
  * xhat_dev: total_elems complex64 output; sym_dev: total_elems uint8 hard decisions
  * i_I * sqrt(Q) + i_Q (Eq. demod; nullable; frames with qam = 0 are left untouched);
  * stats_dev: nframes otfs_frame_stats (nullable). */
@@ -227,6 +231,22 @@ otfs_status otfs_lmmse_cg(otfs_plan_t* plan, const void* y_dev, void* xhat_dev, 
  * against. */
 otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y_dev, void* xhat_dev,
                                 uint8_t* sym_dev, otfs_frame_stats* stats_dev, void* stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* Discrete Zak transform (the receiver's front end)                                      */
+/* ------------------------------------------------------------------------------------ */
+/* DZT of nframes received time-domain frames (Sec. III-A, Eq. zak):
+ *     Y[k, l] = N^{-1/2} sum_{i=0}^{N-1} y[k + i M] e^{-j 2 pi i l / N},
+ * computed as the batched complex GEMM of Sec. IV-A (Eq. zak_gemm): per frame the N x M
+ * matrix of samples (row i = slot, column k = delay) is multiplied by the N x N kernel
+ * e^{-j 2 pi l i / N} / sqrt(N) on the matrix cores (FP32 MFMA, FP32 accumulation).  The
+ * kernel is the unitary one of Eq. zak; the printed kernel matrix of Eq. zak_exp differs
+ * from it by the factor sqrt(N) (-1)^l.  inverse != 0 computes Eq. iZak instead.
+ * in_dev: nframes * M * N complex64, frame after frame, sample i*M + k; out_dev: the same
+ * size, DD frames in vector order q = l*M + k (for the inverse the roles swap).  Distinct
+ * buffers; 1 <= N <= 8192. */
+otfs_status otfs_dzt(int32_t M, int32_t N, int32_t nframes, const void* in_dev, void* out_dev,
+                     int32_t inverse, void* stream);
 
 /* ------------------------------------------------------------------------------------ */
 /* Bits and bit errors (Eq. demod: decided symbols demapped to bits)                      */
@@ -292,8 +312,9 @@ otfs_status otfs_lmmse_cg_noalloc(otfs_plan_t* plan, const void* y_dev, void* xh
  * Takes effect at the next otfs_lmmse_cg call. */
 otfs_status otfs_plan_set_wait_limit(otfs_plan_t* plan, int64_t wait_us);
 
-/* Duration in milliseconds of the fused CG kernel of the last otfs_lmmse_cg call that ran
- * with OTFS_TIME_KERNEL (waits for its end event). */
+/* Duration in milliseconds of the launch sequence of the last otfs_lmmse_cg call that ran
+ * with OTFS_TIME_KERNEL (its fused launches and, with the refresh, the refresh launches
+ * between them; waits for its end event). */
 otfs_status otfs_plan_kernel_ms(otfs_plan_t* plan, float* ms);
 
 /* ------------------------------------------------------------------------------------ */

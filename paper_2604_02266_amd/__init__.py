@@ -118,6 +118,8 @@ def lib() -> ctypes.CDLL:
         "otfs_plan_set_wait_limit": (st, [_vp, ctypes.c_int64]),
         "otfs_plan_paths_from_pilot": (st, [_vp, _vp, ctypes.c_float, _vp, _vp]),
         "otfs_bit_errors": (st, [_vp, _vp, _vp, _vp, _vp]),
+        "otfs_dzt": (st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                          ctypes.c_int32, _vp]),
         "otfs_lmmse_cg_trace": (st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "otfs_server_create": (st, [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(CgOpts),
                                     ctypes.c_int32, ctypes.POINTER(_vp)]),
@@ -485,6 +487,18 @@ class Server:
         out = ServerStats()
         _check(self._lib.otfs_server_stats(self._h, ctypes.byref(out)))
         return out
+
+
+def dzt(x, M: int, N: int, inverse: bool = False, out=None, stream=None):
+    """otfs_dzt: DZT (Eq. zak) or its inverse (Eq. iZak) of a contiguous complex64 tensor
+    holding nframes frames of M*N samples; returns the output tensor."""
+    torch = _torch()
+    if x.dtype != torch.complex64 or not x.is_cuda or not x.is_contiguous() or x.numel() % (M * N):
+        raise ValueError("x: need a contiguous cuda complex64 tensor of nframes * M * N values")
+    out = torch.empty_like(x) if out is None else out
+    _check(lib().otfs_dzt(int(M), int(N), x.numel() // (M * N), _vp(_ptr(x)), _vp(_ptr(out)),
+                          int(bool(inverse)), _vp(_stream_ptr(stream))))
+    return out
 
 
 def stats_numpy(stats) -> np.ndarray:

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libotfs.so")
-SOURCES = ["kernels.hip", "plan.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "dzt.hip", "plan.cpp", "server.cpp"]
 ARCH = os.environ.get("OTFS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -704,6 +704,22 @@ __device__ bool halo_wait(const unsigned* prog, int T, TileRange tr, unsigned ta
 #ifndef OTFS_PATHS
 #define OTFS_PATHS 4
 #endif
+#ifndef OTFS_STRIP_LANES
+#define OTFS_STRIP_LANES 64
+#endif
+// Lanes across one row in the gather passes (a multiple of 64): a band is walked in
+// strips of that many delay columns (twice as many in the paired form), every row of the
+// band per strip, so the source rows a strip reaches stay in cache while its paths reuse
+// them.
+constexpr int kStripLanes = OTFS_STRIP_LANES;
+// Lanes across a row for a band of band_rows rows walked R rows per thread chunk: the
+// strip width, widened (doubling, up to a whole workgroup) while the band is too short to
+// give every thread R rows; at most `width` (the lanes a whole row needs).  Wave-uniform.
+__device__ __forceinline__ int strip_lanes(int width, int band_rows, int R) {
+  int t = kStripLanes;
+  while (t < kBlock && t * band_rows < kBlock * R) t <<= 1;
+  return width < t ? width : t;
+}
 constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
 constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
 #ifndef OTFS_PATHS_GENERAL
@@ -749,7 +765,7 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
   using C = typename A::C;
   constexpr bool STORED = SD != kDNone;
   const int M = F.M, N = F.N, P = F.P;
-  const int TX = M < kBlock ? M : kBlock;
+  const int TX = strip_lanes(M, le - lb, R);
   const int TY = kBlock / TX;
   const int tx = threadIdx.x % TX;
   // UNI: TX is a multiple of 64, so every wave lies in one row group ty and the row
@@ -872,7 +888,7 @@ __device__ __forceinline__ void band_apply_rows(const FrameDev& F, int lb, int l
 template <int R, int U, bool ADJ, int SD, class Src, class Pref, class Sink, class A = ArithF32>
 __device__ __forceinline__ void band_apply(const FrameDev& F, int lb, int le, const Src& src,
                                            Pref pref, Sink sink, A = A{}) {
-  const int TX = F.M < kBlock ? F.M : kBlock;
+  const int TX = strip_lanes(F.M, le - lb, R);
   // the per-lane row arithmetic of the general form holds more registers: fewer paths
   // in flight there
   if ((TX & 63) == 0)
@@ -913,7 +929,7 @@ __device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int 
                                                  Pref pref, Sink sink) {
   const int M = F.M, N = F.N, P = F.P;
   const int M2 = M >> 1;
-  const int TX = M2 < kBlock ? M2 : kBlock;   // a multiple of 64: every wave in one row
+  const int TX = strip_lanes(M2, le - lb, R);   // a multiple of 64: waves in one row
   const int TY = kBlock / TX;
   const int tx = threadIdx.x % TX;
   const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TX);
@@ -2217,9 +2233,18 @@ __global__ void k_xcc_probe(int* out) {
 // k_refresh_u also clears the frame's barrier and neighbour counters for the next fused
 // launch of the same solve.
 // ---------------------------------------------------------------------------------------
-constexpr int kRefRows = 2;    // rows per thread chunk in the FP64 gathers
+#ifndef OTFS_REF_ROWS
+#define OTFS_REF_ROWS 8
+#endif
+#ifndef OTFS_REF_MIN_WAVES
+#define OTFS_REF_MIN_WAVES 2
+#endif
+// rows per thread chunk in the FP64 gathers: each path's FP64 coefficient (16 bytes per
+// column) is read once per chunk, so tall chunks keep the table reads small next to the
+// gathered data; one workgroup per CU leaves the registers for them
+constexpr int kRefRows = OTFS_REF_ROWS;
 constexpr int kRefPaths = 4;   // paths in flight together
-__global__ __launch_bounds__(kBlock) void k_refresh_u(const FrameDev* __restrict__ frames,
+__global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_u(const FrameDev* __restrict__ frames,
                                                       const WorkItem* __restrict__ items, Bases B,
                                                       unsigned* qhead, int nq) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -2249,7 +2274,7 @@ __global__ __launch_bounds__(kBlock) void k_refresh_u(const FrameDev* __restrict
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
 
-__global__ __launch_bounds__(kBlock) void k_refresh_c(const FrameDev* __restrict__ frames,
+__global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_c(const FrameDev* __restrict__ frames,
                                                       const WorkItem* __restrict__ items, Bases B) {
   __shared__ double redd[kWaves];
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");

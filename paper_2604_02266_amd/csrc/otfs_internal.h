@@ -216,6 +216,12 @@ hipError_t launch_trace_errors(const FrameDev* frames, const WorkItem* items, in
                                const uint8_t* tx, unsigned long long* errs, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 
+// Discrete Zak transform (inverse = false, Eq. zak) or its inverse (Eq. iZak) of nframes
+// frames of M x N complex64 samples (dzt.hip): batched GEMM on MFMA.  in and out distinct.
+hipError_t launch_dzt(int M, int N, int nframes, bool inverse, const float2* in, float2* out,
+                      hipStream_t s);
+constexpr int kDztMaxN = 8192;   // twiddle table of N complex64 values in LDS (64 KiB)
+
 // Build the stored D table of every frame (sd = kDBf16 or kDC64).
 hipError_t launch_build_d(int sd, const FrameDev* frames, const WorkItem* items, int nitems,
                           hipStream_t s);

@@ -962,6 +962,23 @@ extern "C" otfs_status otfs_lmmse_cg_plain(otfs_plan_t* plan, const void* y, voi
   return OTFS_OK;
 }
 
+extern "C" otfs_status otfs_dzt(int32_t M, int32_t N, int32_t nframes, const void* in, void* out,
+                                int32_t inverse, void* stream) {
+  if (M < 1 || N < 1 || nframes < 0)
+    return fail(OTFS_E_INVAL, "need M, N >= 1 and nframes >= 0 (got %d, %d, %d)", M, N, nframes);
+  if ((int64_t)M * N > (int64_t(1) << 28))
+    return fail(OTFS_E_INVAL, "M*N = %lld exceeds 2^28", (long long)M * N);
+  if (N > kDztMaxN)
+    return fail(OTFS_E_UNSUPPORTED, "N = %d exceeds %d (twiddle table in LDS)", N, kDztMaxN);
+  if (nframes == 0) return OTFS_OK;
+  if (!in || !out) return fail(OTFS_E_INVAL, "in and out must be non-null");
+  if (in == out) return fail(OTFS_E_INVAL, "in and out must be distinct buffers");
+  hipError_t e = launch_dzt(M, N, nframes, inverse != 0, static_cast<const float2*>(in),
+                            static_cast<float2*>(out), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "DZT");
+  return OTFS_OK;
+}
+
 extern "C" otfs_status otfs_bit_errors(const otfs_plan_t* plan, const uint8_t* sym,
                                        const uint8_t* sym_tx, uint64_t* errs, void* stream) {
   otfs_status st = check_bound(plan);

@@ -106,3 +106,16 @@ def test_tiling_changes_workspace():
     assert p.info().tile_elems == 65536
     with pytest.raises(otfs.OtfsError):
         p.set_tiling(-1, 0, rebind=False)
+
+
+def test_ber_profile_rule_matches_the_oracle():
+    # the profiler's convergence rule (product code) against the oracle's statement of
+    # Eq. ber_convergence, on random and hand-made BER curves
+    import oracle as O
+    from paper_2604_02266_amd import ber_profile
+    rng = np.random.default_rng(3)
+    curves = [[0.1, 0.05, 0.0499, 0.04], [0.1, 0.02, 0.03], [0.0, 0.0, 0.0], [0.5, 0.25, 0.125]]
+    curves += [list(np.sort(rng.uniform(0, 0.2, 12))[::-1] * rng.uniform(0.9, 1.1, 12))
+               for _ in range(50)]
+    for c in curves:
+        assert ber_profile.convergence_iteration(c) == O.ber_convergence(c)
