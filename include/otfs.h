@@ -304,6 +304,15 @@ otfs_status otfs_plan_paths_from_pilot(otfs_plan_t* plan, const void* ypilot_dev
 otfs_status otfs_lmmse_cg_noalloc(otfs_plan_t* plan, const void* y_dev, void* xhat_dev,
                                   uint8_t* sym_dev, otfs_frame_stats* stats_dev, void* stream);
 
+/* Read back the paths a frame currently has on the device (after otfs_plan_bind or
+ * otfs_plan_paths_from_pilot): *P receives the path count; the first min(P, capacity)
+ * paths' delay, Doppler and gain h_p (2 floats, re/im, read from the FP32 delay-ramp table
+ * the kernels use: exact for delays >= 0, within FP32 rounding otherwise) are written to
+ * the host arrays, in the order the kernels sum them.  Synchronises `stream`. */
+otfs_status otfs_plan_get_paths(const otfs_plan_t* plan, int32_t frame, int32_t capacity,
+                                int32_t* P, int32_t* delay, int32_t* doppler, float* h,
+                                void* stream);
+
 /* Bound of the fused kernel's in-kernel waits (per-frame barriers and neighbour waits), in
  * microseconds: a wait that is not satisfied within it gives up, raises the launch-wide
  * abort word (every other wait of the launch then gives up too), and the frames concerned

@@ -49,6 +49,7 @@ __all__ = [
     "qam_decide_bruteforce", "decision_margin", "pilot_estimate_direct",
     "pilot_estimate_hadamard", "pilot_frame", "threshold_paths", "received_frame", "nmse",
     "gray_bits", "bit_errors", "cg_lmmse_trace", "ber_convergence",
+    "fractional_td_channel", "veh_a_received",
 ]
 
 
@@ -277,6 +278,41 @@ def dense_H_timedomain(M, N, h, tau, nu) -> np.ndarray:
             Htd[i, (i - tau[p]) % E] += h[p] * np.exp(2j * np.pi * nu[p] * (i - tau[p]) / E)
     Z = dzt_matrix(M, N)
     return Z @ Htd @ Z.conj().T
+
+
+def fractional_td_channel(x_td, M, N, h, delay_samples, doppler_bins) -> np.ndarray:
+    """Time-domain channel with fractional delays and Dopplers (Eq. y_discrete_td without
+    its noise term, with the Doppler in the phase ramp as in dense_H_timedomain):
+        y[i] = sum_p h_p e^{j 2 pi nu_p (i - tau_p) / (M N)} x(i - tau_p),
+    nu_p in Doppler bins and tau_p in samples, both real.  x(t) is the band-limited
+    continuation of the frame, periodic over its M N samples (a delay by tau multiplies
+    DFT bin f of the frame by e^{-j 2 pi f tau / (M N)}, f taken in the symmetric range
+    [-MN/2, MN/2)); for integer tau this is the circular shift of dense_H_timedomain."""
+    x = np.asarray(x_td, dtype=np.complex128).reshape(-1)
+    E = M * N
+    X = np.fft.fft(x)
+    f = np.fft.fftfreq(E) * E                  # symmetric bin indices
+    i = np.arange(E)
+    y = np.zeros(E, dtype=np.complex128)
+    for hp, tau, nu in zip(np.asarray(h), np.asarray(delay_samples, dtype=np.float64),
+                           np.asarray(doppler_bins, dtype=np.float64)):
+        shifted = np.fft.ifft(X * np.exp(-2j * np.pi * f * tau / E))
+        y += hp * np.exp(2j * np.pi * nu * (i - tau) / E) * shifted
+    return y
+
+
+def veh_a_received(packet):
+    """(received pilot frame, received data frames) in the time domain for a packet of the
+    fractional workload: the pilot impulse at (M/2, N/2) and the QAM data frames, each
+    taken to the time domain by Eq. iZak, through fractional_td_channel, plus the packet's
+    time-domain noise; rounded once to complex64 (what a receiver gets)."""
+    M, N = packet.M, packet.N
+    chan = lambda xdd: fractional_td_channel(idzt(xdd, M, N), M, N, packet.h,
+                                             packet.delay_samples, packet.doppler_bins)
+    yp = (chan(pilot_frame(M, N)) + packet.noise_pilot).astype(np.complex64)
+    ys = np.stack([(chan(qam_points(packet.sym[d], packet.qam)) + packet.noise[d])
+                   for d in range(packet.sym.shape[0])]).astype(np.complex64)
+    return yp, ys
 
 
 # ----------------------------------------------------------------------------------------

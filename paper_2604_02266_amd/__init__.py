@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
         "otfs_plan_kernel_ms": (st, [_vp, ctypes.POINTER(ctypes.c_float)]),
         "otfs_plan_set_wait_limit": (st, [_vp, ctypes.c_int64]),
         "otfs_plan_paths_from_pilot": (st, [_vp, _vp, ctypes.c_float, _vp, _vp]),
+        "otfs_plan_get_paths": (st, [_vp, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32), _vp, _vp, _vp, _vp]),
         "otfs_bit_errors": (st, [_vp, _vp, _vp, _vp, _vp]),
         "otfs_dzt": (st, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                           ctypes.c_int32, _vp]),
@@ -375,6 +377,20 @@ class Plan:
                                              _vp(_ptr(sym_tx)), _vp(_ptr(errs)),
                                              _vp(_stream_ptr(stream))))
         return xhat, sym, errs
+
+    def get_paths(self, frame: int, stream=None):
+        """otfs_plan_get_paths: (delay, doppler, h) of a frame's paths on the device."""
+        cap = max(int(getattr(self.frames[frame], "P", 0) or
+                      np.asarray(self.frames[frame].tau).shape[0]), 64)
+        P = ctypes.c_int32()
+        tau = np.zeros(cap, dtype=np.int32)
+        nu = np.zeros(cap, dtype=np.int32)
+        h = np.zeros(2 * cap, dtype=np.float32)
+        _check(self._lib.otfs_plan_get_paths(self._h, int(frame), cap, ctypes.byref(P),
+                                             _vp(tau.ctypes.data), _vp(nu.ctypes.data),
+                                             _vp(h.ctypes.data), _vp(_stream_ptr(stream))))
+        n = min(int(P.value), cap)
+        return tau[:n].copy(), nu[:n].copy(), (h[0:2 * n:2] + 1j * h[1:2 * n:2]).astype(np.complex64)
 
     def set_wait_limit(self, wait_us: int):
         _check(self._lib.otfs_plan_set_wait_limit(self._h, int(wait_us)))

@@ -164,7 +164,10 @@ hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abor
 // windowed: frames tiled into strips whose gathers stream source rows through an LDS ring
 constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKindDirectFD = 3,
               kKindWindowed = 4, kKinds = 5;
-constexpr int kFusedDirMaxPaths = 8;
+#ifndef OTFS_FUSED_DIR_MAX_PATHS
+#define OTFS_FUSED_DIR_MAX_PATHS 8
+#endif
+constexpr int kFusedDirMaxPaths = OTFS_FUSED_DIR_MAX_PATHS;
 // frames of at least this many elements stream t (see FrameDev::stream_t)
 constexpr int64_t kStreamTElems = 131072;
 hipError_t launch_cg_fused(int kind, int sd, const FrameDev* frames, const WorkItem* items,

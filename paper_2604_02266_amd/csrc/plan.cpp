@@ -1029,6 +1029,50 @@ extern "C" otfs_status otfs_lmmse_cg_trace(otfs_plan_t* plan, const void* y, voi
   return OTFS_OK;
 }
 
+extern "C" otfs_status otfs_plan_get_paths(const otfs_plan_t* plan, int32_t frame,
+                                           int32_t capacity, int32_t* P, int32_t* delay,
+                                           int32_t* doppler, float* h, void* stream) {
+  otfs_status st = check_bound(plan);
+  if (st != OTFS_OK) return st;
+  if (frame < 0 || frame >= (int32_t)plan->frames.size())
+    return fail(OTFS_E_INVAL, "frame %d out of range [0, %zu)", frame, plan->frames.size());
+  if (!P || (capacity > 0 && (!delay || !doppler || !h)) || capacity < 0)
+    return fail(OTFS_E_INVAL, "P must be non-null; delay, doppler, h non-null when capacity > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FrameDev d;
+  hipError_t e = hipMemcpyAsync(&d, plan->d_frames + frame, sizeof d, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "path table readback");
+  *P = d.P;
+  const int n = std::min(d.P, capacity);
+  if (n > 0) {
+    std::vector<int2> tn(n);
+    std::vector<float2> r(n);   // R_p[tau_p mod M] = h_p (the ramp's phase vanishes at k = tau_p)
+    e = hipMemcpyAsync(tn.data(), d.paths, n * sizeof(int2), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (int p = 0; p < n && e == hipSuccess; ++p) {
+      const int k = ((tn[p].x % d.M) + d.M) % d.M;
+      e = hipMemcpyAsync(&r[p], d.rtab + (size_t)p * d.M + k, sizeof(float2), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "path table readback");
+    const int64_t MN = (int64_t)d.M * d.N;
+    for (int p = 0; p < n; ++p) {
+      delay[p] = tn[p].x;
+      doppler[p] = tn[p].y;
+      // R_p[k] = h_p e^{j 2 pi nu (k - tau) / MN}; k - tau is 0 (tau >= 0) or M (tau < 0)
+      const int k = ((tn[p].x % d.M) + d.M) % d.M;
+      int64_t num = ((int64_t)tn[p].y * (k - tn[p].x)) % MN;
+      if (num < 0) num += MN;
+      const double ang = -2.0 * M_PI * ((double)num / (double)MN);
+      const double c = std::cos(ang), sn = std::sin(ang);
+      h[2 * p] = (float)(r[p].x * c - r[p].y * sn);
+      h[2 * p + 1] = (float)(r[p].x * sn + r[p].y * c);
+    }
+  }
+  return OTFS_OK;
+}
+
 extern "C" otfs_status otfs_plan_paths_from_pilot(otfs_plan_t* plan, const void* ypilot,
                                                   float theta, int32_t* npaths, void* stream) {
   otfs_status st = check_bound(plan);

@@ -346,3 +346,40 @@ def test_pins_catch_planted_mistakes(mutation):
         assert err <= 1e-13
     else:
         assert err > 1e-3
+
+
+def test_fractional_channel_reduces_to_the_operator_and_shifts_exactly():
+    # integer delays and Dopplers: the time-domain simulation, taken to the DD domain by the
+    # DZT, is the (pinned) DD operator; a fractional delay moves a band-limited tone by the
+    # closed-form phase; delays compose and the shift is norm-preserving
+    M, N = 8, 4
+    rng = np.random.default_rng(91)
+    h = _rand_c(3, rng)
+    tau, nu = [0, 3, 6], [1, -2, 0]
+    x = _rand_c(M * N, rng)
+    y_td = O.fractional_td_channel(O.idzt(x, M, N), M, N, h, tau, nu)
+    ref = O.TwistedConvChannel(M, N, h, tau, nu).apply(x)
+    assert np.abs(O.dzt(y_td, M, N) - ref).max() <= 1e-12
+    E = M * N
+    i = np.arange(E)
+    for f0 in (1, 5, -7):
+        tone = np.exp(2j * np.pi * f0 * i / E)
+        out = O.fractional_td_channel(tone, M, N, [1.0], [0.37], [0.0])
+        assert np.abs(out - tone * np.exp(-2j * np.pi * f0 * 0.37 / E)).max() <= 1e-12
+    a = O.fractional_td_channel(O.fractional_td_channel(x, M, N, [1.0], [0.3], [0.0]), M, N,
+                                [1.0], [1.45], [0.0])
+    b = O.fractional_td_channel(x, M, N, [1.0], [1.75], [0.0])
+    assert np.abs(a - b).max() <= 1e-12
+    assert abs(np.linalg.norm(b) - np.linalg.norm(x)) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_veh_a_draws_follow_the_profile():
+    pk = W.veh_a_packet(np.random.default_rng(5), 128, 32, ndata=2, qam=16, snr_db=20.0)
+    # delays of Table vehAProf in samples at B = M * 30 kHz; Dopplers within nu_max / (df / N)
+    assert np.allclose(pk.delay_samples, np.array(W.VEH_A_DELAYS_US) * 1e-6 * 128 * 30e3)
+    assert np.all(np.abs(pk.doppler_bins) <= 100.0 / (30e3 / 32) + 1e-12)
+    assert pk.sym.shape == (2, 128 * 32) and pk.noise.shape == (2, 128 * 32)
+    # noise relative to each frame's own mean power: lam per data sample, lam / (MN) for the
+    # impulse pilot
+    assert abs(np.mean(np.abs(pk.noise) ** 2) / pk.lam - 1.0) < 0.05
+    assert abs(np.mean(np.abs(pk.noise_pilot) ** 2) * 128 * 32 / pk.lam - 1.0) < 0.1

@@ -27,7 +27,7 @@ from typing import Iterator, List, Optional
 import numpy as np
 
 __all__ = ["FrameSpec", "Frame", "CONFIGS", "make_frame_specs", "draw_frame", "iter_frames",
-           "small_frame"]
+           "small_frame", "VEH_A_DELAYS_US", "VEH_A_POWERS_DB", "VehAPacket", "veh_a_packet"]
 
 
 @dataclasses.dataclass
@@ -186,3 +186,60 @@ def small_frame(rng: np.random.Generator, M: int, N: int, P: int, tau_range, nu_
     spec = FrameSpec(M=M, N=N, tau=tau, nu=nu, h=h, qam=qam, snr_db=snr_db, lam=lam,
                      max_iters=max_iters, tol=tol)
     return _draw_bulk(rng, spec)
+
+
+# ----------------------------------------------------------------------------------------
+# Fractional delay-Doppler packets (the paper's channel model, Sec. V, Table vehAProf): the
+# ITU Vehicular-A power-delay profile, Doppler nu_p = nu_max cos(2 pi U_p), U_p ~ U(0, 1).
+# Delays and Dopplers are fractional on the DD grid.  Only the random draws live here; the
+# time-domain channel is applied by the consumer.
+# ----------------------------------------------------------------------------------------
+VEH_A_DELAYS_US = (0.00, 0.31, 0.71, 1.09, 1.73, 2.51)
+VEH_A_POWERS_DB = (0.0, -1.0, -9.0, -10.0, -15.0, -20.0)
+
+
+@dataclasses.dataclass
+class VehAPacket:
+    """One packet: a pilot frame and `ndata` data frames through one Veh-A channel.
+
+    delay_samples[p] = tau_p * B with B = M * df (fractional samples); doppler_bins[p] =
+    nu_p / (df / N) (fractional Doppler bins); gains h_p ~ CN(0, power_p) with the profile's
+    powers normalised to sum 1.  Noise samples are time-domain, with sigma^2 = rho_s / gamma
+    taken per frame from that frame's mean signal power rho_s (Sec. V): lam for a data
+    frame (unit-energy symbols), lam / (M N) for the pilot frame (one unit impulse)."""
+    M: int
+    N: int
+    df_hz: float
+    nu_max_hz: float
+    delay_samples: np.ndarray
+    doppler_bins: np.ndarray
+    h: np.ndarray
+    qam: int
+    snr_db: float
+    lam: float
+    sym: np.ndarray          # int64[ndata, M*N] symbol indices, vector order q = l*M + k
+    noise_pilot: np.ndarray  # complex128[M*N] time-domain noise of the pilot frame
+    noise: np.ndarray        # complex128[ndata, M*N] time-domain noise of the data frames
+
+
+def veh_a_packet(rng: np.random.Generator, M: int, N: int, ndata: int = 1, df_hz: float = 30e3,
+                 nu_max_hz: float = 100.0, qam: int = 4, snr_db: float = 20.0) -> VehAPacket:
+    """Draws in this order: path Dopplers U_p, gains, symbols, pilot noise, data noise."""
+    B = M * df_hz
+    dnu = df_hz / N
+    delays = np.asarray(VEH_A_DELAYS_US) * 1e-6 * B
+    power = 10.0 ** (np.asarray(VEH_A_POWERS_DB) / 10.0)
+    power /= power.sum()
+    P = delays.size
+    u = rng.uniform(0.0, 1.0, P)
+    dopp = nu_max_hz * np.cos(2.0 * np.pi * u) / dnu
+    g = rng.standard_normal(P) + 1j * rng.standard_normal(P)
+    h = np.sqrt(power / 2.0) * g
+    E = M * N
+    sym = rng.integers(0, qam, size=(ndata, E))
+    lam = 10.0 ** (-snr_db / 10.0)
+    wp = np.sqrt(lam / (2.0 * E)) * (rng.standard_normal(E) + 1j * rng.standard_normal(E))
+    w = np.sqrt(lam / 2.0) * (rng.standard_normal((ndata, E)) + 1j * rng.standard_normal((ndata, E)))
+    return VehAPacket(M=M, N=N, df_hz=df_hz, nu_max_hz=nu_max_hz, delay_samples=delays,
+                      doppler_bins=dopp, h=h.astype(np.complex128), qam=qam, snr_db=snr_db,
+                      lam=lam, sym=sym, noise_pilot=wp, noise=w)
