@@ -362,6 +362,22 @@ otfs_status otfs_submit(otfs_server_t* srv, const otfs_frame_desc* frame, const 
 otfs_status otfs_poll(otfs_server_t* srv, uint64_t ticket, void* xhat_host, uint8_t* sym_host,
                       otfs_frame_stats* stats, uint64_t* latency_ns);
 
+/* Batched forms for front ends that hand over bursts of frames (one lock and one call for
+ * many frames; the per-frame rules are those of otfs_submit and otfs_poll).
+ * otfs_submit_many queues frames[0..n) with y_host[i] the received frame of frames[i], in
+ * order, and writes their tickets; if any frame is rejected nothing is queued and the
+ * status is that frame's.  otfs_poll_many looks up tickets[0..n): status[i] is OTFS_OK (the
+ * results of ticket i were copied to xhat_host[i], sym_host[i], stats[i], latency_ns[i] and
+ * the ticket is forgotten), OTFS_E_AGAIN (still running), OTFS_E_NOTFOUND or OTFS_E_DEVICE;
+ * ndone counts the OTFS_OK entries.  xhat_host, sym_host, stats, latency_ns and their
+ * entries are nullable like otfs_poll's arguments; status is required. */
+otfs_status otfs_submit_many(otfs_server_t* srv, const otfs_frame_desc* frames, int32_t n,
+                             const void* const* y_host, uint64_t* tickets);
+otfs_status otfs_poll_many(otfs_server_t* srv, const uint64_t* tickets, int32_t n,
+                           void* const* xhat_host, uint8_t* const* sym_host,
+                           otfs_frame_stats* stats, uint64_t* latency_ns, int32_t* status,
+                           int32_t* ndone);
+
 /* Pool bytes one frame of this shape holds while admitted (frame_bytes, nullable) and the
  * size of the server's fixed control region at the start of the pool (control_bytes,
  * nullable): a pool of control_bytes + n * frame_bytes admits n such frames at once. */
@@ -372,11 +388,15 @@ typedef struct {
   uint64_t submitted, completed, steps;
   uint64_t queued, active;          /* frames waiting for admission / holding pool memory */
   uint64_t pool_bytes_in_use, pool_bytes_peak;
+  /* scheduler time, cumulative ns: enqueueing admission copies; steps from descriptor
+   * building to their synchronisation (ns_gpu of it between the first and last launch on
+   * the device); result copies and retirement */
+  uint64_t ns_admit, ns_step, ns_gpu, ns_fetch;
 } otfs_server_stats_t;
 otfs_status otfs_server_stats(otfs_server_t* srv, otfs_server_stats_t* out);
 
 /* Tile size (elements per workgroup band) for frames of shape M x N submitted from now
- * on; 0 restores the built-in rule (8192).  A frame's tiling depends only on its own
+ * on; 0 restores the built-in rule (32768).  A frame's tiling depends only on its own
  * shape, so its result is the same alone and among other frames.  Used to apply the
  * autotuner's per-shape serving tiles. */
 otfs_status otfs_server_set_tiling(otfs_server_t* srv, int32_t M, int32_t N, int32_t tile_elems);

@@ -74,7 +74,9 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("steps", ctypes.c_uint64), ("queued", ctypes.c_uint64),
                 ("active", ctypes.c_uint64), ("pool_bytes_in_use", ctypes.c_uint64),
-                ("pool_bytes_peak", ctypes.c_uint64)]
+                ("pool_bytes_peak", ctypes.c_uint64), ("ns_admit", ctypes.c_uint64),
+                ("ns_step", ctypes.c_uint64), ("ns_gpu", ctypes.c_uint64),
+                ("ns_fetch", ctypes.c_uint64)]
 
 
 _lib = None
@@ -129,6 +131,12 @@ def lib() -> ctypes.CDLL:
                              ctypes.POINTER(ctypes.c_uint64)]),
         "otfs_poll": (st, [_vp, ctypes.c_uint64, _vp, _vp, ctypes.POINTER(FrameStats),
                            ctypes.POINTER(ctypes.c_uint64)]),
+        "otfs_submit_many": (st, [_vp, ctypes.POINTER(FrameDesc), ctypes.c_int32,
+                                  ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_uint64)]),
+        "otfs_poll_many": (st, [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
+                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                ctypes.POINTER(FrameStats), ctypes.POINTER(ctypes.c_uint64),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
         "otfs_server_stats": (st, [_vp, ctypes.POINTER(ServerStats)]),
         "otfs_server_set_tiling": (st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "otfs_server_frame_bytes": (st, [_vp, ctypes.POINTER(FrameDesc),
@@ -454,21 +462,42 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
+    @staticmethod
+    def prepare(frame) -> "_Descs":
+        """The frame's descriptor built once, for repeated submits of the same channel."""
+        return frame if isinstance(frame, _Descs) else _Descs([frame])
+
     def submit(self, frame, y) -> int:
-        """Queue one frame; y: host complex64 array of M*N values (copied)."""
-        y = np.ascontiguousarray(np.asarray(y, dtype=np.complex64).reshape(-1))
-        if y.size != int(frame.M) * int(frame.N):
-            raise ValueError(f"y: need {int(frame.M) * int(frame.N)} values, got {y.size}")
-        descs = _Descs([frame])
+        """Queue one frame (a frame spec, or its prepare() result); y: host complex64 array
+        of M*N values (copied)."""
+        descs = self.prepare(frame)
+        E = int(descs.arr[0].M) * int(descs.arr[0].N)
+        if not (isinstance(y, np.ndarray) and y.dtype == np.complex64 and y.flags.c_contiguous):
+            y = np.ascontiguousarray(np.asarray(y, dtype=np.complex64))
+        if y.size != E:
+            raise ValueError(f"y: need {E} values, got {y.size}")
         t = ctypes.c_uint64()
         _check(self._lib.otfs_submit(self._h, descs.arr, _vp(y.ctypes.data), ctypes.byref(t)))
         return int(t.value)
 
-    def poll(self, ticket: int, frame):
-        """None while running; else (xhat, sym or None, FrameStats, latency_s)."""
-        E = int(frame.M) * int(frame.N)
-        x = np.empty(E, dtype=np.complex64)
-        sym = np.empty(E, dtype=np.uint8) if int(getattr(frame, "qam", 0) or 0) > 0 else None
+    def poll(self, ticket: int, frame, out=None):
+        """None while running; else (xhat, sym or None, FrameStats, latency_s).  out: an
+        optional (xhat, sym) pair of arrays (complex64 and uint8, M*N each; sym may be None)
+        to receive the results instead of new arrays."""
+        if isinstance(frame, _Descs):
+            E, qam = int(frame.arr[0].M) * int(frame.arr[0].N), int(frame.arr[0].qam)
+        else:
+            E, qam = int(frame.M) * int(frame.N), int(getattr(frame, "qam", 0) or 0)
+        if out is not None:
+            x, sym = out
+            if x.dtype != np.complex64 or x.size != E or not x.flags.c_contiguous or (
+                    sym is not None and (sym.dtype != np.uint8 or sym.size != E)):
+                raise ValueError("out: need complex64 and uint8 arrays of M*N values")
+            if qam <= 0:
+                sym = None
+        else:
+            x = np.empty(E, dtype=np.complex64)
+            sym = np.empty(E, dtype=np.uint8) if qam > 0 else None
         st = FrameStats()
         lat = ctypes.c_uint64()
         status = self._lib.otfs_poll(self._h, ctypes.c_uint64(ticket), _vp(x.ctypes.data),
@@ -479,11 +508,64 @@ class Server:
         _check(status)
         return x, sym, st, lat.value * 1e-9
 
-    def wait(self, ticket: int, frame, timeout: float = 60.0, sleep: float = 1e-4):
+    def submit_many(self, frames, ys) -> List[int]:
+        """Queue frames[i] (specs or prepare() results) with received frames ys[i] (host
+        complex64 arrays, copied) in one call; returns their tickets."""
+        n = len(frames)
+        if n != len(ys):
+            raise ValueError("need one y per frame")
+        arr = (FrameDesc * max(n, 1))()
+        keep = []
+        ptrs = (_vp * max(n, 1))()
+        for i, (f, y) in enumerate(zip(frames, ys)):
+            d = self.prepare(f)
+            keep.append(d)
+            arr[i] = d.arr[0]
+            E = int(d.arr[0].M) * int(d.arr[0].N)
+            if not (isinstance(y, np.ndarray) and y.dtype == np.complex64 and y.flags.c_contiguous):
+                y = np.ascontiguousarray(np.asarray(y, dtype=np.complex64))
+            if y.size != E:
+                raise ValueError(f"ys[{i}]: need {E} values, got {y.size}")
+            keep.append(y)
+            ptrs[i] = y.ctypes.data
+        t = (ctypes.c_uint64 * max(n, 1))()
+        _check(self._lib.otfs_submit_many(self._h, arr, n, ptrs, t))
+        return [int(t[i]) for i in range(n)]
+
+    def poll_many(self, tickets, outs):
+        """Poll tickets[i] into outs[i] = (xhat, sym or None) arrays (complex64 / uint8, M*N
+        each).  Returns a list with (FrameStats, latency_s) for the finished tickets and None
+        for those still running."""
+        n = len(tickets)
+        tk = (ctypes.c_uint64 * max(n, 1))(*tickets)
+        xp = (_vp * max(n, 1))()
+        sp = (_vp * max(n, 1))()
+        for i, (x, sym) in enumerate(outs):
+            if x.dtype != np.complex64 or not x.flags.c_contiguous:
+                raise ValueError("outs: xhat must be a contiguous complex64 array")
+            xp[i] = x.ctypes.data
+            sp[i] = sym.ctypes.data if sym is not None else None
+        stats = (FrameStats * max(n, 1))()
+        lat = (ctypes.c_uint64 * max(n, 1))()
+        status = (ctypes.c_int32 * max(n, 1))()
+        nd = ctypes.c_int32()
+        _check(self._lib.otfs_poll_many(self._h, tk, n, xp, sp, stats, lat, status,
+                                        ctypes.byref(nd)))
+        res = []
+        for i in range(n):
+            if status[i] == 0:
+                res.append((stats[i], lat[i] * 1e-9))
+            elif status[i] == E_AGAIN:
+                res.append(None)
+            else:
+                raise OtfsError(int(status[i]), f"ticket {tickets[i]}: status {status[i]}")
+        return res
+
+    def wait(self, ticket: int, frame, timeout: float = 60.0, sleep: float = 1e-4, out=None):
         import time
         t_end = time.monotonic() + timeout
         while True:
-            r = self.poll(ticket, frame)
+            r = self.poll(ticket, frame, out=out)
             if r is not None:
                 return r
             if time.monotonic() > t_end:

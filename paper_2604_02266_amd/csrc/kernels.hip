@@ -2949,6 +2949,26 @@ hipError_t launch_trace_errors(const FrameDev* frames, const WorkItem* items, in
   return hipGetLastError();
 }
 
+// Gather of result regions into one staging buffer (the serving loop's result copy): one
+// workgroup per segment, 16-byte vector copies, the last bytes of a segment one by one.
+__global__ __launch_bounds__(256) void k_gather_segments(const CopySeg* __restrict__ segs,
+                                                         unsigned char* __restrict__ dst) {
+  const CopySeg sg = segs[blockIdx.x];
+  const uint64_t n16 = sg.bytes / 16;
+  const uint4* s4 = reinterpret_cast<const uint4*>(sg.src);
+  uint4* d4 = reinterpret_cast<uint4*>(dst + sg.dst);
+  for (uint64_t i = threadIdx.x; i < n16; i += blockDim.x) d4[i] = s4[i];
+  for (uint64_t i = n16 * 16 + threadIdx.x; i < sg.bytes; i += blockDim.x)
+    dst[sg.dst + i] = sg.src[i];
+}
+
+hipError_t launch_gather_segments(const CopySeg* segs, int nseg, unsigned char* dst,
+                                  hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_segments, dim3((unsigned)nseg), dim3(256), 0, s, segs, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s) {
   if (n > 0)
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0,

@@ -219,6 +219,17 @@ hipError_t launch_trace_errors(const FrameDev* frames, const WorkItem* items, in
                                const uint8_t* tx, unsigned long long* errs, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 
+// One piece of a gather copy: `bytes` bytes from device address src to byte offset dst of
+// the destination buffer (src and dst 16-byte aligned).
+struct CopySeg {
+  const unsigned char* src;
+  uint64_t dst;
+  uint64_t bytes;
+};
+// Copy nseg segments (device array segs) into dst, one workgroup per segment.
+hipError_t launch_gather_segments(const CopySeg* segs, int nseg, unsigned char* dst,
+                                  hipStream_t s);
+
 // Discrete Zak transform (inverse = false, Eq. zak) or its inverse (Eq. iZak) of nframes
 // frames of M x N complex64 samples (dzt.hip): batched GEMM on MFMA.  in and out distinct.
 hipError_t launch_dzt(int M, int N, int nframes, bool inverse, const float2* in, float2* out,

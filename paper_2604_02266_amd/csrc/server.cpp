@@ -31,7 +31,7 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 #ifndef OTFS_SERVE_TILE
-#define OTFS_SERVE_TILE 8192
+#define OTFS_SERVE_TILE 32768
 #endif
 constexpr int kServeTileElems = OTFS_SERVE_TILE;   // frame-local tiling rule (independent of the mix)
 }  // namespace
@@ -89,10 +89,12 @@ class PoolAlloc {
   size_t used_ = 0;
 };
 
-// Byte offsets inside one frame's slot.
+// Byte offsets inside one frame's slot.  The inputs (y, tables, paths, initial state) come
+// first, in [0, in_bytes): the submitting thread writes them into one page-locked host
+// buffer of the same layout, and admission is a single copy of that buffer.
 struct SlotLayout {
-  size_t y, x, c, p0, p1, t, a, u, rtab, wtab, rtab64, wtab64, paths, part_pa, part_cc, part_d,
-      bar, prog, st, sym, total;
+  size_t y, rtab, wtab, rtab64, wtab64, paths, st, in_bytes, x, c, p0, p1, t, a, u, part_pa,
+      part_cc, part_d, bar, prog, sym, total;
 };
 
 SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
@@ -105,6 +107,13 @@ SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
   };
   const size_t E = (size_t)f.M * f.N;
   L.y = take(E * 8);
+  L.rtab = take((size_t)f.P * f.M * 8);
+  L.wtab = take((size_t)f.N * 8);
+  L.rtab64 = refresh ? take((size_t)f.P * f.M * 16) : 0;
+  L.wtab64 = refresh ? take((size_t)f.N * 16) : 0;
+  L.paths = take((size_t)f.P * 8);
+  L.st = take(sizeof(FrameState));
+  L.in_bytes = o;
   L.x = take(E * 8);
   L.c = take(E * 8);
   L.p0 = take(E * 8);
@@ -112,17 +121,11 @@ SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
   L.t = take(E * 8);
   L.a = take(E * 8);
   L.u = refresh ? take(E * 16) : 0;
-  L.rtab = take((size_t)f.P * f.M * 8);
-  L.wtab = take((size_t)f.N * 8);
-  L.rtab64 = refresh ? take((size_t)f.P * f.M * 16) : 0;
-  L.wtab64 = refresh ? take((size_t)f.N * 16) : 0;
-  L.paths = take((size_t)f.P * 8);
   L.part_pa = take((size_t)tiles * 4);
   L.part_cc = take((size_t)tiles * 4);
   L.part_d = take((size_t)tiles * 8);
   L.bar = take(4);
   L.prog = take((size_t)tiles * 4);
-  L.st = take(sizeof(FrameState));
   L.sym = take(E);
   L.total = o;
   return L;
@@ -130,8 +133,11 @@ SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
 
 // Control region at the start of the pool: step descriptors.
 struct CtrlLayout {
-  size_t frames, items, qitems, qrange, qhead, abort, stats, probe, total;
+  size_t frames, items, qitems, qrange, qhead, abort, stats, probe, segs, mirror, results, total;
 };
+// Device staging of finished frames' results (x-hat and decisions), gathered by a kernel
+// and copied to the host in one piece per chunk of this size.
+constexpr size_t kResultStage = (size_t)32 << 20;
 CtrlLayout ctrl_layout() {
   CtrlLayout C{};
   size_t o = 0;
@@ -148,6 +154,9 @@ CtrlLayout ctrl_layout() {
   C.abort = take(sizeof(unsigned));
   C.stats = take(kMaxActive * sizeof(otfs_frame_stats));
   C.probe = take(kProbeBlocks * sizeof(int));
+  C.segs = take(2 * kMaxActive * sizeof(CopySeg));
+  C.mirror = o;   // the host mirror holds everything before the result staging
+  C.results = take(kResultStage);
   C.total = o;
   return C;
 }
@@ -168,7 +177,16 @@ class HostPool {
         else std::free(p);
       }
   }
+  // Buffers are kept per size class (eight classes per power of two, at most 12.5 % over the
+  // request), so frames whose shapes or path counts differ a little reuse each other's.
+  static size_t size_class(size_t n) {
+    if (n <= 4096) return 4096;
+    int b = 63 - __builtin_clzll((unsigned long long)n);   // 2^b <= n
+    const size_t step = (size_t)1 << (b - 3);
+    return (n + step - 1) / step * step;
+  }
   void* get(size_t n) {
+    n = size_class(n);
     {
       std::lock_guard<std::mutex> g(mu_);
       auto it = free_.find(n);
@@ -190,6 +208,7 @@ class HostPool {
     return std::malloc(n);
   }
   void put(void* p, size_t n) {
+    n = size_class(n);
     std::lock_guard<std::mutex> g(mu_);
     free_[n].push_back(p);
   }
@@ -228,7 +247,7 @@ struct HostBuf {
 struct Request {
   uint64_t ticket = 0;
   HostFrame hf;
-  HostBuf y;                     // the received frame (released at retirement)
+  HostBuf in;                    // the slot's input region: y, tables, paths, initial state
   Clock::time_point t_submit, t_done;
   int state = 0;   // 0 queued, 1 admitted, 2 done
   // slot
@@ -238,15 +257,13 @@ struct Request {
   std::vector<WorkItem> items;   // frame-local tiles (frame index patched per step)
   FrameDev dev{};
   FrameDev geo{};                // staging geometry
-  // tables and initial state, built at submission; they stay alive until the frame is
-  // done, so the admission copies need no synchronisation
-  std::vector<float2> r32, w32;
-  std::vector<double2> r64, w64;   // refresh only
-  std::vector<int2> paths;
-  FrameState st0{};
+  // `in` is filled at submission and stays alive until the frame is done, so the
+  // admission copy needs no synchronisation
   // results
-  HostBuf xhat;                  // complex64, M*N
-  HostBuf sym;                   // u8, M*N (QAM frames)
+  // results: x-hat (complex64, M*N) at res_x and the decisions (u8, M*N, QAM frames) at
+  // res_sym of a host buffer that the frames finished in the same chunk share
+  std::shared_ptr<HostBuf> res;
+  size_t res_x = 0, res_sym = 0;
   otfs_frame_stats stats{};
 };
 
@@ -287,8 +304,13 @@ struct otfs_server {
   int cap = 0;              // workgroups of the fused kernel resident at once
   bool ready = false;       // scheduler_init finished
   int active_tiles = 0;
+  // page-locked mirror of the control region: step descriptors are built here and copied
+  // by DMA; the step's per-frame stats come back into it
+  HostBuf stage;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;   // around a step's launches
   // counters
   uint64_t submitted = 0, completed = 0, steps = 0, peak = 0;
+  uint64_t ns_admit = 0, ns_step = 0, ns_gpu = 0, ns_fetch = 0;   // scheduler time split
   // per-shape tile sizes (otfs_server_set_tiling); other shapes use serve_tile_elems()
   std::map<std::pair<int, int>, int> tile_of_shape;
   int tile_elems(const otfs::HostFrame& f) {
@@ -305,25 +327,29 @@ bool frame_fits_ever(otfs_server* S, const SlotLayout& L) {
   return L.total <= S->pool_bytes - S->slot_base;
 }
 
-// Host-side tables of a frame (FP64 phases, FP32 copies for the kernels) and its initial
-// state, built on the submitting thread.
+// Host-side tables of a frame (FP64 phases, FP32 copies for the kernels), its path list
+// and initial state, written into the request's input buffer at the slot's offsets; built
+// on the submitting thread.
 void build_tables(bool refresh, Request* r) {
   const HostFrame& f = r->hf;
+  const SlotLayout& L = r->L;
+  char* in = static_cast<char*>(r->in.p);
   std::vector<double2> r64, w64;
   for (int p = 0; p < f.P; ++p) delay_ramp(f, p, r64);
   wrap_factors(f, w64);
-  r->paths.clear();
-  for (int p = 0; p < f.P; ++p) r->paths.push_back(make_int2(f.tau[p], f.nu[p]));
-  r->r32.resize(r64.size());
-  r->w32.resize(w64.size());
-  for (size_t i = 0; i < r64.size(); ++i) r->r32[i] = make_float2((float)r64[i].x, (float)r64[i].y);
-  for (size_t i = 0; i < w64.size(); ++i) r->w32[i] = make_float2((float)w64[i].x, (float)w64[i].y);
+  int2* paths = reinterpret_cast<int2*>(in + L.paths);
+  for (int p = 0; p < f.P; ++p) paths[p] = make_int2(f.tau[p], f.nu[p]);
+  float2* r32 = reinterpret_cast<float2*>(in + L.rtab);
+  float2* w32 = reinterpret_cast<float2*>(in + L.wtab);
+  for (size_t i = 0; i < r64.size(); ++i) r32[i] = make_float2((float)r64[i].x, (float)r64[i].y);
+  for (size_t i = 0; i < w64.size(); ++i) w32[i] = make_float2((float)w64[i].x, (float)w64[i].y);
   if (refresh) {
-    r->r64 = std::move(r64);
-    r->w64 = std::move(w64);
+    std::memcpy(in + L.rtab64, r64.data(), r64.size() * sizeof(double2));
+    std::memcpy(in + L.wtab64, w64.data(), w64.size() * sizeof(double2));
   }
-  r->st0 = FrameState{};
-  r->st0.status = OTFS_FRAME_RUNNING;
+  FrameState st0{};
+  st0.status = OTFS_FRAME_RUNNING;
+  std::memcpy(in + L.st, &st0, sizeof st0);
 }
 
 // Descriptor of an admitted frame (device pointers into its slot).
@@ -365,25 +391,13 @@ void set_failed(otfs_server* S, const std::string& msg) {
 }
 
 // ---- GPU executor steps (scheduler thread) ----------------------------------------------
-// Enqueue the copies of an admitted frame's inputs into its slot (stream order puts them
-// before the next step; the sources live in the request until it is done).
+// Enqueue the copy of an admitted frame's inputs into its slot: one copy from page-locked
+// memory (stream order puts it before the next step; the source lives in the request until
+// it is done).
 bool gpu_admit(otfs_server* S, Request* r) {
   build_frame_dev(S, r);
   char* base = S->pool + S->slot_base + r->slot_off;
-  hipError_t e = hipSuccess;
-  auto up = [&](size_t off, const void* src, size_t bytes) {
-    if (e == hipSuccess && bytes)
-      e = hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, S->s);
-  };
-  up(r->L.y, r->y.p, r->y.n);
-  up(r->L.rtab, r->r32.data(), r->r32.size() * sizeof(float2));
-  up(r->L.wtab, r->w32.data(), r->w32.size() * sizeof(float2));
-  if (S->opts.refresh_every > 0) {
-    up(r->L.rtab64, r->r64.data(), r->r64.size() * sizeof(double2));
-    up(r->L.wtab64, r->w64.data(), r->w64.size() * sizeof(double2));
-  }
-  up(r->L.paths, r->paths.data(), r->paths.size() * sizeof(int2));
-  up(r->L.st, &r->st0, sizeof r->st0);
+  const hipError_t e = hipMemcpyAsync(base, r->in.p, r->L.in_bytes, hipMemcpyHostToDevice, S->s);
   if (e != hipSuccess) {
     set_failed(S, std::string("admission copy: ") + hipGetErrorString(e));
     return false;
@@ -393,27 +407,30 @@ bool gpu_admit(otfs_server* S, Request* r) {
 
 bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame_stats>& out) {
   const int n = (int)act.size();
-  std::vector<FrameDev> fd(n);
+  const CtrlLayout& C = S->C;
+  char* H = static_cast<char*>(S->stage.p);
+  FrameDev* fd = reinterpret_cast<FrameDev*>(H + C.frames);
+  WorkItem* items_h = reinterpret_cast<WorkItem*>(H + C.items);
   std::vector<HostFrame> frames(n);
-  std::vector<WorkItem> items;
   std::vector<int> tile_base(n), tiles(n);
-  otfs_frame_stats* dstats = reinterpret_cast<otfs_frame_stats*>(S->pool + S->C.stats);
+  otfs_frame_stats* dstats = reinterpret_cast<otfs_frame_stats*>(S->pool + C.stats);
+  int nitems = 0;
   for (int i = 0; i < n; ++i) {
     Request* r = act[i];
     fd[i] = r->dev;
     fd[i].stats = dstats + i;
     fd[i].index = i;
     frames[i] = r->hf;
-    tile_base[i] = (int)items.size();
+    tile_base[i] = nitems;
     tiles[i] = r->tiles;
+    if (nitems + (int)r->items.size() > kMaxItems) {
+      set_failed(S, "too many tiles in one step");
+      return false;
+    }
     for (WorkItem w : r->items) {
       w.frame = i;
-      items.push_back(w);
+      items_h[nitems++] = w;
     }
-  }
-  if ((int)items.size() > kMaxItems) {
-    set_failed(S, "too many tiles in one step");
-    return false;
   }
   std::vector<int32_t> qitems;
   std::vector<int2> qrange;
@@ -426,19 +443,21 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
     set_failed(S, otfs_last_error());
     return false;
   }
+  std::memcpy(H + C.qitems, qitems.data(), qitems.size() * sizeof(int32_t));
+  std::memcpy(H + C.qrange, qrange.data(), qrange.size() * sizeof(int2));
   char* P = S->pool;
-  const CtrlLayout& C = S->C;
   hipError_t e = hipSuccess;
-  auto up = [&](size_t off, const void* src, size_t bytes) {
-    if (e == hipSuccess && bytes) e = hipMemcpyAsync(P + off, src, bytes, hipMemcpyHostToDevice, S->s);
+  auto up = [&](size_t off, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(P + off, H + off, bytes, hipMemcpyHostToDevice, S->s);
   };
-  up(C.frames, fd.data(), fd.size() * sizeof(FrameDev));
-  up(C.items, items.data(), items.size() * sizeof(WorkItem));
-  up(C.qitems, qitems.data(), qitems.size() * sizeof(int32_t));
-  up(C.qrange, qrange.data(), qrange.size() * sizeof(int2));
+  up(C.frames, (size_t)n * sizeof(FrameDev));
+  up(C.items, (size_t)nitems * sizeof(WorkItem));
+  up(C.qitems, qitems.size() * sizeof(int32_t));
+  up(C.qrange, qrange.size() * sizeof(int2));
   const FrameDev* dframes = reinterpret_cast<const FrameDev*>(P + C.frames);
   unsigned* qhead = reinterpret_cast<unsigned*>(P + C.qhead);
   unsigned* abort_flag = reinterpret_cast<unsigned*>(P + C.abort);
+  if (e == hipSuccess) e = hipEventRecord(S->ev_begin, S->s);
   if (e == hipSuccess)
     e = launch_step_reset(dframes, n, abort_flag, qhead, kKinds * kMaxGroups, S->s);
   Bases B{nullptr, nullptr, nullptr, nullptr};
@@ -453,37 +472,96 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   // frames that reached a refresh point in this step get their FP64 true residual before
   // the next step resumes them
   if (e == hipSuccess && S->opts.refresh_every > 0)
-    e = launch_refresh(dframes, reinterpret_cast<const WorkItem*>(P + C.items), (int)items.size(),
+    e = launch_refresh(dframes, reinterpret_cast<const WorkItem*>(P + C.items), nitems,
                        B, qhead, kKinds * kMaxGroups, S->s);
-  out.resize(n);
+  if (e == hipSuccess) e = hipEventRecord(S->ev_end, S->s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(out.data(), dstats, n * sizeof(otfs_frame_stats), hipMemcpyDeviceToHost, S->s);
+    e = hipMemcpyAsync(H + C.stats, dstats, (size_t)n * sizeof(otfs_frame_stats),
+                       hipMemcpyDeviceToHost, S->s);
   if (e == hipSuccess) e = hipStreamSynchronize(S->s);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, S->ev_begin, S->ev_end);
   if (e != hipSuccess) {
     set_failed(S, std::string("serving step: ") + hipGetErrorString(e));
     return false;
   }
+  out.resize(n);
+  std::memcpy(out.data(), H + C.stats, (size_t)n * sizeof(otfs_frame_stats));
+  S->ns_gpu += (uint64_t)((double)ms * 1e6);
   return true;
 }
 
-// Results of the frames finished in a step: every copy enqueued, one synchronisation.
+// Results of the frames finished in a step.  Chunk by chunk (up to kResultStage bytes), a
+// kernel gathers the frames' x-hat and decisions from their slots into the staging region
+// and one copy brings the chunk to a page-locked host buffer that those frames share; a
+// frame too large for the staging region is copied from its slot directly.
 bool gpu_fetch(otfs_server* S, const std::vector<Request*>& done) {
+  const CtrlLayout& C = S->C;
+  char* H = static_cast<char*>(S->stage.p);
+  CopySeg* segs_h = reinterpret_cast<CopySeg*>(H + C.segs);
+  const CopySeg* segs_d = reinterpret_cast<const CopySeg*>(S->pool + C.segs);
+  unsigned char* stage_d = reinterpret_cast<unsigned char*>(S->pool + C.results);
   hipError_t e = hipSuccess;
-  for (Request* r : done) {
+  auto result_bytes = [](const Request* r, size_t* xo, size_t* so) {
     const size_t E = (size_t)r->hf.M * r->hf.N;
-    if (!r->xhat.take(S->hpool, E * sizeof(float2)) ||
-        (r->hf.qam > 0 && !r->sym.take(S->hpool, E))) {
+    *xo = 0;
+    *so = align_up(E * sizeof(float2));
+    return align_up(*so + (r->hf.qam > 0 ? E : 0));
+  };
+  size_t i = 0;
+  while (e == hipSuccess && i < done.size()) {
+    size_t xo, so;
+    const size_t b0 = result_bytes(done[i], &xo, &so);
+    auto buf = std::make_shared<HostBuf>();
+    if (b0 > kResultStage) {   // alone, straight from its slot
+      Request* r = done[i];
+      const size_t E = (size_t)r->hf.M * r->hf.N;
+      if (!buf->take(S->hpool, b0)) {
+        set_failed(S, "result copy: out of host memory");
+        return false;
+      }
+      char* base = S->pool + S->slot_base + r->slot_off;
+      char* hb = static_cast<char*>(buf->p);
+      e = hipMemcpyAsync(hb + xo, base + r->L.x, E * sizeof(float2), hipMemcpyDeviceToHost, S->s);
+      if (e == hipSuccess && r->hf.qam > 0)
+        e = hipMemcpyAsync(hb + so, base + r->L.sym, E, hipMemcpyDeviceToHost, S->s);
+      if (e == hipSuccess) e = hipStreamSynchronize(S->s);
+      r->res = buf;
+      r->res_x = xo;
+      r->res_sym = so;
+      ++i;
+      continue;
+    }
+    // frames [i, j) fill this chunk
+    size_t used = 0;
+    int nseg = 0;
+    size_t j = i;
+    for (; j < done.size(); ++j) {
+      Request* r = done[j];
+      const size_t b = result_bytes(r, &xo, &so);
+      if (b > kResultStage || used + b > kResultStage) break;
+      const size_t E = (size_t)r->hf.M * r->hf.N;
+      const unsigned char* base =
+          reinterpret_cast<const unsigned char*>(S->pool + S->slot_base + r->slot_off);
+      segs_h[nseg++] = CopySeg{base + r->L.x, used + xo, E * sizeof(float2)};
+      if (r->hf.qam > 0) segs_h[nseg++] = CopySeg{base + r->L.sym, used + so, E};
+      r->res_x = used + xo;
+      r->res_sym = used + so;
+      used += b;
+    }
+    if (!buf->take(S->hpool, used)) {
       set_failed(S, "result copy: out of host memory");
       return false;
     }
-    char* base = S->pool + S->slot_base + r->slot_off;
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(r->xhat.p, base + r->L.x, E * sizeof(float2), hipMemcpyDeviceToHost,
-                         S->s);
-    if (r->hf.qam > 0 && e == hipSuccess)
-      e = hipMemcpyAsync(r->sym.p, base + r->L.sym, E, hipMemcpyDeviceToHost, S->s);
+    e = hipMemcpyAsync(S->pool + C.segs, segs_h, (size_t)nseg * sizeof(CopySeg),
+                       hipMemcpyHostToDevice, S->s);
+    if (e == hipSuccess) e = launch_gather_segments(segs_d, nseg, stage_d, S->s);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf->p, stage_d, used, hipMemcpyDeviceToHost, S->s);
+    // the segment list in the host mirror is rewritten by the next chunk: wait here
+    if (e == hipSuccess) e = hipStreamSynchronize(S->s);
+    for (size_t k = i; k < j; ++k) done[k]->res = buf;
+    i = j;
   }
-  if (e == hipSuccess && !done.empty()) e = hipStreamSynchronize(S->s);
   if (e != hipSuccess) {
     set_failed(S, std::string("result copy: ") + hipGetErrorString(e));
     return false;
@@ -506,6 +584,16 @@ bool scheduler_init(otfs_server* S) {
   }
   if (probe_xcds(S->device, S->pool + S->C.probe, S->s, &S->xcd) != OTFS_OK) {
     set_failed(S, std::string("XCC probe: ") + otfs_last_error());
+    return false;
+  }
+  if (!S->stage.take(S->hpool, S->C.mirror)) {
+    set_failed(S, "no host memory for the step descriptors");
+    return false;
+  }
+  e = hipEventCreate(&S->ev_begin);
+  if (e == hipSuccess) e = hipEventCreate(&S->ev_end);
+  if (e != hipSuccess) {
+    set_failed(S, std::string("server events: ") + hipGetErrorString(e));
     return false;
   }
   int v = 0;
@@ -545,9 +633,11 @@ void scheduler(otfs_server* S) {
       }
       S->peak = std::max<uint64_t>(S->peak, S->alloc.used());
     }
+    const auto t_admit = Clock::now();
     for (Request* r : admitted) {
       if (!S->dry && !gpu_admit(S, r)) return;
     }
+    const auto t_step = Clock::now();
     std::vector<Request*> act;
     {
       std::lock_guard<std::mutex> g(S->mu);
@@ -570,6 +660,7 @@ void scheduler(otfs_server* S) {
     } else if (!gpu_step(S, act, st)) {
       return;
     }
+    const auto t_fetch = Clock::now();
     std::vector<Request*> done;
     for (size_t i = 0; i < act.size(); ++i)
       if (st[i].status != OTFS_FRAME_RUNNING) {
@@ -579,8 +670,13 @@ void scheduler(otfs_server* S) {
     if (S->dry) {
       for (Request* r : done) {
         const size_t E = (size_t)r->hf.M * r->hf.N;
-        if (r->xhat.take(S->hpool, E * sizeof(float2))) std::memset(r->xhat.p, 0, r->xhat.n);
-        if (r->hf.qam > 0 && r->sym.take(S->hpool, E)) std::memset(r->sym.p, 0, r->sym.n);
+        auto buf = std::make_shared<HostBuf>();
+        const size_t so = align_up(E * sizeof(float2));
+        const size_t b = so + (r->hf.qam > 0 ? E : 0);
+        if (buf->take(S->hpool, b)) std::memset(buf->p, 0, b);
+        r->res = buf;
+        r->res_x = 0;
+        r->res_sym = so;
       }
     } else if (!gpu_fetch(S, done)) {
       return;
@@ -588,10 +684,16 @@ void scheduler(otfs_server* S) {
     {
       std::lock_guard<std::mutex> g(S->mu);
       const auto now = Clock::now();
+      auto ns = [](Clock::duration d) {
+        return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(d).count();
+      };
+      S->ns_admit += ns(t_step - t_admit);
+      S->ns_step += ns(t_fetch - t_step);
+      S->ns_fetch += ns(now - t_fetch);
       for (Request* r : done) {
         r->t_done = now;
         r->state = 2;
-        r->y.reset();   // its admission copy finished at an earlier step's synchronisation
+        r->in.reset();   // its admission copy finished at an earlier step's synchronisation
         S->alloc.release(r->slot_off, r->L.total);
         S->active_tiles -= r->tiles;
         S->active.erase(std::find(S->active.begin(), S->active.end(), r));
@@ -664,13 +766,16 @@ extern "C" otfs_status otfs_server_create(int device, void* pool_dev, size_t poo
   return OTFS_OK;
 }
 
-extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* frame,
-                                   const void* y_host, uint64_t* ticket) {
-  if (!S || !frame || !y_host || !ticket) return fail(OTFS_E_INVAL, "null argument");
+namespace otfs {
+namespace {
+// A request for one frame: validation, tiling, slot layout, its inputs copied into a
+// page-locked buffer and its tables built (the submitting thread's share of the work).
+otfs_status make_request(otfs_server* S, const otfs_frame_desc& frame, const void* y_host,
+                         std::unique_ptr<Request>* out) {
   auto r = std::make_unique<Request>();
-  otfs_status st = validate_frame(*frame, 0, &r->hf);
+  otfs_status st = validate_frame(frame, 0, &r->hf);
   if (st != OTFS_OK) return st;
-  const size_t E = (size_t)frame->M * frame->N;
+  const size_t E = (size_t)frame.M * frame.N;
   std::vector<WorkItem> items;
   std::vector<int> tb, tl;
   make_tiles(std::vector<HostFrame>{r->hf}, S->tile_elems(r->hf), items, tb, tl);
@@ -686,19 +791,51 @@ extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* fram
   if (!frame_fits_ever(S, r->L))
     return fail(OTFS_E_BUDGET, "frame state needs %zu bytes, the pool has %zu for frames",
                 r->L.total, S->pool_bytes - S->slot_base);
-  if (!r->y.take(S->hpool, E * sizeof(float2)))
-    return fail(OTFS_E_NOMEM, "no host memory for the frame's copy of y");
-  std::memcpy(r->y.p, y_host, E * sizeof(float2));
+  if (!r->in.take(S->hpool, r->L.in_bytes))
+    return fail(OTFS_E_NOMEM, "no host memory for the frame's inputs");
+  std::memcpy(static_cast<char*>(r->in.p) + r->L.y, y_host, E * sizeof(float2));
   build_tables(S->opts.refresh_every > 0, r.get());
-  r->t_submit = Clock::now();
-  std::lock_guard<std::mutex> g(S->mu);
-  if (S->failed) return fail(OTFS_E_DEVICE, "server failed: %s", S->fail_msg.c_str());
-  r->ticket = S->next_ticket++;
-  *ticket = r->ticket;
-  Request* raw = r.get();
-  S->reqs.emplace(raw->ticket, std::move(r));
-  S->queue.push_back(raw);
-  ++S->submitted;
+  *out = std::move(r);
+  return OTFS_OK;
+}
+
+// Queue requests in order (S->mu held): tickets, submit times, the scheduler's queue.
+void enqueue_locked(otfs_server* S, std::vector<std::unique_ptr<Request>>& rs, uint64_t* tickets) {
+  const auto now = Clock::now();
+  for (size_t i = 0; i < rs.size(); ++i) {
+    Request* raw = rs[i].get();
+    raw->t_submit = now;
+    raw->ticket = S->next_ticket++;
+    tickets[i] = raw->ticket;
+    S->reqs.emplace(raw->ticket, std::move(rs[i]));
+    S->queue.push_back(raw);
+    ++S->submitted;
+  }
+}
+}  // namespace
+}  // namespace otfs
+
+extern "C" otfs_status otfs_submit(otfs_server_t* S, const otfs_frame_desc* frame,
+                                   const void* y_host, uint64_t* ticket) {
+  return otfs_submit_many(S, frame, 1, &y_host, ticket);
+}
+
+extern "C" otfs_status otfs_submit_many(otfs_server_t* S, const otfs_frame_desc* frames,
+                                        int32_t n, const void* const* y_host,
+                                        uint64_t* tickets) {
+  if (!S || n < 0 || (n > 0 && (!frames || !y_host || !tickets)))
+    return fail(OTFS_E_INVAL, "null argument or negative count");
+  std::vector<std::unique_ptr<Request>> rs((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!y_host[i]) return fail(OTFS_E_INVAL, "y_host[%d] is null", i);
+    const otfs_status st = make_request(S, frames[i], y_host[i], &rs[i]);
+    if (st != OTFS_OK) return st;   // nothing queued
+  }
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->failed) return fail(OTFS_E_DEVICE, "server failed: %s", S->fail_msg.c_str());
+    enqueue_locked(S, rs, tickets);
+  }
   S->cv.notify_all();
   return OTFS_OK;
 }
@@ -730,6 +867,24 @@ extern "C" otfs_status otfs_server_frame_bytes(otfs_server_t* S, const otfs_fram
   return OTFS_OK;
 }
 
+namespace otfs {
+namespace {
+// Copy a finished request's results out (no lock needed: the request is no longer shared).
+void deliver(const Request& r, void* xhat_host, uint8_t* sym_host, otfs_frame_stats* stats,
+             uint64_t* latency_ns) {
+  const size_t E = (size_t)r.hf.M * r.hf.N;
+  if (r.res && !r.res->empty()) {
+    const char* hb = static_cast<const char*>(r.res->p);
+    if (xhat_host) std::memcpy(xhat_host, hb + r.res_x, E * sizeof(float2));
+    if (sym_host && r.hf.qam > 0) std::memcpy(sym_host, hb + r.res_sym, E);
+  }
+  if (stats) *stats = r.stats;
+  if (latency_ns)
+    *latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r.t_done - r.t_submit).count();
+}
+}  // namespace
+}  // namespace otfs
+
 extern "C" otfs_status otfs_poll(otfs_server_t* S, uint64_t ticket, void* xhat_host,
                                  uint8_t* sym_host, otfs_frame_stats* stats,
                                  uint64_t* latency_ns) {
@@ -746,11 +901,38 @@ extern "C" otfs_status otfs_poll(otfs_server_t* S, uint64_t ticket, void* xhat_h
     r = std::move(it->second);
     S->reqs.erase(it);
   }
-  if (xhat_host && !r->xhat.empty()) std::memcpy(xhat_host, r->xhat.p, r->xhat.n);
-  if (sym_host && !r->sym.empty()) std::memcpy(sym_host, r->sym.p, r->sym.n);
-  if (stats) *stats = r->stats;
-  if (latency_ns)
-    *latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
+  deliver(*r, xhat_host, sym_host, stats, latency_ns);
+  return OTFS_OK;
+}
+
+extern "C" otfs_status otfs_poll_many(otfs_server_t* S, const uint64_t* tickets, int32_t n,
+                                      void* const* xhat_host, uint8_t* const* sym_host,
+                                      otfs_frame_stats* stats, uint64_t* latency_ns,
+                                      int32_t* status, int32_t* ndone) {
+  if (!S || n < 0 || (n > 0 && (!tickets || !status)))
+    return fail(OTFS_E_INVAL, "null argument or negative count");
+  std::vector<std::pair<int32_t, std::unique_ptr<Request>>> got;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    for (int32_t i = 0; i < n; ++i) {
+      auto it = S->reqs.find(tickets[i]);
+      if (it == S->reqs.end()) {
+        status[i] = OTFS_E_NOTFOUND;
+      } else if (it->second->state != 2) {
+        status[i] = S->failed ? OTFS_E_DEVICE : OTFS_E_AGAIN;
+      } else {
+        status[i] = OTFS_OK;
+        got.emplace_back(i, std::move(it->second));
+        S->reqs.erase(it);
+      }
+    }
+  }
+  for (auto& gr : got) {
+    const int32_t i = gr.first;
+    deliver(*gr.second, xhat_host ? xhat_host[i] : nullptr, sym_host ? sym_host[i] : nullptr,
+            stats ? stats + i : nullptr, latency_ns ? latency_ns + i : nullptr);
+  }
+  if (ndone) *ndone = (int32_t)got.size();
   return OTFS_OK;
 }
 
@@ -764,6 +946,10 @@ extern "C" otfs_status otfs_server_stats(otfs_server_t* S, otfs_server_stats_t* 
   out->active = S->active.size();
   out->pool_bytes_in_use = S->alloc.used();
   out->pool_bytes_peak = S->peak;
+  out->ns_admit = S->ns_admit;
+  out->ns_step = S->ns_step;
+  out->ns_gpu = S->ns_gpu;
+  out->ns_fetch = S->ns_fetch;
   if (S->failed) return fail(OTFS_E_DEVICE, "server failed: %s", S->fail_msg.c_str());
   return OTFS_OK;
 }
@@ -780,6 +966,8 @@ extern "C" otfs_status otfs_server_free(otfs_server_t* S) {
     (void)hipStreamSynchronize(S->s);
     (void)hipStreamDestroy(S->s);
   }
+  if (S->ev_begin) (void)hipEventDestroy(S->ev_begin);
+  if (S->ev_end) (void)hipEventDestroy(S->ev_end);
   delete S;
   return OTFS_OK;
 }

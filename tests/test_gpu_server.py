@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 NMSE_TOL = 1e-5
 MAX_ITERS, TOL = 50, 1e-6
-SERVE_TILE_ELEMS = 8192      # the server's frame-local tiling rule
+SERVE_TILE_ELEMS = 32768     # the server's frame-local tiling rule
 
 
 @pytest.fixture(scope="module")

@@ -137,3 +137,47 @@ def test_free_with_frames_in_flight():
         s.submit(f, _y(f))
     time.sleep(0.01)
     s.close()          # drops queued and running frames, joins the scheduler
+
+
+def test_submit_many_and_poll_many():
+    with _dry(max_iters=12, step_iters=4) as s:
+        frames = [_frame(), _frame(32, 8, qam=16), _frame(128, 4, qam=0)] * 3
+        prep = [s.prepare(f) for f in frames]
+        tickets = s.submit_many(prep, [_y(f) for f in frames])
+        assert tickets == sorted(tickets) and len(set(tickets)) == len(frames)
+        outs = [(np.full(f.E, 1 + 1j, dtype=np.complex64), np.full(f.E, 7, dtype=np.uint8))
+                for f in frames]
+        left = list(range(len(frames)))
+        t_end = time.monotonic() + 30.0
+        while left:
+            res = s.poll_many([tickets[i] for i in left], [outs[i] for i in left])
+            nxt = []
+            for i, r in zip(left, res):
+                if r is None:
+                    nxt.append(i)
+                    continue
+                st, lat = r
+                assert st.status == otfs.FRAME_DRYRUN and st.iters == 12 and lat >= 0.0
+                assert np.all(outs[i][0] == 0)
+                # a frame without a constellation leaves the decision buffer alone
+                assert np.all(outs[i][1] == (7 if frames[i].qam == 0 else 0))
+            left = nxt
+            assert time.monotonic() < t_end
+            time.sleep(1e-3)
+        ss = s.stats()
+        assert ss.submitted == len(frames) and ss.completed == len(frames)
+        # every ticket was forgotten by the batched poll
+        with pytest.raises(otfs.OtfsError) as ei:
+            s.poll_many([tickets[0]], [outs[0]])
+        assert ei.value.status == otfs.E_NOTFOUND
+
+
+def test_submit_many_rejects_the_whole_batch():
+    with _dry() as s:
+        good = _frame()
+        bad = SpecLike(64, 16, [0, 3], [1, -2], [1.0, 0.5], lam=0.05, qam=5)   # no such QAM
+        with pytest.raises(otfs.OtfsError):
+            s.submit_many([good, bad], [_y(good), _y(bad)])
+        assert s.stats().submitted == 0
+        with pytest.raises(ValueError):
+            s.submit_many([good], [np.zeros(good.E - 1, dtype=np.complex64)])
