@@ -96,6 +96,11 @@ enum {
                                     gathered straight from memory has P <= 8 (and no stored
                                     D), the H pass forms it inside its gathers instead; the
                                     results are identical                                   */
+  OTFS_LDS_GATHER = 1u << 8,     /* fused kernel: frames of several tiles whose rows split
+                                    into 16-byte pairs (M a multiple of 128) gather H and H^H
+                                    through LDS windows (each strip's source window copied in
+                                    once, then read by every path) where the window fits
+                                    160 KiB; the results are identical to the direct gathers */
   OTFS_D_STORED_C64 = 1u << 7    /* store D_{p,q} (Eq. D_definition) in complex64 in the
                                     workspace: the SS table of Eq. ds_repr as the paper keeps
                                     it (Sec. IV-B, "Efficient Data Structure"), P x total_elems

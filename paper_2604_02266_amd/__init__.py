@@ -28,6 +28,7 @@ D_STORED_BF16 = 1 << 0
 Y_BF16 = 1 << 1
 USE_GRAPH = 1 << 2
 TIME_KERNEL = 1 << 3
+LDS_GATHER = 1 << 8
 AGENT_BARRIER = 1 << 4
 NO_LDS_RESIDENT = 1 << 5
 SPLIT_DIRECTION = 1 << 6
@@ -222,6 +223,8 @@ class Plan:
                 stage_bytes = int(self.tuned["stage_bytes"]) or None
                 if self.tuned["split_direction"]:
                     flags |= SPLIT_DIRECTION
+                if self.tuned.get("lds_gather"):
+                    flags |= LDS_GATHER
         self.opts = make_opts(max_iters, rel_tol, refresh_every, flags)
         descs = _Descs(self.frames)
         h = _vp()

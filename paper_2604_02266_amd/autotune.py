@@ -35,6 +35,7 @@ CACHE_PATH = os.environ.get("OTFS_TUNED") or os.path.join(HERE, "tuned.json")
 
 # the flag bits of the header that the tuner may set (the others are the caller's)
 _SPLIT_DIRECTION = 1 << 6
+_LDS_GATHER = 1 << 8
 _D_STORED_BF16, _Y_BF16, _D_STORED_C64 = 1 << 0, 1 << 1, 1 << 7
 
 
@@ -68,7 +69,7 @@ def _load() -> Dict:
 
 def lookup(frames: Sequence, refresh_every: int = 0, flags: int = 0) -> Optional[Dict]:
     """The stored winner for this batch signature: {"tile_elems", "split_direction",
-    "stage_bytes"}, or None."""
+    "stage_bytes", "lds_gather"}, or None."""
     ent = _load()["batches"].get(signature(frames, refresh_every, flags))
     return None if ent is None else ent["best"]
 
@@ -80,7 +81,8 @@ def serving_tiles() -> Dict[str, int]:
 
 def candidates(frames: Sequence, cus: int = 256) -> List[Dict]:
     """Tilings from the frame sizes and the machine (tiles per frame for the largest frame,
-    and tiles per CU for the whole batch), crossed with the direction form."""
+    and tiles per CU for the whole batch), crossed with the direction form and, for frames
+    whose rows split into 16-byte pairs, the LDS-windowed gathers."""
     Emax = max(int(f.M) * int(f.N) for f in frames)
     Etot = sum(int(f.M) * int(f.N) for f in frames)
     Nmax = max(int(f.N) for f in frames)
@@ -91,11 +93,17 @@ def candidates(frames: Sequence, cus: int = 256) -> List[Dict]:
     for w in (0.5, 1.0, 2.0):
         tiles.add(max(512, int(Etot / (cus * w))))
     tiles = sorted(t for t in tiles if t >= 512)
+    pairs = any(int(f.M) % 128 == 0 for f in frames)
     out = []
     for te in tiles:
-        out.append({"tile_elems": te, "split_direction": False, "stage_bytes": 0})
+        out.append({"tile_elems": te, "split_direction": False, "stage_bytes": 0,
+                    "lds_gather": False})
         if max(int(np.asarray(f.tau).shape[0]) for f in frames) <= 8:
-            out.append({"tile_elems": te, "split_direction": True, "stage_bytes": 0})
+            out.append({"tile_elems": te, "split_direction": True, "stage_bytes": 0,
+                        "lds_gather": False})
+        if pairs:
+            out.append({"tile_elems": te, "split_direction": False, "stage_bytes": 0,
+                        "lds_gather": True})
     return out
 
 
@@ -125,6 +133,7 @@ def _received(otfs, torch, frames, seed=7):
 
 def _time(otfs, torch, frames, y, cand, max_iters, rel_tol, refresh_every, flags, reps):
     fl = flags | otfs.TIME_KERNEL | (_SPLIT_DIRECTION if cand["split_direction"] else 0)
+    fl |= _LDS_GATHER if cand.get("lds_gather") else 0
     plan = otfs.Plan(frames, max_iters=max_iters, rel_tol=rel_tol, refresh_every=refresh_every,
                      flags=fl, tile_elems=cand["tile_elems"],
                      stage_bytes=cand["stage_bytes"], tune=False)
@@ -169,7 +178,8 @@ def tune(frames: Sequence, max_iters: int = 50, rel_tol: float = 1e-6, refresh_e
         raise RuntimeError("no candidate ran")
     best = min(good, key=lambda r: r["ms"])
     sig = signature(frames, refresh_every, flags)
-    ent = {"best": {k: best[k] for k in ("tile_elems", "split_direction", "stage_bytes")},
+    ent = {"best": {k: best.get(k, False) for k in ("tile_elems", "split_direction", "stage_bytes",
+                                                     "lds_gather")},
            "ms": best["ms"], "device": torch.cuda.get_device_name(0),
            "date": time.strftime("%Y-%m-%d"), "table": table}
     if save:

@@ -722,6 +722,7 @@ __device__ __forceinline__ int strip_lanes(int width, int band_rows, int R) {
 }
 constexpr int kRows = OTFS_ROWS;    // rows per thread chunk in the FP32 gathers
 constexpr int kPaths = OTFS_PATHS;  // paths whose gathers are in flight together
+static_assert(kRows == OTFS_ROWS, "the host's strip rule assumes kRows rows per chunk");
 #ifndef OTFS_PATHS_GENERAL
 #define OTFS_PATHS_GENERAL 2
 #endif
@@ -1059,6 +1060,161 @@ __device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int 
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// LDS-windowed paired band application (frames of the staged kind with F.lpk > 0).
+//
+// The outputs, their assignment to threads, the order in which each thread produces them
+// and the operations forming each one are those of band_apply_pairs, so the two give
+// identical bits; only where the source elements come from changes.  For each strip of
+// KC = 2 TX delay columns (TX lanes across a row, as band_apply_pairs chooses them) the
+// workgroup first copies the strip's source window -- every row the band's paths reach
+// (rows [lb - nu_hi, le - nu_lo) for H, [lb + nu_lo, le + nu_hi) for H^H, or all N) times
+// F.lwc columns from an even column origin (or all M columns and the first two again) --
+// into LDS with 16-byte direct-to-LDS loads (buffer_load_dwordx4 ... lds: a wave fills 1 KiB,
+// 128 consecutive window elements, each lane two elements of one row), then every path's
+// gathers read the window: an element is fetched from memory once per strip instead of
+// once per path.  Window element (r, c) holds the source at row <row0 + r>_N, column
+// <col0 + c>_M, so a pair whose two sources straddle the row's wrap point is adjacent in
+// the window and needs no fix-up read.  The H^H coefficients R_p at the source columns
+// still come from the table in memory (with the fix-up for a straddling pair).
+// ---------------------------------------------------------------------------------------
+constexpr int kLdsRows = 8;   // output rows per thread chunk in the LDS-windowed gathers
+
+// Whether band [lb, le)'s window fits the frame's LDS window geometry (F.lwr x F.lwc) with
+// its current shift ranges (a path table made on the device may widen them).
+__device__ __forceinline__ bool lds_window_fits(const FrameDev& F, int lb, int le) {
+  const int band = le - lb, dnu = F.nu_hi - F.nu_lo;
+  const int wr = band + dnu >= F.N ? F.N : band + dnu;
+  if (wr > F.lwr) return false;
+  if (F.lwc >= F.M) return true;
+  int wc = 2 * strip_lanes(F.M >> 1, band, kRows) + (F.tau_hi - F.tau_lo) + 1;
+  wc += wc & 1;
+  return wc < F.M && wc <= F.lwc;
+}
+
+template <bool ADJ, class Pref, class Sink>
+__device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int le, const SrcBuf& src,
+                                                float2* lds_gen, Pref pref, Sink sink) {
+  const int M = F.M, N = F.N, P = F.P;
+  const int TX = strip_lanes(M >> 1, le - lb, kRows);   // band_apply_pairs's strip width
+  const int TY = kBlock / TX;
+  const int tx = threadIdx.x % TX;
+  const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.x / TX);
+  const bool act = ty < TY;
+  const int KC = 2 * TX;
+  const int nrows = (act && le - lb - ty > 0) ? (le - lb - ty + TY - 1) / TY : 0;
+  const int band = le - lb, dnu = F.nu_hi - F.nu_lo;
+  const bool full_rows = band + dnu >= N;
+  const int WR = full_rows ? N : band + dnu;
+  const int row0 = full_rows ? 0 : (ADJ ? lb + F.nu_lo : lb - F.nu_hi);
+  const int WC = F.lwc;                  // even; M + 2 when the window spans every column
+  const bool full_cols = WC >= M;
+  const int total = WR * WC;
+  const int nchunk = (total + 127) >> 7;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const uint32_t M8 = 8u * (uint32_t)M;
+  const KPairs paths = kpairs(F.paths);
+  const KPairs wtab_s = kpairs(F.wtab);
+  const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(F.rtab, (int64_t)P * M * 8);
+  const lptr<u64> win = (lptr<u64>)lds_gen;
+  for (int k0 = 0; k0 < M; k0 += KC) {
+    const int col0 = full_cols ? 0 : ((ADJ ? k0 + F.tau_lo : k0 - F.tau_hi) & ~1);
+    __syncthreads();   // the previous strip's window is no longer read
+    for (int c = wave; c < nchunk; c += kWaves) {
+      const int e = (c << 7) + 2 * lane;
+      if (e < total) {
+        const int r = e / WC, cc = e - r * WC;
+        int sr = row0 + r;
+        sr += sr < 0 ? N : 0;
+        sr -= sr >= N ? N : 0;
+        int sc = col0 + cc;
+        sc += sc < 0 ? M : 0;
+        sc -= sc >= M ? M : 0;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(src.r, (lptr<void>)(win + (c << 7)), 16,
+                                                 (uint32_t)(sr * M + sc) * 8u, 0, 0, 0);
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    const int k = k0 + 2 * tx;
+    if (nrows == 0 || k >= M) continue;
+    for (int j0 = 0; j0 < nrows; j0 += kLdsRows) {
+      int l[kLdsRows];
+      float2 wl[kLdsRows];
+      float2 acc0[kLdsRows], acc1[kLdsRows];
+      decltype(pref(0u)) pf[kLdsRows];
+#pragma unroll
+      for (int i = 0; i < kLdsRows; ++i) {
+        l[i] = lb + ty + min(j0 + i, nrows - 1) * TY;
+        wl[i] = wtab_s.f(l[i]);
+        acc0[i] = make_float2(0.f, 0.f);
+        acc1[i] = make_float2(0.f, 0.f);
+        pf[i] = pref((uint32_t)(l[i] * M + k));
+      }
+      for (int p = 0; p < P; ++p) {
+        const int2 tn = paths.i2(p);
+        const int K = ADJ ? k + tn.x : k - tn.x;   // source column of element 0 (unwrapped)
+        const bool lo0 = K < 0, hi0 = K >= M, lo1 = K + 1 < 0, hi1 = K + 1 >= M;
+        const int s0 = lo0 ? K + M : (hi0 ? K - M : K);
+        const bool split = s0 == M - 1;
+        float2 c0, c1;
+        unpack2(buf_ld4b(rtab, ADJ ? 8u * (uint32_t)s0 : 8u * (uint32_t)k, (uint32_t)p * M8),
+                c0, c1);
+        if (ADJ) {
+          if (__builtin_amdgcn_ballot_w64(split) != 0) {
+            const float2 cfx = __builtin_bit_cast(
+                float2, __builtin_amdgcn_raw_buffer_load_b64(rtab, 0u, (uint32_t)p * M8, 0));
+            if (split) c1 = cfx;
+          }
+          c0 = make_float2(c0.x, -c0.y);
+          c1 = make_float2(c1.x, -c1.y);
+        }
+        const int lc = full_cols ? s0 : K - col0;   // window column of element 0
+        const int sh = ADJ ? tn.y : -tn.y;
+        float2 e0[kLdsRows], e1[kLdsRows];
+#pragma unroll
+        for (int i = 0; i < kLdsRows; ++i) {
+          int lr = l[i] + sh;
+          if (full_rows) {
+            lr += lr < 0 ? N : 0;
+            lr -= lr >= N ? N : 0;
+          } else {
+            lr -= row0;
+          }
+          const lptr<u64> w = win + lr * WC + lc;
+          e0[i] = __builtin_bit_cast(float2, w[0]);
+          e1[i] = __builtin_bit_cast(float2, w[1]);
+        }
+        if (__builtin_amdgcn_ballot_w64(lo0 || hi0 || lo1 || hi1) != 0) {
+          float2 cw0 = c0, cw1 = c1;
+          if (!ADJ) {
+            const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
+            cw0 = cmulf(c0, make_float2(wn.x, hi0 ? -wn.y : wn.y));
+            cw1 = cmulf(c1, make_float2(wn.x, hi1 ? -wn.y : wn.y));
+          }
+#pragma unroll
+          for (int i = 0; i < kLdsRows; ++i) {
+            const float2 w0 = make_float2(wl[i].x, hi0 ? wl[i].y : -wl[i].y);
+            const float2 w1 = make_float2(wl[i].x, hi1 ? wl[i].y : -wl[i].y);
+            cmacf(acc0[i], (lo0 || hi0) ? cmulf(cw0, w0) : c0, e0[i]);
+            cmacf(acc1[i], (lo1 || hi1) ? cmulf(cw1, w1) : c1, e1[i]);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < kLdsRows; ++i) {
+            cmacf(acc0[i], c0, e0[i]);
+            cmacf(acc1[i], c1, e1[i]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kLdsRows; ++i)
+        if (j0 + i < nrows) sink((uint32_t)(l[i] * M + k), acc0[i], acc1[i], pf[i]);
+    }
+  }
+  __syncthreads();   // the window region is free for the caller
+}
+
 // band_apply with nothing to prefetch: sink(q, v)
 struct NoPref {
   __device__ __forceinline__ NoPre operator()(uint32_t) const { return NoPre{}; }
@@ -1206,51 +1362,83 @@ __device__ __forceinline__ void staged_apply(const FrameDev& F, int lb, int le, 
   }
 }
 
-// Band application of H / H^H: staged through LDS (STAGED: frames with a window
-// geometry), gathered straight from memory otherwise.  out.pre(q) issues the loads output q needs
-// besides the source; out.put(q, v, pre, own) receives it with own[] = the source
-// vectors' elements at q.
-template <bool ADJ, int SD, bool STAGED, int R = kRows, int UP = kPaths, class Src,
-          class Out>
+// Band application of H / H^H.  GM says where the gathers read from: memory (kGmDirect),
+// LDS windows of the staged geometry (kGmStaged: frames with F.skc > 0), or the windowed
+// paired gathers (kGmLds: frames with F.lpk > 0, else memory).  out.pre(q) issues the
+// loads output q needs besides the source; out.put(q, v, pre, own) receives it with own[] =
+// the source vectors' elements at q.
+constexpr int kGmDirect = 0, kGmStaged = 1, kGmLds = 2;
+
+template <bool ADJ, int SD, int GM, int R = kRows, int UP = kPaths, class Src, class Out>
 __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, float2* lds,
                                            const Src& src, const Out& out) {
-  if constexpr (STAGED && SD == kDNone && Src::kStageable) {
+  if constexpr (GM == kGmStaged && SD == kDNone && Src::kStageable) {
     staged_apply<ADJ>(F, lb, le, lds, src, out);
-  } else {
-    if constexpr (SD == kDNone && Src::kPairs) {
-      if (pairs_ok(F)) {
-        struct PreOwn2 {
-          typename Out::Pre2 pre;
-          float2 own0[Src::kNV], own1[Src::kNV];
-        };
-        band_apply_pairs<R, (UP < kPairPaths ? UP : kPairPaths), ADJ>(
-            F, lb, le, src,
-            [&](uint32_t u) {
-              PreOwn2 po;
-              po.pre = out.pre2(u);
-              if (Out::kOwn) src.own2(u, po.own0, po.own1);
-              return po;
-            },
-            [&](uint32_t q, float2 v0, float2 v1, const PreOwn2& po) {
-              out.put2(q, v0, v1, po.pre, po.own0, po.own1);
+    return;
+  }
+  if constexpr (GM == kGmLds && SD == kDNone) {
+    if constexpr (std::is_same<Src, SrcBuf>::value) {
+      if (pairs_ok(F) && lds_window_fits(F, lb, le)) {   // same bits as the direct pairs
+        static_assert(!Out::kOwn, "the windowed pairs pass no own elements");
+        lds_apply_pairs<ADJ>(
+            F, lb, le, src, lds, [&](uint32_t u) { return out.pre2(u); },
+            [&](uint32_t q, float2 v0, float2 v1, const typename Out::Pre2& pr) {
+              out.put2(q, v0, v1, pr, nullptr, nullptr);
             });
         return;
       }
     }
-    struct PreOwn {
+    // otherwise (not pairs-aligned, a window that does not fit, or a source the window
+    // does not take): gathered straight from memory one element per lane (this kind keeps
+    // the registers of the paired gathers for the window's form)
+    struct PreOwnL {
       typename Out::Pre pre;
       float2 own[Src::kNV];
     };
     band_apply<R, UP, ADJ, SD>(
         F, lb, le, src,
         [&](uint32_t u) {
-          PreOwn po;
+          PreOwnL po;
           po.pre = out.pre(u);
           if (Out::kOwn) src.own(u, po.own);
           return po;
         },
-        [&](int q, float2 v, const PreOwn& po) { out.put((uint32_t)q, v, po.pre, po.own); });
+        [&](int q, float2 v, const PreOwnL& po) { out.put((uint32_t)q, v, po.pre, po.own); });
+    return;
   }
+  if constexpr (SD == kDNone && Src::kPairs) {
+    if (pairs_ok(F)) {
+      struct PreOwn2 {
+        typename Out::Pre2 pre;
+        float2 own0[Src::kNV], own1[Src::kNV];
+      };
+      band_apply_pairs<R, (UP < kPairPaths ? UP : kPairPaths), ADJ>(
+          F, lb, le, src,
+          [&](uint32_t u) {
+            PreOwn2 po;
+            po.pre = out.pre2(u);
+            if (Out::kOwn) src.own2(u, po.own0, po.own1);
+            return po;
+          },
+          [&](uint32_t q, float2 v0, float2 v1, const PreOwn2& po) {
+            out.put2(q, v0, v1, po.pre, po.own0, po.own1);
+          });
+      return;
+    }
+  }
+  struct PreOwn {
+    typename Out::Pre pre;
+    float2 own[Src::kNV];
+  };
+  band_apply<R, UP, ADJ, SD>(
+      F, lb, le, src,
+      [&](uint32_t u) {
+        PreOwn po;
+        po.pre = out.pre(u);
+        if (Out::kOwn) src.own(u, po.own);
+        return po;
+      },
+      [&](int q, float2 v, const PreOwn& po) { out.put((uint32_t)q, v, po.pre, po.own); });
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1548,9 +1736,10 @@ struct LaunchCtx {
   int xcd_local;     // barrier coherence mode (see frame_barrier)
 };
 
-// FDIR: the H pass forms p' = c + beta p inside its gathers (direct-fd kind).
-template <int SD, bool STAGED, bool FDIR = false>
-__device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
+// GM: where the gathers read from (kGmDirect, kGmStaged, kGmLds).  FDIR: the H pass forms
+// p' = c + beta p inside its gathers (direct-fd kind).
+template <int SD, int GM, bool FDIR = false>
+__device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                         const LaunchCtx& L, float* red, int* sflag, float2* lds) {
   // the stored-table reads leave fewer registers for gathers in flight
   constexpr int RR = SD != kDNone ? 2 : kRows;
@@ -1604,9 +1793,9 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     float acc = 0.f;
     const OutInit out{cv, cvec(F.p0, E), xv, &acc};
     if (V.ybf16)
-      apply_band<true, SD, STAGED, RR>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, out);
+      apply_band<true, SD, GM, RR>(F, lb, le, lds, SrcBf16{buf_rsrc(V.y, E * 4)}, out);
     else
-      apply_band<true, SD, STAGED, RR>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, out);
+      apply_band<true, SD, GM, RR>(F, lb, le, lds, SrcBuf{buf_rsrc(V.y, E * 8)}, out);
     const float bs = block_sum(acc, red);
     if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
     if (!bar()) return fail_timeout();
@@ -1665,14 +1854,14 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
     const float al = s.alpha, be = (s.pending & 2) ? s.beta : 0.f;
 
     // ---- A: deferred updates of the band, t = H p ----
-    if constexpr (STAGED) {
+    if constexpr (GM == kGmStaged) {
       // c and the old p are staged together; p' = c + beta p is formed from the windows
-      apply_band<false, SD, true, RR>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
-                                      OutA{tv, pnv, xv, al, be, xp});
+      apply_band<false, SD, kGmStaged, RR>(F, lb, le, lds, SrcDir{cv.r, pov.r, be},
+                                           OutA{tv, pnv, xv, al, be, xp});
     } else if constexpr (FDIR) {
       // p' = c + beta p_old formed from both vectors at every gather (two loads each: fewer
       // paths in flight), stored once for the own rows with x += alpha p_old
-      apply_band<false, SD, false, kFdRows, kFdPaths>(F, lb, le, lds,
+      apply_band<false, SD, kGmDirect, kFdRows, kFdPaths>(F, lb, le, lds,
                                                          SrcDir{cv.r, pov.r, be},
                                                          OutA{tv, pnv, xv, al, be, xp});
     } else {
@@ -1717,18 +1906,18 @@ __device__ void cg_item(const FrameDev& F, const WorkItem& wi, int budget, const
         }
       }
       if (!halo(rd_h)) return fail_timeout();
-      // A2: t = H p' (one load per gather)
+      // A2: t = H p' (one load per gather, or through LDS windows)
       if (kNtT && F.stream_t)
-        apply_band<false, SD, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<true>{tv});
+        apply_band<false, SD, GM, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<true>{tv});
       else
-        apply_band<false, SD, false, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<false>{tv});
+        apply_band<false, SD, GM, RR>(F, lb, le, lds, SrcBuf{pnv.r}, OutStore<false>{tv});
     }
     if (!halo(rd_hh)) return fail_timeout();
 
     // ---- B: a = H^H t + lam p, partial Re(p^H a) ----
     {
       float acc = 0.f;
-      apply_band<true, SD, STAGED, RR>(F, lb, le, lds, SrcBuf{tv.r}, OutB{av, pnv, lam, &acc});
+      apply_band<true, SD, GM, RR>(F, lb, le, lds, SrcBuf{tv.r}, OutB{av, pnv, lam, &acc});
       const float bs = block_sum(acc, red);
       if (threadIdx.x == 0) F.part_pa[wi.tile] = bs;
     }
@@ -2171,8 +2360,9 @@ __device__ __forceinline__ int xcc_id() {
 #endif
 constexpr int fused_min_waves(int kind) {
   return kind == kKindWindowed ? OTFS_WIN_MIN_WAVES
-                               : ((kind == kKindDirect || kind == kKindDirectFD) ? OTFS_FUSED_MIN_WAVES
-                                                                                : OTFS_LDS_MIN_WAVES);
+                               : ((kind == kKindDirect || kind == kKindDirectFD || kind == kKindLds)
+                                      ? OTFS_FUSED_MIN_WAVES
+                                      : OTFS_LDS_MIN_WAVES);
 }
 template <int SD, int KIND>
 __global__ __launch_bounds__(kBlock, fused_min_waves(KIND)) void k_cg_fused(const FrameDev* __restrict__ frames,
@@ -2212,7 +2402,8 @@ __global__ __launch_bounds__(kBlock, fused_min_waves(KIND)) void k_cg_fused(cons
     else if constexpr (KIND == kKindWindowed)
       cg_item_win(F, wi, budget, B, L, red, &sflag, stage_lds);
     else
-      cg_item<SD, KIND == kKindStaged, KIND == kKindDirectFD>(F, wi, budget, B, L, red, &sflag,
+      cg_item<SD, KIND == kKindStaged ? kGmStaged : (KIND == kKindLds ? kGmLds : kGmDirect),
+              KIND == kKindDirectFD>(F, wi, budget, B, L, red, &sflag,
                                                               stage_lds);
     __syncthreads();
   }
@@ -2322,11 +2513,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ f
     win_apply_any<ADJ>(F, wi.k_begin, stage_lds, src_vec(in + F.off, E), NoPref{},
                        [&](int q, float2 v, NoPre) { dst.st((uint32_t)q, v); });
   else if (SD == kDNone && F.skc > 0)
-    apply_band<ADJ, SD, true>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
-                              OutStore<>{dst});
+    apply_band<ADJ, SD, kGmStaged>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
+                                   OutStore<>{dst});
   else
-    apply_band<ADJ, SD, false>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
-                               OutStore<>{dst});
+    apply_band<ADJ, SD, kGmDirect>(F, wi.l_begin, wi.l_end, stage_lds, src_vec(in + F.off, E),
+                                   OutStore<>{dst});
 }
 
 __global__ void k_reset(const FrameDev* __restrict__ frames, int nframes, unsigned* abort_flag,
@@ -2847,6 +3038,7 @@ static const void* fused_fn(int kind, int sd) {
     case kKindWindowed: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindWindowed>);
     case kKindDirectFD: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindDirectFD>);
     case kKindStaged: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindStaged>);
+    case kKindLds: return reinterpret_cast<const void*>(&k_cg_fused<kDNone, kKindLds>);
     default: break;
   }
   if (sd == kDBf16) return reinterpret_cast<const void*>(&k_cg_fused<kDBf16, kKindDirect>);
@@ -2861,7 +3053,7 @@ hipError_t launch_cg_fused(int kind, int sd, const FrameDev* frames, const WorkI
   if (grid <= 0) return hipSuccess;
   if (kind != kKindDirect && sd != kDNone) return hipErrorInvalidValue;
   LaunchCtx L{abort_flag, wait_ticks(wait_us), xcd_local ? 1 : 0};
-  if (kind == kKindWindowed || kind == kKindStaged) {
+  if (kind == kKindWindowed || kind == kKindStaged || kind == kKindLds) {
     hipError_t e = hipFuncSetAttribute(fused_fn(kind, sd), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        lds_bytes);
     if (e != hipSuccess) return e;
@@ -2878,6 +3070,9 @@ hipError_t launch_cg_fused(int kind, int sd, const FrameDev* frames, const WorkI
       break;
     case kKindStaged:
       launch_fused_t<kDNone, kKindStaged>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
+      break;
+    case kKindLds:
+      launch_fused_t<kDNone, kKindLds>(frames, items, qitems, qrange, qhead, ngroups, grid, budget, bases, L, lds_bytes, s);
       break;
     default:
       if (sd == kDBf16)

@@ -15,6 +15,21 @@ namespace otfs {
 #endif
 constexpr int kBlock = OTFS_BLOCK;   // threads per workgroup of every kernel
 constexpr int kWaves = kBlock / 64;  // wave64
+#ifndef OTFS_ROWS
+#define OTFS_ROWS 4
+#endif
+#ifndef OTFS_STRIP_LANES
+#define OTFS_STRIP_LANES 64
+#endif
+// Lanes across one row of a band in the gather passes: OTFS_STRIP_LANES (a multiple of 64),
+// doubled while the band is too short to give every thread OTFS_ROWS rows, at most a
+// workgroup, and at most `width` (the lanes a whole row needs).  The host uses it to size
+// the LDS windows of the windowed paired gathers.
+__host__ __device__ inline int strip_lanes_rule(int width, int band_rows) {
+  int t = OTFS_STRIP_LANES;
+  while (t < kBlock && t * band_rows < kBlock * OTFS_ROWS) t <<= 1;
+  return width < t ? width : t;
+}
 
 // Coefficients D_{p,q}: synthesised on the fly from the delay-ramp and wrap tables, or read
 // from a stored P x E table (the SS representation of Eq. ds_repr) in bf16 or complex64.
@@ -79,6 +94,9 @@ struct FrameDev {
   // LDS staging of the gathers (0 = gather straight from memory): column chunk and row
   // sub-band of one staged block, and the delay / Doppler shift ranges of the paths
   int32_t skc, ssb, swin;   // swin: LDS elements per staged vector (window, padded)
+  // LDS-windowed paired gathers (staged kind, 0 = off): strip columns of the window's
+  // owner strips and the window's width in columns (even; M + 2 when it spans the rows)
+  int32_t lpk, lwc, lwr;   // ... and its height in rows (for the tallest band)
   int32_t tau_lo, tau_hi, nu_lo, nu_hi;
   // 1: a one-workgroup frame whose five CG vectors (x, c, p, t, a) live in LDS for the
   // whole solve (y read once, x written once)
@@ -163,7 +181,7 @@ hipError_t launch_step_reset(const FrameDev* frames, int nframes, unsigned* abor
 // whose direct frames all have P <= kFusedDirMaxPaths)
 // windowed: frames tiled into strips whose gathers stream source rows through an LDS ring
 constexpr int kKindDirect = 0, kKindStaged = 1, kKindResident = 2, kKindDirectFD = 3,
-              kKindWindowed = 4, kKinds = 5;
+              kKindWindowed = 4, kKindLds = 5, kKinds = 6;
 #ifndef OTFS_FUSED_DIR_MAX_PATHS
 #define OTFS_FUSED_DIR_MAX_PATHS 8
 #endif

@@ -50,6 +50,7 @@ otfs_status validate_opts(const otfs_cg_opts* o, otfs_cg_opts* out) {
     return fail(OTFS_E_INVAL, "rel_tol must be finite and >= 0");
   if (d.refresh_every < 0) return fail(OTFS_E_INVAL, "refresh_every must be >= 0");
   const uint32_t known = OTFS_D_STORED_BF16 | OTFS_Y_BF16 | OTFS_USE_GRAPH | OTFS_TIME_KERNEL |
+                         OTFS_LDS_GATHER |
                          OTFS_AGENT_BARRIER | OTFS_NO_LDS_RESIDENT | OTFS_SPLIT_DIRECTION |
                          OTFS_D_STORED_C64;
   if (d.flags & ~known) return fail(OTFS_E_INVAL, "unknown flag bits 0x%x", d.flags & ~known);
@@ -160,6 +161,9 @@ void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const 
   d->skc = geo.skc;
   d->ssb = geo.ssb;
   d->swin = geo.swin;
+  d->lpk = geo.lpk;
+  d->lwc = geo.lwc;
+  d->lwr = geo.lwr;
   d->tau_lo = geo.tau_lo;
   d->tau_hi = geo.tau_hi;
   d->nu_lo = geo.nu_lo;
@@ -171,11 +175,41 @@ void frame_scalars(const HostFrame& fr, const otfs_cg_opts& o, int tiles, const 
   d->pcap = fr.P;
 }
 
+// Window of the LDS-windowed paired gathers for a frame cut into `tiles` row bands (of
+// floor(N / tiles) or ceil(N / tiles) rows): frames whose rows split into 16-byte pairs (M a
+// multiple of 128); the strip width is the gather rule's widest over the two band heights,
+// the window width covers a strip, the delay range and an even origin, the height the
+// tallest band and the Doppler range.  Returns the window's bytes, 0 (geometry untouched)
+// if it does not fit the LDS budget.
+int lds_pair_geometry(const HostFrame& f, int tiles, int budget_bytes, FrameDev* geo) {
+  if (f.M % 128 != 0 || tiles < 1) return 0;
+  const int dtau = geo->tau_hi - geo->tau_lo, dnu = geo->nu_hi - geo->nu_lo;
+  const int band_lo = f.N / tiles, band_rows = (f.N + tiles - 1) / tiles;
+  int kc = 0;
+  for (int b : {band_lo, band_rows})
+    kc = std::max(kc, 2 * strip_lanes_rule(f.M / 2, std::max(1, b)));
+  int wc = kc + dtau + 1;
+  wc += wc & 1;
+  if (wc >= f.M) wc = f.M + 2;
+  const int wr = band_rows + dnu >= f.N ? f.N : band_rows + dnu;
+  const int64_t bytes = (int64_t)wr * wc * (int64_t)sizeof(float2);
+  if (bytes > budget_bytes) return 0;
+  geo->lpk = kc;
+  geo->lwc = wc;
+  geo->lwr = wr;
+  return (int)bytes;
+}
+
 int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opts& o,
                  int budget_bytes, FrameDev* geo) {
   std::memset(geo, 0, sizeof(FrameDev));
   const int64_t E = (int64_t)f.M * f.N;
   const bool stored = stored_mode(o.flags) != kDNone;
+  if ((o.flags & OTFS_LDS_GATHER) && !stored && tiles > 1) {
+    stage_geometry(f, band_rows, 0, geo);   // shift ranges
+    const int b = lds_pair_geometry(f, tiles, kLdsGatherBytes, geo);
+    if (b > 0) return b;
+  }
   if (tiles == 1 && !stored && o.refresh_every == 0 && !(o.flags & OTFS_NO_LDS_RESIDENT) &&
       E * kResidentVecs * (int64_t)sizeof(float2) <= kResidentBytes) {
     stage_geometry(f, band_rows, 0, geo);   // shift ranges only; no staging
@@ -192,6 +226,7 @@ int lds_geometry(const HostFrame& f, int tiles, int band_rows, const otfs_cg_opt
 
 int frame_kind(const FrameDev& geo) {
   if (geo.win_w > 0) return kKindWindowed;
+  if (geo.lpk > 0) return kKindLds;
   return geo.resident ? kKindResident : (geo.skc > 0 ? kKindStaged : kKindDirect);
 }
 
@@ -199,6 +234,7 @@ int frame_lds_bytes(const HostFrame& f, const FrameDev& geo) {
   if (geo.win_w > 0)
     return win_lds_bytes(geo.win_w, geo.win_rc, geo.tau_hi - geo.tau_lo, geo.nu_hi - geo.nu_lo);
   if (geo.resident) return (int)((int64_t)f.M * f.N * kResidentVecs * (int64_t)sizeof(float2));
+  if (geo.lpk > 0) return geo.lwr * geo.lwc * (int)sizeof(float2);
   if (geo.skc > 0) return kStageVecs * geo.swin * (int)sizeof(float2);
   return 0;
 }
@@ -636,7 +672,7 @@ extern "C" otfs_status otfs_plan_info(const otfs_plan_t* plan, otfs_plan_info_t*
   info->staged_frames = 0;
   info->resident_frames = 0;
   for (const FrameDev& d : plan->h_frames) {
-    info->staged_frames += d.skc > 0 ? 1 : 0;
+    info->staged_frames += (d.skc > 0 || d.lpk > 0) ? 1 : 0;
     info->resident_frames += d.resident ? 1 : 0;
   }
   return OTFS_OK;

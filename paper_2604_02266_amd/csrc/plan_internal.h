@@ -60,6 +60,9 @@ void make_tiles(const std::vector<HostFrame>& frames, int tile_elems, std::vecto
 // chunk of rc rows, or 0 when the frame does not meet the form's limits.
 int window_width(const HostFrame& f, int w, int rc);
 constexpr int kMaxLdsBytes = 160 * 1024;
+// LDS of the windowed paired gathers' window (the workgroup's static LDS stays below 1 KiB)
+constexpr int kLdsGatherBytes = kMaxLdsBytes - 1024;
+int lds_pair_geometry(const HostFrame& f, int tiles, int budget_bytes, FrameDev* geo);
 // Work queues of the fused kernel.  ngroups groups (one per XCD in XCD-local mode, else
 // one); every frame's tiles go, consecutively, to one group; groups are balanced by work.
 // per_group_cap: workgroups one group can hold resident.  Returns false if some frame has

@@ -67,10 +67,10 @@ def test_invalid_options_are_rejected():
         assert ei.value.status == otfs.E_INVAL and msg in str(ei.value)
     # every documented flag is accepted
     for f in (otfs.NO_LDS_RESIDENT, otfs.SPLIT_DIRECTION, otfs.AGENT_BARRIER,
-              otfs.TIME_KERNEL, otfs.D_STORED_C64, otfs.D_STORED_BF16):
+              otfs.TIME_KERNEL, otfs.D_STORED_C64, otfs.D_STORED_BF16, otfs.LDS_GATHER):
         _plan(fr, flags=f)
     with pytest.raises(otfs.OtfsError):
-        _plan(fr, flags=1 << 8)
+        _plan(fr, flags=1 << 9)
     # the two stored tables exclude each other
     with pytest.raises(otfs.OtfsError) as ei:
         _plan(fr, flags=otfs.D_STORED_C64 | otfs.D_STORED_BF16)
