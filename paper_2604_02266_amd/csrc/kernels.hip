@@ -228,14 +228,6 @@ struct SrcLds {   // complex64 vector in LDS
   }
   __device__ __forceinline__ float2 value(Raw x) const { return x; }
 };
-struct SrcC128 {  // complex128 vector (16 B per element; offsets given for complex64)
-  __amdgpu_buffer_rsrc_t r;
-  using Raw = u32x4;
-  __device__ __forceinline__ Raw load_b(uint32_t vb, uint32_t sb) const {
-    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, 2u * vb, 2u * sb, 0));
-  }
-  __device__ __forceinline__ double2 value(Raw v) const { return __builtin_bit_cast(double2, v); }
-};
 
 // Arithmetic of a band application: FP32 (the CG passes) or FP64 (the true-residual
 // refresh), each with the delay-ramp and wrap tables of its precision.
@@ -1092,9 +1084,19 @@ __device__ __forceinline__ bool lds_window_fits(const FrameDev& F, int lb, int l
   return wc < F.M && wc <= F.lwc;
 }
 
-template <bool ADJ, class Pref, class Sink>
+template <class C>
+__device__ __forceinline__ C cplx(decltype(C{}.x) x, decltype(C{}.x) y) {
+  return C{x, y};
+}
+
+// A: the arithmetic (ArithF32 for the CG passes; ArithF64 for the true-residual refresh,
+// whose sums and coefficients are FP64 while the window holds the FP32 source).
+template <bool ADJ, class A, class Pref, class Sink>
 __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int le, const SrcBuf& src,
-                                                float2* lds_gen, Pref pref, Sink sink) {
+                                                float2* lds_gen, Pref pref, Sink sink, A = A{}) {
+  using C = typename A::C;
+  constexpr bool F32 = std::is_same<A, ArithF32>::value;
+  constexpr uint32_t TS = A::kTabBytes / 8u;   // table entry / 8 bytes
   const int M = F.M, N = F.N, P = F.P;
   const int TX = strip_lanes(M >> 1, le - lb, kRows);   // band_apply_pairs's strip width
   const int TY = kBlock / TX;
@@ -1114,8 +1116,8 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const uint32_t M8 = 8u * (uint32_t)M;
   const KPairs paths = kpairs(F.paths);
-  const KPairs wtab_s = kpairs(F.wtab);
-  const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(F.rtab, (int64_t)P * M * 8);
+  const void* wt = A::wtab(F);
+  const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(A::rtab(F), (int64_t)P * M * A::kTabBytes);
   const lptr<u64> win = (lptr<u64>)lds_gen;
   for (int k0 = 0; k0 < M; k0 += KC) {
     const int col0 = full_cols ? 0 : ((ADJ ? k0 + F.tau_lo : k0 - F.tau_hi) & ~1);
@@ -1140,15 +1142,15 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
     if (nrows == 0 || k >= M) continue;
     for (int j0 = 0; j0 < nrows; j0 += kLdsRows) {
       int l[kLdsRows];
-      float2 wl[kLdsRows];
-      float2 acc0[kLdsRows], acc1[kLdsRows];
+      C wl[kLdsRows];
+      C acc0[kLdsRows], acc1[kLdsRows];
       decltype(pref(0u)) pf[kLdsRows];
 #pragma unroll
       for (int i = 0; i < kLdsRows; ++i) {
         l[i] = lb + ty + min(j0 + i, nrows - 1) * TY;
-        wl[i] = wtab_s.f(l[i]);
-        acc0[i] = make_float2(0.f, 0.f);
-        acc1[i] = make_float2(0.f, 0.f);
+        wl[i] = A::tab_s(wt, l[i]);
+        acc0[i] = A::zero();
+        acc1[i] = A::zero();
         pf[i] = pref((uint32_t)(l[i] * M + k));
       }
       for (int p = 0; p < P; ++p) {
@@ -1157,21 +1159,27 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
         const bool lo0 = K < 0, hi0 = K >= M, lo1 = K + 1 < 0, hi1 = K + 1 >= M;
         const int s0 = lo0 ? K + M : (hi0 ? K - M : K);
         const bool split = s0 == M - 1;
-        float2 c0, c1;
-        unpack2(buf_ld4b(rtab, ADJ ? 8u * (uint32_t)s0 : 8u * (uint32_t)k, (uint32_t)p * M8),
-                c0, c1);
-        if (ADJ) {
-          if (__builtin_amdgcn_ballot_w64(split) != 0) {
+        C c0, c1;
+        if constexpr (F32) {
+          unpack2(buf_ld4b(rtab, ADJ ? 8u * (uint32_t)s0 : 8u * (uint32_t)k, (uint32_t)p * M8),
+                  c0, c1);
+          if (ADJ && __builtin_amdgcn_ballot_w64(split) != 0) {
             const float2 cfx = __builtin_bit_cast(
                 float2, __builtin_amdgcn_raw_buffer_load_b64(rtab, 0u, (uint32_t)p * M8, 0));
             if (split) c1 = cfx;
           }
-          c0 = make_float2(c0.x, -c0.y);
-          c1 = make_float2(c1.x, -c1.y);
+        } else {   // one 16-byte entry per column
+          const uint32_t k1 = ADJ ? (split ? 0u : (uint32_t)s0 + 1u) : (uint32_t)k + 1u;
+          c0 = A::tab(rtab, TS * 8u * (ADJ ? (uint32_t)s0 : (uint32_t)k), TS * (uint32_t)p * M8);
+          c1 = A::tab(rtab, TS * 8u * k1, TS * (uint32_t)p * M8);
+        }
+        if (ADJ) {
+          c0 = A::conj(c0);
+          c1 = A::conj(c1);
         }
         const int lc = full_cols ? s0 : K - col0;   // window column of element 0
         const int sh = ADJ ? tn.y : -tn.y;
-        float2 e0[kLdsRows], e1[kLdsRows];
+        C e0[kLdsRows], e1[kLdsRows];
 #pragma unroll
         for (int i = 0; i < kLdsRows; ++i) {
           int lr = l[i] + sh;
@@ -1182,28 +1190,28 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
             lr -= row0;
           }
           const lptr<u64> w = win + lr * WC + lc;
-          e0[i] = __builtin_bit_cast(float2, w[0]);
-          e1[i] = __builtin_bit_cast(float2, w[1]);
+          e0[i] = A::from(__builtin_bit_cast(float2, w[0]));
+          e1[i] = A::from(__builtin_bit_cast(float2, w[1]));
         }
         if (__builtin_amdgcn_ballot_w64(lo0 || hi0 || lo1 || hi1) != 0) {
-          float2 cw0 = c0, cw1 = c1;
+          C cw0 = c0, cw1 = c1;
           if (!ADJ) {
-            const float2 wn = wtab_s.f(tn.y < 0 ? tn.y + N : tn.y);
-            cw0 = cmulf(c0, make_float2(wn.x, hi0 ? -wn.y : wn.y));
-            cw1 = cmulf(c1, make_float2(wn.x, hi1 ? -wn.y : wn.y));
+            const C wn = A::tab_s(wt, tn.y < 0 ? tn.y + N : tn.y);
+            cw0 = A::mul(c0, cplx<C>(wn.x, hi0 ? -wn.y : wn.y));
+            cw1 = A::mul(c1, cplx<C>(wn.x, hi1 ? -wn.y : wn.y));
           }
 #pragma unroll
           for (int i = 0; i < kLdsRows; ++i) {
-            const float2 w0 = make_float2(wl[i].x, hi0 ? wl[i].y : -wl[i].y);
-            const float2 w1 = make_float2(wl[i].x, hi1 ? wl[i].y : -wl[i].y);
-            cmacf(acc0[i], (lo0 || hi0) ? cmulf(cw0, w0) : c0, e0[i]);
-            cmacf(acc1[i], (lo1 || hi1) ? cmulf(cw1, w1) : c1, e1[i]);
+            const C w0 = cplx<C>(wl[i].x, hi0 ? wl[i].y : -wl[i].y);
+            const C w1 = cplx<C>(wl[i].x, hi1 ? wl[i].y : -wl[i].y);
+            A::mac(acc0[i], (lo0 || hi0) ? A::mul(cw0, w0) : c0, e0[i]);
+            A::mac(acc1[i], (lo1 || hi1) ? A::mul(cw1, w1) : c1, e1[i]);
           }
         } else {
 #pragma unroll
           for (int i = 0; i < kLdsRows; ++i) {
-            cmacf(acc0[i], c0, e0[i]);
-            cmacf(acc1[i], c1, e1[i]);
+            A::mac(acc0[i], c0, e0[i]);
+            A::mac(acc1[i], c1, e1[i]);
           }
         }
       }
@@ -1380,7 +1388,7 @@ __device__ __forceinline__ void apply_band(const FrameDev& F, int lb, int le, fl
     if constexpr (std::is_same<Src, SrcBuf>::value) {
       if (pairs_ok(F) && lds_window_fits(F, lb, le)) {   // same bits as the direct pairs
         static_assert(!Out::kOwn, "the windowed pairs pass no own elements");
-        lds_apply_pairs<ADJ>(
+        lds_apply_pairs<ADJ, ArithF32>(
             F, lb, le, src, lds, [&](uint32_t u) { return out.pre2(u); },
             [&](uint32_t q, float2 v0, float2 v1, const typename Out::Pre2& pr) {
               out.put2(q, v0, v1, pr, nullptr, nullptr);
@@ -2435,9 +2443,18 @@ __global__ void k_xcc_probe(int* out) {
 // gathered data; one workgroup per CU leaves the registers for them
 constexpr int kRefRows = OTFS_REF_ROWS;
 constexpr int kRefPaths = 4;   // paths in flight together
+// The refresh of a tile reads its gathers through the LDS window of the windowed paired
+// gathers when the frame has that geometry, the window fits the launch's LDS and the
+// frame's vectors split into 16-byte pairs.
+__device__ __forceinline__ bool ref_lds_ok(const FrameDev& F, const WorkItem& wi, int lds_bytes) {
+  return F.lpk > 0 && pairs_ok(F) && F.lwr * F.lwc * (int)sizeof(float2) <= lds_bytes &&
+         lds_window_fits(F, wi.l_begin, wi.l_end);
+}
+
 __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_u(const FrameDev* __restrict__ frames,
                                                       const WorkItem* __restrict__ items, Bases B,
-                                                      unsigned* qhead, int nq) {
+                                                      unsigned* qhead, int nq, int lds_bytes) {
+  extern __shared__ float2 ref_lds[];
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const WorkItem wi = items[blockIdx.x];
   const FrameDev& F = frames[wi.frame];
@@ -2452,22 +2469,35 @@ __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_u(const 
   }
   const FrameVecs V = frame_vecs(F, B);
   const int64_t E = (int64_t)F.M * F.N;
-  const __amdgpu_buffer_rsrc_t u = buf_rsrc(F.u, E * 16);
-  band_apply<kRefRows, kRefPaths, false, kDNone>(
-      F, wi.l_begin, wi.l_end, SrcBuf{buf_rsrc(V.x, E * 8)},
-      [&](uint32_t q) { return load_y(V.y, q, V.ybf16); },
-      [&](int q, double2 v, float2 yv) {
-        const double2 r = make_double2((double)yv.x - v.x, (double)yv.y - v.y);
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), u, (uint32_t)q * 16u,
-                                               0, 0);
-      },
-      ArithF64{});
+  const CVec u = cvec(F.u, E);
+  const SrcBuf xs{buf_rsrc(V.x, E * 8)};
+  // the residual is formed in FP64 (no cancellation between y and Hx) and kept in FP32
+  auto res = [](float2 yv, double2 v) {
+    return make_float2((float)((double)yv.x - v.x), (float)((double)yv.y - v.y));
+  };
+  if (ref_lds_ok(F, wi, lds_bytes)) {
+    struct Y2 {
+      float2 a, b;
+    };
+    lds_apply_pairs<false, ArithF64>(
+        F, wi.l_begin, wi.l_end, xs, ref_lds,
+        [&](uint32_t q) { return Y2{load_y(V.y, q, V.ybf16), load_y(V.y, q + 1u, V.ybf16)}; },
+        [&](uint32_t q, double2 v0, double2 v1, const Y2& yv) {
+          u.st2(q, res(yv.a, v0), res(yv.b, v1));
+        });
+  } else {
+    band_apply<kRefRows, kRefPaths, false, kDNone>(
+        F, wi.l_begin, wi.l_end, xs, [&](uint32_t q) { return load_y(V.y, q, V.ybf16); },
+        [&](int q, double2 v, float2 yv) { u.st((uint32_t)q, res(yv, v)); }, ArithF64{});
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
 
 __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_c(const FrameDev* __restrict__ frames,
-                                                      const WorkItem* __restrict__ items, Bases B) {
+                                                      const WorkItem* __restrict__ items, Bases B,
+                                                      int lds_bytes) {
   __shared__ double redd[kWaves];
+  extern __shared__ float2 ref_lds[];
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const WorkItem wi = items[blockIdx.x];
   const FrameDev& F = frames[wi.frame];
@@ -2480,17 +2510,41 @@ __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_c(const 
   const double lam = (double)F.lam;
   const CVec cv = cvec(F.c, E), xv = cvec(V.x, E);
   double acc = 0.0;
-  band_apply<kRefRows, kRefPaths, true, kDNone>(
-      F, wi.l_begin, wi.l_end, SrcC128{buf_rsrc(F.u, E * 16)},
-      [&](uint32_t q) { return xv.ld(q); },
-      [&](int q, double2 v, float2 x) {
-        const float2 cf = make_float2((float)(v.x - lam * (double)x.x),
-                                      (float)(v.y - lam * (double)x.y));
-        cv.st((uint32_t)q, cf);
-        acc = fma((double)cf.x, (double)cf.x, acc);
-        acc = fma((double)cf.y, (double)cf.y, acc);
-      },
-      ArithF64{});
+  const SrcBuf us{buf_rsrc(F.u, E * 8)};
+  auto cval = [&](double2 v, float2 x) {
+    return make_float2((float)(v.x - lam * (double)x.x), (float)(v.y - lam * (double)x.y));
+  };
+  auto nrm = [&](float2 cf) {
+    acc = fma((double)cf.x, (double)cf.x, acc);
+    acc = fma((double)cf.y, (double)cf.y, acc);
+  };
+  if (ref_lds_ok(F, wi, lds_bytes)) {
+    struct X2 {
+      float2 a, b;
+    };
+    lds_apply_pairs<true, ArithF64>(
+        F, wi.l_begin, wi.l_end, us, ref_lds,
+        [&](uint32_t q) {
+          X2 r;
+          xv.ld2(q, r.a, r.b);
+          return r;
+        },
+        [&](uint32_t q, double2 v0, double2 v1, const X2& x) {
+          const float2 c0 = cval(v0, x.a), c1 = cval(v1, x.b);
+          cv.st2(q, c0, c1);
+          nrm(c0);
+          nrm(c1);
+        });
+  } else {
+    band_apply<kRefRows, kRefPaths, true, kDNone>(
+        F, wi.l_begin, wi.l_end, us, [&](uint32_t q) { return xv.ld(q); },
+        [&](int q, double2 v, float2 x) {
+          const float2 cf = cval(v, x);
+          cv.st((uint32_t)q, cf);
+          nrm(cf);
+        },
+        ArithF64{});
+  }
   const double bs = block_sum_d(acc, redd);
   if (threadIdx.x == 0) F.part_d[wi.tile] = bs;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -3086,11 +3140,20 @@ hipError_t launch_cg_fused(int kind, int sd, const FrameDev* frames, const WorkI
 }
 
 hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nitems, Bases bases,
-                          unsigned* qhead, int nq, hipStream_t s) {
-  if (nitems <= 0 || nq > kBlock) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_refresh_u, dim3(nitems), dim3(kBlock), 0, s, frames, items, bases, qhead,
-                     nq);
-  hipLaunchKernelGGL(k_refresh_c, dim3(nitems), dim3(kBlock), 0, s, frames, items, bases);
+                          unsigned* qhead, int nq, int lds_bytes, hipStream_t s) {
+  if (nitems <= 0 || nq > kBlock || lds_bytes < 0) return hipErrorInvalidValue;
+  if (lds_bytes > 0) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refresh_u),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refresh_c),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_refresh_u, dim3(nitems), dim3(kBlock), lds_bytes, s, frames, items, bases,
+                     qhead, nq, lds_bytes);
+  hipLaunchKernelGGL(k_refresh_c, dim3(nitems), dim3(kBlock), lds_bytes, s, frames, items, bases,
+                     lds_bytes);
   return hipGetLastError();
 }
 

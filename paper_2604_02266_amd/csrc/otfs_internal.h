@@ -68,7 +68,7 @@ struct FrameDev {
   float2* p1;
   float2* t;              // H p
   float2* a;              // H^H H p + lam p
-  double2* u;             // FP64 scratch of the residual refresh (nullable)
+  float2* u;              // the refresh's residual y - Hx, formed in FP64, kept in FP32 (nullable)
   const float2* rtab;     // P x M: R_p[k] = h_p e^{j 2 pi nu_p (k - tau_p) / (MN)}
   const float2* wtab;     // N: W[l] = e^{j 2 pi l / N}
   const double2* rtab64;  // FP64 copies of the two tables for the refresh (nullable)
@@ -199,8 +199,10 @@ int fused_blocks_per_cu(int kind, int sd, int lds_bytes);
 // nitems work items (one workgroup each): two launches, u = y - H x, then
 // c = H^H u - lam x with the FP64 partial norms in part_d.  Also clears every frame's
 // barrier and neighbour counters and the nq queue cursors for the next fused launch.
+// lds_bytes: dynamic LDS for the windows of frames with the windowed paired geometry (the
+// largest window of the windowed kind's launch; 0 = every frame gathers from memory).
 hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nitems, Bases bases,
-                          unsigned* qhead, int nq, hipStream_t s);
+                          unsigned* qhead, int nq, int lds_bytes, hipStream_t s);
 
 // Static scratch of the entry point that allocates nothing: kNoAllocBytes per device.
 // *ptr = its device address on `device`, which must be the current device (found once per

@@ -230,6 +230,13 @@ int frame_kind(const FrameDev& geo) {
   return geo.resident ? kKindResident : (geo.skc > 0 ? kKindStaged : kKindDirect);
 }
 
+int refresh_lds_bytes(const std::vector<KindLaunch>& launches) {
+  int b = 0;
+  for (const KindLaunch& L : launches)
+    if (L.kind == kKindLds) b = std::max(b, L.lds_bytes);
+  return b;
+}
+
 int frame_lds_bytes(const HostFrame& f, const FrameDev& geo) {
   if (geo.win_w > 0)
     return win_lds_bytes(geo.win_w, geo.win_rc, geo.tau_hi - geo.tau_lo, geo.nu_hi - geo.nu_lo);
@@ -571,7 +578,7 @@ void compute_layout(otfs_plan_t* pl) {
   L.p1 = take(Ep * sizeof(float2));
   L.t = take(Ep * sizeof(float2));
   L.a = take(Ep * sizeof(float2));
-  L.u = refresh ? take(Ep * sizeof(double2)) : 0;
+  L.u = refresh ? take(Ep * sizeof(float2)) : 0;
   L.dtab = sd == kDNone ? 0 : take(dt * (sd == kDC64 ? sizeof(float2) : sizeof(uint32_t)));
   L.total = std::max<size_t>(o, 256);
 }
@@ -785,7 +792,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
     d.p1 = reinterpret_cast<float2*>(base + L.p1) + eo;
     d.t = reinterpret_cast<float2*>(base + L.t) + eo;
     d.a = reinterpret_cast<float2*>(base + L.a) + eo;
-    d.u = refresh ? reinterpret_cast<double2*>(base + L.u) + eo : nullptr;
+    d.u = refresh ? reinterpret_cast<float2*>(base + L.u) + eo : nullptr;
     d.rtab = reinterpret_cast<const float2*>(base + L.rtab) + ro;
     d.wtab = reinterpret_cast<const float2*>(base + L.wtab) + wo;
     d.rtab64 = refresh ? reinterpret_cast<const double2*>(base + L.rtab64) + ro : nullptr;
@@ -921,7 +928,7 @@ static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s
     }
     if (seg + 1 < nseg) {
       e = launch_refresh(plan->d_frames, plan->d_items, (int)plan->items.size(), B,
-                         plan->d_qhead, kKinds * kMaxGroups, s);
+                         plan->d_qhead, kKinds * kMaxGroups, refresh_lds_bytes(plan->launches), s);
       if (e != hipSuccess) return e;
     }
   }
@@ -1047,7 +1054,7 @@ extern "C" otfs_status otfs_lmmse_cg_trace(otfs_plan_t* plan, const void* y, voi
     if (it > 0) {   // counters and cursors of the next one-iteration launch
       e = plan->opts.refresh_every > 0
               ? launch_refresh(plan->d_frames, plan->d_items, ni, B, plan->d_qhead,
-                               kKinds * kMaxGroups, s)
+                               kKinds * kMaxGroups, refresh_lds_bytes(plan->launches), s)
               : launch_step_reset(plan->d_frames, nf, plan->d_abort, plan->d_qhead,
                                   kKinds * kMaxGroups, s);
     }

@@ -99,6 +99,9 @@ struct KindLaunch {
   int lds_bytes = 0;
   int qbase = 0;
 };
+// The refresh launches' LDS: the windowed paired kind's window bytes among `launches` (0
+// when it has none).
+int refresh_lds_bytes(const std::vector<KindLaunch>& launches);
 int frame_kind(const FrameDev& geo);
 // LDS a frame of this kind and geometry needs in its launch.
 int frame_lds_bytes(const HostFrame& f, const FrameDev& geo);

@@ -120,7 +120,7 @@ SlotLayout slot_layout(const HostFrame& f, int tiles, bool refresh) {
   L.p1 = take(E * 8);
   L.t = take(E * 8);
   L.a = take(E * 8);
-  L.u = refresh ? take(E * 16) : 0;
+  L.u = refresh ? take(E * 8) : 0;
   L.part_pa = take((size_t)tiles * 4);
   L.part_cc = take((size_t)tiles * 4);
   L.part_d = take((size_t)tiles * 8);
@@ -367,7 +367,7 @@ void build_frame_dev(otfs_server* S, Request* r) {
   d.p1 = reinterpret_cast<float2*>(base + L.p1);
   d.t = reinterpret_cast<float2*>(base + L.t);
   d.a = reinterpret_cast<float2*>(base + L.a);
-  d.u = refresh ? reinterpret_cast<double2*>(base + L.u) : nullptr;
+  d.u = refresh ? reinterpret_cast<float2*>(base + L.u) : nullptr;
   d.rtab = reinterpret_cast<const float2*>(base + L.rtab);
   d.wtab = reinterpret_cast<const float2*>(base + L.wtab);
   d.rtab64 = refresh ? reinterpret_cast<const double2*>(base + L.rtab64) : nullptr;
@@ -473,7 +473,7 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   // the next step resumes them
   if (e == hipSuccess && S->opts.refresh_every > 0)
     e = launch_refresh(dframes, reinterpret_cast<const WorkItem*>(P + C.items), nitems,
-                       B, qhead, kKinds * kMaxGroups, S->s);
+                       B, qhead, kKinds * kMaxGroups, refresh_lds_bytes(launches), S->s);
   if (e == hipSuccess) e = hipEventRecord(S->ev_end, S->s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(H + C.stats, dstats, (size_t)n * sizeof(otfs_frame_stats),
