@@ -235,6 +235,8 @@ def solve_block(otfs, O, np, torch, name, frames, ys, refs, steps, warmup, refre
     ser = float(np.mean(dh.astype(np.int64) != sym_tx))
     parity = check_against_oracle(O, np, frames, offs, xh, dh, refs)
     lb = launch_bytes(specs, iters, refresh)
+    lds = bool(plan.tuned and plan.tuned.get("lds_gather"))
+    kname = "k_cg_fused<0, 5> (LDS-windowed paired gathers)" if lds else "k_cg_fused"
     kms, solve_ms = kernel_times(otfs, specs, y, xhat, dec, stats, steps, refresh, torch)
     kavg = float(np.mean(kms))
     achieved = lb / (kavg * 1e-3) / 1e9
@@ -254,7 +256,7 @@ def solve_block(otfs, O, np, torch, name, frames, ys, refs, steps, warmup, refre
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": load_traffic(name, refresh),
-                     "kernel": "k_cg_fused" + (" + k_refresh_u + k_refresh_c" if refresh else ""),
+                     "kernel": kname + (" + k_refresh_u + k_refresh_c" if refresh else ""),
                      "kernel_ms": kavg,
                      "algorithmic_bytes_per_launch": lb,
                      "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
