@@ -575,6 +575,7 @@ def main():
                                        args.sweep_frames, args.sweep_pool_gib << 30)
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    out["build"] = otfs.build_info()   # the library's source stamp, checked against this tree
     print(json.dumps(out), flush=True)
 
 

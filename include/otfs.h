@@ -56,6 +56,10 @@ typedef enum {
 /* Text of the last non-OK status returned on the calling thread ("" if none). */
 const char* otfs_last_error(void);
 
+/* Provenance of this build: "source_sha=<16 hex digits> arch=<gfx target>", the SHA-256
+ * prefix of the sources and headers the library was compiled from (static string). */
+const char* otfs_build_info(void);
+
 /* ------------------------------------------------------------------------------------ */
 /* Frames, options, statistics                                                           */
 /* ------------------------------------------------------------------------------------ */

@@ -84,6 +84,19 @@ _lib = None
 _vp = ctypes.c_void_p
 
 
+def build_info() -> dict:
+    """The loaded library's build stamp {"source_sha", "arch"}, and whether the sources in
+    this tree still hash to it ("current")."""
+    raw = lib().otfs_build_info().decode()
+    info = dict(kv.split("=", 1) for kv in raw.split())
+    try:
+        from .build_lib import source_sha
+        info["current"] = info.get("source_sha") == source_sha()
+    except OSError:   # sources not shipped with the library
+        info["current"] = None
+    return info
+
+
 def header_functions() -> List[str]:
     """Names of the functions include/otfs.h declares."""
     txt = open(HEADER_PATH).read()
@@ -102,6 +115,7 @@ def lib() -> ctypes.CDLL:
     st = ctypes.c_int
     sig = {
         "otfs_last_error": (ctypes.c_char_p, []),
+        "otfs_build_info": (ctypes.c_char_p, []),
         "otfs_plan": (st, [ctypes.POINTER(FrameDesc), ctypes.c_int32, ctypes.POINTER(CgOpts),
                            ctypes.POINTER(_vp)]),
         "otfs_plan_workspace_bytes": (st, [_vp, ctypes.POINTER(ctypes.c_size_t),

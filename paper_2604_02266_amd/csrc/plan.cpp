@@ -604,6 +604,16 @@ using namespace otfs;
 // =========================================================================================
 extern "C" const char* otfs_last_error(void) { return otfs::last_error(); }
 
+#ifndef OTFS_SOURCE_SHA
+#define OTFS_SOURCE_SHA "unstamped"
+#endif
+#ifndef OTFS_BUILD_ARCH
+#define OTFS_BUILD_ARCH "unknown"
+#endif
+extern "C" const char* otfs_build_info(void) {
+  return "source_sha=" OTFS_SOURCE_SHA " arch=" OTFS_BUILD_ARCH;
+}
+
 extern "C" otfs_status otfs_plan(const otfs_frame_desc* frames, int32_t nframes,
                                  const otfs_cg_opts* opts, otfs_plan_t** out) {
   if (!out) return fail(OTFS_E_INVAL, "out must be non-null");

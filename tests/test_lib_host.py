@@ -119,3 +119,11 @@ def test_ber_profile_rule_matches_the_oracle():
                for _ in range(50)]
     for c in curves:
         assert ber_profile.convergence_iteration(c) == O.ber_convergence(c)
+
+
+def test_build_stamp_matches_the_sources():
+    # the library carries the hash of the sources it was compiled from; the loader compares
+    # it with this tree, so a stale build cannot pass for the current code
+    info = otfs.build_info()
+    assert len(info["source_sha"]) == 16 and info["arch"].startswith("gfx")
+    assert info["current"] is True, info
