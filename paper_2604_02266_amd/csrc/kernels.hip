@@ -1140,6 +1140,17 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
     __syncthreads();
     const int k = k0 + 2 * tx;
     if (nrows == 0 || k >= M) continue;
+    // Whether any pair of this strip wraps around the delay axis for a path in the frame's
+    // delay range (uniform over the strip; the per-pair tests below then decide as before).
+    // Strips that do not, in a band window, run a chunk loop with neither the wrap branch
+    // nor the row wrap: its accumulators stay in place (no copies between the branches).
+    const int kmax = min(k0 + KC, M) - 2;
+    const int kmin_src = ADJ ? k0 + F.tau_lo : k0 - F.tau_hi;
+    const int kmax_src = ADJ ? kmax + F.tau_hi : kmax - F.tau_lo;
+    const bool strip_wraps = kmin_src < 0 || kmax_src + 1 >= M;
+    auto chunks = [&](auto wrap_c, auto rows_c) __attribute__((always_inline)) {
+    constexpr bool WRAP = decltype(wrap_c)::value;
+    constexpr int FR = decltype(rows_c)::value;   // 0: band window, 1: all rows, 2: either
     for (int j0 = 0; j0 < nrows; j0 += kLdsRows) {
       int l[kLdsRows];
       C wl[kLdsRows];
@@ -1183,7 +1194,7 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
 #pragma unroll
         for (int i = 0; i < kLdsRows; ++i) {
           int lr = l[i] + sh;
-          if (full_rows) {
+          if (FR == 1 || (FR == 2 && full_rows)) {
             lr += lr < 0 ? N : 0;
             lr -= lr >= N ? N : 0;
           } else {
@@ -1193,7 +1204,7 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
           e0[i] = A::from(__builtin_bit_cast(float2, w[0]));
           e1[i] = A::from(__builtin_bit_cast(float2, w[1]));
         }
-        if (__builtin_amdgcn_ballot_w64(lo0 || hi0 || lo1 || hi1) != 0) {
+        if (WRAP && __builtin_amdgcn_ballot_w64(lo0 || hi0 || lo1 || hi1) != 0) {
           C cw0 = c0, cw1 = c1;
           if (!ADJ) {
             const C wn = A::tab_s(wt, tn.y < 0 ? tn.y + N : tn.y);
@@ -1219,6 +1230,11 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
       for (int i = 0; i < kLdsRows; ++i)
         if (j0 + i < nrows) sink((uint32_t)(l[i] * M + k), acc0[i], acc1[i], pf[i]);
     }
+    };
+    if (!strip_wraps && !full_rows)
+      chunks(std::false_type{}, std::integral_constant<int, 0>{});
+    else
+      chunks(std::true_type{}, std::integral_constant<int, 2>{});
   }
   __syncthreads();   // the window region is free for the caller
 }
@@ -1681,7 +1697,7 @@ __device__ __forceinline__ FrameVecs frame_vecs(const FrameDev& F, const Bases& 
 }
 
 // Final x update (if pending), decisions and statistics of one tile.
-__device__ void finish_tile(const FrameDev& F, const WorkItem& wi, const FrameVecs& V,
+__device__ __forceinline__ void finish_tile(const FrameDev& F, const WorkItem& wi, const FrameVecs& V,
                             const FrameState& s, const float2* pcur, bool xpending,
                             int status) {
   const int M = F.M;
@@ -2446,6 +2462,17 @@ constexpr int kRefPaths = 4;   // paths in flight together
 // The refresh of a tile reads its gathers through the LDS window of the windowed paired
 // gathers when the frame has that geometry, the window fits the launch's LDS and the
 // frame's vectors split into 16-byte pairs.
+// Item of this workgroup in the refresh launches.  Workgroup b runs on XCD b % nxcd; the
+// workgroups of one XCD take consecutive items (the items of a frame are consecutive), so
+// the tiles of a frame, whose windows share the rows of the Doppler range, read them
+// through one L2.  A bijection of [0, nitems) for any nitems and nxcd >= 1.
+__device__ __forceinline__ int refresh_item(int nitems, int nxcd) {
+  if (nxcd <= 1) return (int)blockIdx.x;
+  const int b = (int)blockIdx.x, x = b % nxcd;
+  int o = 0;
+  for (int y = 0; y < x; ++y) o += (nitems - y + nxcd - 1) / nxcd;
+  return o + b / nxcd;
+}
 __device__ __forceinline__ bool ref_lds_ok(const FrameDev& F, const WorkItem& wi, int lds_bytes) {
   return F.lpk > 0 && pairs_ok(F) && F.lwr * F.lwc * (int)sizeof(float2) <= lds_bytes &&
          lds_window_fits(F, wi.l_begin, wi.l_end);
@@ -2453,10 +2480,11 @@ __device__ __forceinline__ bool ref_lds_ok(const FrameDev& F, const WorkItem& wi
 
 __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_u(const FrameDev* __restrict__ frames,
                                                       const WorkItem* __restrict__ items, Bases B,
-                                                      unsigned* qhead, int nq, int lds_bytes) {
+                                                      unsigned* qhead, int nq, int lds_bytes,
+                                                      int nxcd) {
   extern __shared__ float2 ref_lds[];
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  const WorkItem wi = items[blockIdx.x];
+  const WorkItem wi = items[refresh_item((int)gridDim.x, nxcd)];
   const FrameDev& F = frames[wi.frame];
   if (blockIdx.x == 0 && (int)threadIdx.x < nq) qhead[threadIdx.x] = 0u;
   if (threadIdx.x == 0) {
@@ -2495,11 +2523,11 @@ __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_u(const 
 
 __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_c(const FrameDev* __restrict__ frames,
                                                       const WorkItem* __restrict__ items, Bases B,
-                                                      int lds_bytes) {
+                                                      int lds_bytes, int nxcd) {
   __shared__ double redd[kWaves];
   extern __shared__ float2 ref_lds[];
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  const WorkItem wi = items[blockIdx.x];
+  const WorkItem wi = items[refresh_item((int)gridDim.x, nxcd)];
   const FrameDev& F = frames[wi.frame];
   if (F.st->refresh == 0 || F.st->status != OTFS_FRAME_RUNNING) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -3140,8 +3168,8 @@ hipError_t launch_cg_fused(int kind, int sd, const FrameDev* frames, const WorkI
 }
 
 hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nitems, Bases bases,
-                          unsigned* qhead, int nq, int lds_bytes, hipStream_t s) {
-  if (nitems <= 0 || nq > kBlock || lds_bytes < 0) return hipErrorInvalidValue;
+                          unsigned* qhead, int nq, int lds_bytes, int nxcd, hipStream_t s) {
+  if (nitems <= 0 || nq > kBlock || lds_bytes < 0 || nxcd < 1) return hipErrorInvalidValue;
   if (lds_bytes > 0) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refresh_u),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
@@ -3151,9 +3179,9 @@ hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nit
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_refresh_u, dim3(nitems), dim3(kBlock), lds_bytes, s, frames, items, bases,
-                     qhead, nq, lds_bytes);
+                     qhead, nq, lds_bytes, nxcd);
   hipLaunchKernelGGL(k_refresh_c, dim3(nitems), dim3(kBlock), lds_bytes, s, frames, items, bases,
-                     lds_bytes);
+                     lds_bytes, nxcd);
   return hipGetLastError();
 }
 

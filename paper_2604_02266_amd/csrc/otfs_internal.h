@@ -201,8 +201,10 @@ int fused_blocks_per_cu(int kind, int sd, int lds_bytes);
 // barrier and neighbour counters and the nq queue cursors for the next fused launch.
 // lds_bytes: dynamic LDS for the windows of frames with the windowed paired geometry (the
 // largest window of the windowed kind's launch; 0 = every frame gathers from memory).
+// nxcd: XCDs over which the device dispatches workgroups round robin (1: no such layout);
+// the blocks of one XCD then take consecutive items, so a frame's tiles share its L2.
 hipError_t launch_refresh(const FrameDev* frames, const WorkItem* items, int nitems, Bases bases,
-                          unsigned* qhead, int nq, int lds_bytes, hipStream_t s);
+                          unsigned* qhead, int nq, int lds_bytes, int nxcd, hipStream_t s);
 
 // Static scratch of the entry point that allocates nothing: kNoAllocBytes per device.
 // *ptr = its device address on `device`, which must be the current device (found once per

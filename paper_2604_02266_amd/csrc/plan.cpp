@@ -771,6 +771,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   XcdInfo xi;
   otfs_status pst = probe_xcds(dev, static_cast<char*>(ws) + plan->L.probe, s, &xi);
   if (pst != OTFS_OK) return pst;
+  plan->ref_xcds = xi.round_robin ? xi.nxcd : 1;
   pst = plan_launches(plan->frames, geo, plan->tile_base, plan->tiles,
                       stored_mode(plan->opts.flags), plan->opts.refresh_every > 0,
                       (plan->opts.flags & OTFS_SPLIT_DIRECTION) != 0, cus, plan->max_grid_req, xi,
@@ -938,7 +939,8 @@ static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s
     }
     if (seg + 1 < nseg) {
       e = launch_refresh(plan->d_frames, plan->d_items, (int)plan->items.size(), B,
-                         plan->d_qhead, kKinds * kMaxGroups, refresh_lds_bytes(plan->launches), s);
+                         plan->d_qhead, kKinds * kMaxGroups, refresh_lds_bytes(plan->launches),
+                         plan->ref_xcds, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -1064,7 +1066,8 @@ extern "C" otfs_status otfs_lmmse_cg_trace(otfs_plan_t* plan, const void* y, voi
     if (it > 0) {   // counters and cursors of the next one-iteration launch
       e = plan->opts.refresh_every > 0
               ? launch_refresh(plan->d_frames, plan->d_items, ni, B, plan->d_qhead,
-                               kKinds * kMaxGroups, refresh_lds_bytes(plan->launches), s)
+                               kKinds * kMaxGroups, refresh_lds_bytes(plan->launches),
+                               plan->ref_xcds, s)
               : launch_step_reset(plan->d_frames, nf, plan->d_abort, plan->d_qhead,
                                   kKinds * kMaxGroups, s);
     }

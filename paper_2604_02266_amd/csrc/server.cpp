@@ -473,7 +473,8 @@ bool gpu_step(otfs_server* S, std::vector<Request*>& act, std::vector<otfs_frame
   // the next step resumes them
   if (e == hipSuccess && S->opts.refresh_every > 0)
     e = launch_refresh(dframes, reinterpret_cast<const WorkItem*>(P + C.items), nitems,
-                       B, qhead, kKinds * kMaxGroups, refresh_lds_bytes(launches), S->s);
+                       B, qhead, kKinds * kMaxGroups, refresh_lds_bytes(launches),
+                       S->xcd.round_robin ? S->xcd.nxcd : 1, S->s);
   if (e == hipSuccess) e = hipEventRecord(S->ev_end, S->s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(H + C.stats, dstats, (size_t)n * sizeof(otfs_frame_stats),
