@@ -934,6 +934,16 @@ __device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int 
   const KPairs wtab_s = kpairs(F.wtab);
   const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(F.rtab, (int64_t)P * M * 8);
   for (int k = 2 * tx; k < M; k += 2 * TX) {
+    // Whether a pair of this strip of columns can wrap around the delay axis (or straddle
+    // the row's wrap point) for a path in the frame's delay range: uniform over the strip.
+    // Strips that cannot run a row loop without the wrap and fix-up branches, whose
+    // accumulators then stay in place; the per-pair tests decide as before elsewhere.
+    const int k0 = k - 2 * tx, kmax = min(k0 + 2 * TX, M) - 2;
+    const int kmin_src = ADJ ? k0 + F.tau_lo : k0 - F.tau_hi;
+    const int kmax_src = ADJ ? kmax + F.tau_hi : kmax - F.tau_lo;
+    const bool strip_wraps = kmin_src < 0 || kmax_src + 1 >= M;
+    auto rows = [&](auto wrap_c) __attribute__((always_inline)) {
+    constexpr bool WRAP = decltype(wrap_c)::value;
     for (int r0 = 0; r0 < nrows; r0 += R) {
       int l[R];
       uint32_t l8[R];
@@ -986,7 +996,7 @@ __device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int 
         }
 #pragma unroll
         for (int u = 0; u < NP; ++u) {
-          if (__builtin_amdgcn_ballot_w64(split[u]) != 0) {
+          if (WRAP && __builtin_amdgcn_ballot_w64(split[u]) != 0) {
 #pragma unroll
             for (int i = 0; i < R; ++i) {
               const uint32_t x = l8[i] + dn8[u];
@@ -1001,7 +1011,7 @@ __device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int 
         for (int u = 0; u < NP; ++u) {
           float2 c0, c1;
           unpack2(cf2[u], c0, c1);
-          const bool sp = __builtin_amdgcn_ballot_w64(split[u]) != 0;
+          const bool sp = WRAP && __builtin_amdgcn_ballot_w64(split[u]) != 0;
           if (ADJ) {
             if (sp && split[u]) c1 = cfx[u];
             c0 = make_float2(c0.x, -c0.y);
@@ -1013,7 +1023,7 @@ __device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int 
             src.value2(v[u][i], e0[i], e1[i]);
             if (sp && split[u]) e1[i] = src.value(fx[u][i]);
           }
-          if (__builtin_amdgcn_ballot_w64(lo0[u] || hi0[u] || lo1[u] || hi1[u]) != 0) {
+          if (WRAP && __builtin_amdgcn_ballot_w64(lo0[u] || hi0[u] || lo1[u] || hi1[u]) != 0) {
             // waves holding a delay wrap of this path: wrapped elements take W^n
             float2 cw0 = c0, cw1 = c1;
             if (!ADJ) {
@@ -1049,6 +1059,11 @@ __device__ __forceinline__ void band_apply_pairs(const FrameDev& F, int lb, int 
       for (int i = 0; i < R; ++i)
         if (r0 + i < nrows) sink((uint32_t)(l[i] * M + k), acc0[i], acc1[i], pf[i]);
     }
+    };
+    if (strip_wraps)
+      rows(std::true_type{});
+    else
+      rows(std::false_type{});
   }
 }
 
