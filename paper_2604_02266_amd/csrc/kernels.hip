@@ -1179,6 +1179,62 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
         acc1[i] = A::zero();
         pf[i] = pref((uint32_t)(l[i] * M + k));
       }
+      // window row of output row i for a path with Doppler shift sh
+      auto wrow = [&](int i, int sh) __attribute__((always_inline)) {
+        int lr = l[i] + sh;
+        if (FR == 1 || (FR == 2 && full_rows)) {
+          lr += lr < 0 ? N : 0;
+          lr -= lr >= N ? N : 0;
+        } else {
+          lr -= row0;
+        }
+        return lr;
+      };
+      if constexpr (!WRAP && F32) {
+        // No pair of the strip wraps: every source column is K = k -+ tau in [0, M - 2].
+        // The coefficients of the next path are requested before the current one is
+        // applied, so their latency overlaps its LDS reads and products (same values, same
+        // order); two register sets alternate, so nothing waits on a copy.
+        auto coef = [&](int p, int2& tn) __attribute__((always_inline)) {
+          tn = paths.i2(p);
+          return buf_ld4b(rtab, ADJ ? 8u * (uint32_t)(k + tn.x) : 8u * (uint32_t)k,
+                          (uint32_t)p * M8);
+        };
+        auto apply = [&](int2 tn, u32x4 cf) __attribute__((always_inline)) {
+          float2 f0, f1;
+          unpack2(cf, f0, f1);
+          C c0 = A::from(f0), c1 = A::from(f1);
+          if (ADJ) {
+            c0 = A::conj(c0);
+            c1 = A::conj(c1);
+          }
+          const int K = ADJ ? k + tn.x : k - tn.x;
+          const int lc = full_cols ? K : K - col0;
+          const int sh = ADJ ? tn.y : -tn.y;
+          C e0[kLdsRows], e1[kLdsRows];
+#pragma unroll
+          for (int i = 0; i < kLdsRows; ++i) {
+            const lptr<u64> w = win + wrow(i, sh) * WC + lc;
+            e0[i] = A::from(__builtin_bit_cast(float2, w[0]));
+            e1[i] = A::from(__builtin_bit_cast(float2, w[1]));
+          }
+#pragma unroll
+          for (int i = 0; i < kLdsRows; ++i) {
+            A::mac(acc0[i], c0, e0[i]);
+            A::mac(acc1[i], c1, e1[i]);
+          }
+        };
+        int2 ta, tb;
+        u32x4 ca = coef(0, ta);
+        int p = 0;
+        for (; p + 1 < P; p += 2) {
+          const u32x4 cb = coef(p + 1, tb);
+          apply(ta, ca);
+          ca = coef(p + 2 < P ? p + 2 : p + 1, ta);
+          apply(tb, cb);
+        }
+        if (p < P) apply(ta, ca);
+      } else
       for (int p = 0; p < P; ++p) {
         const int2 tn = paths.i2(p);
         const int K = ADJ ? k + tn.x : k - tn.x;   // source column of element 0 (unwrapped)
@@ -1208,14 +1264,7 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
         C e0[kLdsRows], e1[kLdsRows];
 #pragma unroll
         for (int i = 0; i < kLdsRows; ++i) {
-          int lr = l[i] + sh;
-          if (FR == 1 || (FR == 2 && full_rows)) {
-            lr += lr < 0 ? N : 0;
-            lr -= lr >= N ? N : 0;
-          } else {
-            lr -= row0;
-          }
-          const lptr<u64> w = win + lr * WC + lc;
+          const lptr<u64> w = win + wrow(i, sh) * WC + lc;
           e0[i] = A::from(__builtin_bit_cast(float2, w[0]));
           e1[i] = A::from(__builtin_bit_cast(float2, w[1]));
         }
