@@ -1268,7 +1268,9 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
           e0[i] = A::from(__builtin_bit_cast(float2, w[0]));
           e1[i] = A::from(__builtin_bit_cast(float2, w[1]));
         }
-        if (WRAP && __builtin_amdgcn_ballot_w64(lo0 || hi0 || lo1 || hi1) != 0) {
+        if constexpr (WRAP) {
+          // wrapped elements take W^n; selected per lane without a branch, so the
+          // accumulators are not copied between two arms on every path
           C cw0 = c0, cw1 = c1;
           if (!ADJ) {
             const C wn = A::tab_s(wt, tn.y < 0 ? tn.y + N : tn.y);
