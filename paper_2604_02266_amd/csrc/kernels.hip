@@ -1190,20 +1190,49 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
         }
         return lr;
       };
-      if constexpr (!WRAP && F32) {
+      // the pairs of the kLdsRows rows for one path: every LDS read is issued before any
+      // is used (the FP64 form would otherwise convert each pair as it arrives and wait
+      // for the reads one at a time)
+      auto window_reads = [&](C* e0, C* e1, auto addr) __attribute__((always_inline)) {
+        float2 r0[kLdsRows], r1[kLdsRows];
+#pragma unroll
+        for (int i = 0; i < kLdsRows; ++i) {
+          const lptr<u64> w = addr(i);
+          r0[i] = __builtin_bit_cast(float2, w[0]);
+          r1[i] = __builtin_bit_cast(float2, w[1]);
+        }
+        if constexpr (!F32) asm volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < kLdsRows; ++i) {
+          e0[i] = A::from(r0[i]);
+          e1[i] = A::from(r1[i]);
+        }
+      };
+      if constexpr (!WRAP) {
         // No pair of the strip wraps: every source column is K = k -+ tau in [0, M - 2].
         // The coefficients of the next path are requested before the current one is
         // applied, so their latency overlaps its LDS reads and products (same values, same
         // order); two register sets alternate, so nothing waits on a copy.
+        struct Cf {
+          C c0, c1;
+        };
         auto coef = [&](int p, int2& tn) __attribute__((always_inline)) {
           tn = paths.i2(p);
-          return buf_ld4b(rtab, ADJ ? 8u * (uint32_t)(k + tn.x) : 8u * (uint32_t)k,
-                          (uint32_t)p * M8);
+          const uint32_t kc = ADJ ? (uint32_t)(k + tn.x) : (uint32_t)k;
+          Cf r;
+          if constexpr (F32) {
+            float2 f0, f1;
+            unpack2(buf_ld4b(rtab, 8u * kc, (uint32_t)p * M8), f0, f1);
+            r.c0 = A::from(f0);
+            r.c1 = A::from(f1);
+          } else {   // one 16-byte entry per column
+            r.c0 = A::tab(rtab, TS * 8u * kc, TS * (uint32_t)p * M8);
+            r.c1 = A::tab(rtab, TS * 8u * (kc + 1u), TS * (uint32_t)p * M8);
+          }
+          return r;
         };
-        auto apply = [&](int2 tn, u32x4 cf) __attribute__((always_inline)) {
-          float2 f0, f1;
-          unpack2(cf, f0, f1);
-          C c0 = A::from(f0), c1 = A::from(f1);
+        auto apply = [&](int2 tn, const Cf& cf) __attribute__((always_inline)) {
+          C c0 = cf.c0, c1 = cf.c1;
           if (ADJ) {
             c0 = A::conj(c0);
             c1 = A::conj(c1);
@@ -1212,12 +1241,7 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
           const int lc = full_cols ? K : K - col0;
           const int sh = ADJ ? tn.y : -tn.y;
           C e0[kLdsRows], e1[kLdsRows];
-#pragma unroll
-          for (int i = 0; i < kLdsRows; ++i) {
-            const lptr<u64> w = win + wrow(i, sh) * WC + lc;
-            e0[i] = A::from(__builtin_bit_cast(float2, w[0]));
-            e1[i] = A::from(__builtin_bit_cast(float2, w[1]));
-          }
+          window_reads(e0, e1, [&](int i) { return win + wrow(i, sh) * WC + lc; });
 #pragma unroll
           for (int i = 0; i < kLdsRows; ++i) {
             A::mac(acc0[i], c0, e0[i]);
@@ -1225,10 +1249,10 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
           }
         };
         int2 ta, tb;
-        u32x4 ca = coef(0, ta);
+        Cf ca = coef(0, ta);
         int p = 0;
         for (; p + 1 < P; p += 2) {
-          const u32x4 cb = coef(p + 1, tb);
+          const Cf cb = coef(p + 1, tb);
           apply(ta, ca);
           ca = coef(p + 2 < P ? p + 2 : p + 1, ta);
           apply(tb, cb);
@@ -1262,12 +1286,7 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
         const int lc = full_cols ? s0 : K - col0;   // window column of element 0
         const int sh = ADJ ? tn.y : -tn.y;
         C e0[kLdsRows], e1[kLdsRows];
-#pragma unroll
-        for (int i = 0; i < kLdsRows; ++i) {
-          const lptr<u64> w = win + wrow(i, sh) * WC + lc;
-          e0[i] = A::from(__builtin_bit_cast(float2, w[0]));
-          e1[i] = A::from(__builtin_bit_cast(float2, w[1]));
-        }
+        window_reads(e0, e1, [&](int i) { return win + wrow(i, sh) * WC + lc; });
         if constexpr (WRAP) {
           // wrapped elements take W^n; selected per lane without a branch, so the
           // accumulators are not copied between two arms on every path
