@@ -743,6 +743,10 @@ constexpr int kElemChunk = OTFS_ELEM_CHUNK;   // elements per thread in flight, 
 #define OTFS_ELEM_CHUNK_FD 16
 #endif
 constexpr int kElemChunkFd = OTFS_ELEM_CHUNK_FD;   // the same in the direct-fd kind (more registers free)
+#ifndef OTFS_ELEM_CHUNK_LDS
+#define OTFS_ELEM_CHUNK_LDS 16
+#endif
+constexpr int kElemChunkLds = OTFS_ELEM_CHUNK_LDS;   // and in the windowed-pairs kind
 #ifndef OTFS_RES_ROWS
 #define OTFS_RES_ROWS 2
 #endif
@@ -1852,6 +1856,9 @@ __device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, i
                         const LaunchCtx& L, float* red, int* sflag, float2* lds) {
   // the stored-table reads leave fewer registers for gathers in flight
   constexpr int RR = SD != kDNone ? 2 : kRows;
+  // elements per thread in flight in the element-wise passes (the windowed kind has the
+  // registers for more)
+  constexpr int ECK = GM == kGmLds ? kElemChunkLds : kElemChunk;
   const FrameVecs V = frame_vecs(F, B);
   FrameState s = *F.st;
   if (s.status != OTFS_FRAME_RUNNING) return;
@@ -1976,7 +1983,7 @@ __device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, i
     } else {
       // A1: p' = c + beta p_old and x += alpha p_old over the band, stored once
       if (pairs_ok(F)) {   // two elements per lane and access (16-byte loads and stores)
-        constexpr int EP = kElemChunk / 2;
+        constexpr int EP = ECK / 2;
         for (uint32_t u = u0 + 2u * threadIdx.x; u < u1; u += 2u * kBlock * EP) {
           float2 c0[EP], c1[EP], p0[EP], p1[EP], x0[EP], x1[EP];
 #pragma unroll
@@ -1996,17 +2003,17 @@ __device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, i
           }
         }
       } else
-      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * kElemChunk) {
-        float2 c[kElemChunk], po[kElemChunk], xo[kElemChunk];
+      for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock * ECK) {
+        float2 c[ECK], po[ECK], xo[ECK];
 #pragma unroll
-        for (int j = 0; j < kElemChunk; ++j) {
+        for (int j = 0; j < ECK; ++j) {
           const uint32_t w = min(u + (uint32_t)(j * kBlock), u1 - 1u);
           c[j] = cv.ld<kNtElem>(w);
           po[j] = pov.ld<kNtElem>(w);
           if (xp) xo[j] = xv.ld<kNtElem>(w);
         }
 #pragma unroll
-        for (int j = 0; j < kElemChunk; ++j) {
+        for (int j = 0; j < ECK; ++j) {
           const uint32_t w = u + (uint32_t)(j * kBlock);
           if (w < u1) {
             pnv.st<kNtP>(w, axpyf(be, po[j], c[j]));
@@ -2047,7 +2054,7 @@ __device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, i
       float acc = 0.f;
       // EC elements per thread at a time, all loads issued first (past the band's end the
       // last element is re-read and nothing is stored)
-      constexpr int EC = FDIR ? kElemChunkFd : kElemChunk;
+      constexpr int EC = FDIR ? kElemChunkFd : ECK;
       if (pairs_ok(F)) {   // two elements per lane and access; the same sums per element
         constexpr int EP = EC / 2;
         for (uint32_t u = u0 + 2u * threadIdx.x; u < u1; u += 2u * kBlock * EP) {
@@ -2092,8 +2099,26 @@ __device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, i
         }
       }
       if (refresh_due) {   // x += alpha p' before the refresh launches read x
-        for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock)
-          xv.st(u, axpyf(alpha, pnv.ld(u), xv.ld(u)));
+        if (pairs_ok(F)) {   // as in the passes above: EP pairs per thread in flight
+          constexpr int EP = ECK / 2;
+          for (uint32_t u = u0 + 2u * threadIdx.x; u < u1; u += 2u * kBlock * EP) {
+            float2 p0[EP], p1[EP], x0[EP], x1[EP];
+#pragma unroll
+            for (int j = 0; j < EP; ++j) {
+              const uint32_t w = min(u + (uint32_t)(2 * j * kBlock), u1 - 2u);
+              pnv.ld2(w, p0[j], p1[j]);
+              xv.ld2(w, x0[j], x1[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < EP; ++j) {
+              const uint32_t w = u + (uint32_t)(2 * j * kBlock);
+              if (w < u1) xv.st2(w, axpyf(alpha, p0[j], x0[j]), axpyf(alpha, p1[j], x1[j]));
+            }
+          }
+        } else {
+          for (uint32_t u = u0 + threadIdx.x; u < u1; u += kBlock)
+            xv.st(u, axpyf(alpha, pnv.ld(u), xv.ld(u)));
+        }
       }
       const float bs = block_sum(acc, red);
       if (threadIdx.x == 0) F.part_cc[wi.tile] = bs;
