@@ -463,7 +463,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-__device__ float block_sum(float v, float* red) {
+__device__ __forceinline__ float block_sum(float v, float* red) {
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -473,7 +473,7 @@ __device__ float block_sum(float v, float* red) {
   __syncthreads();
   return s;
 }
-__device__ double block_sum_d(double v, double* red) {
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
   v = wave_sum_d(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -1849,6 +1849,69 @@ struct LaunchCtx {
   int xcd_local;     // barrier coherence mode (see frame_barrier)
 };
 
+// FP64 true-residual refresh of one tile through the LDS window of the windowed paired
+// gathers (used by the refresh launches and, inside the fused launch, by the windowed kind).
+// The residual is formed in FP64 (no cancellation between y and Hx) and kept in FP32.
+__device__ __forceinline__ float2 refresh_res(float2 yv, double2 v) {
+  return make_float2((float)((double)yv.x - v.x), (float)((double)yv.y - v.y));
+}
+// u = y - H x over the band (FP64 tables and sums)
+__device__ __forceinline__ void refresh_u_window(const FrameDev& F, const WorkItem& wi,
+                                                 const FrameVecs& V, float2* lds) {
+  const int64_t E = (int64_t)F.M * F.N;
+  const CVec u = cvec(F.u, E);
+  const SrcBuf xs{buf_rsrc(V.x, E * 8)};
+  struct Y2 {
+    float2 a, b;
+  };
+  lds_apply_pairs<false, ArithF64>(
+      F, wi.l_begin, wi.l_end, xs, lds,
+      [&](uint32_t q) { return Y2{load_y(V.y, q, V.ybf16), load_y(V.y, q + 1u, V.ybf16)}; },
+      [&](uint32_t q, double2 v0, double2 v1, const Y2& yv) {
+        u.st2(q, refresh_res(yv.a, v0), refresh_res(yv.b, v1));
+      });
+}
+// c = H^H u - lam x over the band, rounded to FP32; returns this thread's FP64 partial of
+// ||c||^2
+__device__ __forceinline__ double refresh_c_window(const FrameDev& F, const WorkItem& wi,
+                                                   const FrameVecs& V, float2* lds) {
+  const int64_t E = (int64_t)F.M * F.N;
+  const double lam = (double)F.lam;
+  const CVec cv = cvec(F.c, E), xv = cvec(V.x, E);
+  const SrcBuf us{buf_rsrc(F.u, E * 8)};
+  double acc = 0.0;
+  auto cval = [&](double2 v, float2 x) {
+    return make_float2((float)(v.x - lam * (double)x.x), (float)(v.y - lam * (double)x.y));
+  };
+  auto nrm = [&](float2 cf) {
+    acc = fma((double)cf.x, (double)cf.x, acc);
+    acc = fma((double)cf.y, (double)cf.y, acc);
+  };
+  struct X2 {
+    float2 a, b;
+  };
+  lds_apply_pairs<true, ArithF64>(
+      F, wi.l_begin, wi.l_end, us, lds,
+      [&](uint32_t q) {
+        X2 r;
+        xv.ld2(q, r.a, r.b);
+        return r;
+      },
+      [&](uint32_t q, double2 v0, double2 v1, const X2& x) {
+        const float2 c0 = cval(v0, x.a), c1 = cval(v1, x.b);
+        cv.st2(q, c0, c1);
+        nrm(c0);
+        nrm(c1);
+      });
+  return acc;
+}
+// Whether every tile of the frame refreshes through its window (a decision the same for all
+// tiles of the frame: its bands are floor(N / T) or ceil(N / T) rows)
+__device__ __forceinline__ bool frame_windows_fit(const FrameDev& F) {
+  return F.lpk > 0 && pairs_ok(F) && lds_window_fits(F, 0, F.N / F.T) &&
+         lds_window_fits(F, 0, (F.N + F.T - 1) / F.T);
+}
+
 // GM: where the gathers read from (kGmDirect, kGmStaged, kGmLds).  FDIR: the H pass forms
 // p' = c + beta p inside its gathers (direct-fd kind).
 template <int SD, int GM, bool FDIR = false>
@@ -2129,6 +2192,22 @@ __device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, i
     s.alpha = alpha;
     if (refresh_due) {
       if (!isfinite(cn_new)) return finish_tile(F, wi, V, s, pnew_g, false, OTFS_FRAME_NONFINITE);
+      if constexpr (GM == kGmLds) {
+        if (frame_windows_fit(F)) {
+          // The true residual inside this launch, by the same steps as the refresh launches:
+          // u = y - H x (x is final in every tile after the barrier above), the
+          // neighbouring tiles' u, then c = H^H u - lam x with its FP64 norm.
+          refresh_u_window(F, wi, V, lds);
+          if (!halo(rd_hh)) return fail_timeout();
+          const double bs = block_sum_d(refresh_c_window(F, wi, V, lds),
+                                        reinterpret_cast<double*>(red));
+          if (threadIdx.x == 0) F.part_d[wi.tile] = bs;
+          if (!bar()) return fail_timeout();
+          s.pending = 0;
+          if (!next((float)tile_sum_d(F.part_d, T), false, F.p0)) return;
+          continue;
+        }
+      }
       // leave the launch: the refresh launches form the true residual of x
       s.refresh = 1;
       s.pending = 0;
@@ -2505,7 +2584,8 @@ __global__ __launch_bounds__(kBlock, fused_min_waves(KIND)) void k_cg_fused(cons
                                                      const int2* __restrict__ qrange,
                                                      unsigned* __restrict__ qhead, int ngroups,
                                                      int budget, Bases B, LaunchCtx L) {
-  __shared__ float red[kWaves];
+  __shared__ double red_d[kWaves];   // FP32 sums use its first kWaves floats
+  float* const red = reinterpret_cast<float*>(red_d);
   __shared__ int sflag;
   __shared__ int s_item;
   extern __shared__ float2 stage_lds[];
@@ -2606,27 +2686,15 @@ __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_u(const 
     return;
   }
   const FrameVecs V = frame_vecs(F, B);
-  const int64_t E = (int64_t)F.M * F.N;
-  const CVec u = cvec(F.u, E);
-  const SrcBuf xs{buf_rsrc(V.x, E * 8)};
-  // the residual is formed in FP64 (no cancellation between y and Hx) and kept in FP32
-  auto res = [](float2 yv, double2 v) {
-    return make_float2((float)((double)yv.x - v.x), (float)((double)yv.y - v.y));
-  };
   if (ref_lds_ok(F, wi, lds_bytes)) {
-    struct Y2 {
-      float2 a, b;
-    };
-    lds_apply_pairs<false, ArithF64>(
-        F, wi.l_begin, wi.l_end, xs, ref_lds,
-        [&](uint32_t q) { return Y2{load_y(V.y, q, V.ybf16), load_y(V.y, q + 1u, V.ybf16)}; },
-        [&](uint32_t q, double2 v0, double2 v1, const Y2& yv) {
-          u.st2(q, res(yv.a, v0), res(yv.b, v1));
-        });
+    refresh_u_window(F, wi, V, ref_lds);
   } else {
+    const int64_t E = (int64_t)F.M * F.N;
+    const CVec u = cvec(F.u, E);
+    const SrcBuf xs{buf_rsrc(V.x, E * 8)};
     band_apply<kRefRows, kRefPaths, false, kDNone>(
         F, wi.l_begin, wi.l_end, xs, [&](uint32_t q) { return load_y(V.y, q, V.ybf16); },
-        [&](int q, double2 v, float2 yv) { u.st((uint32_t)q, res(yv, v)); }, ArithF64{});
+        [&](int q, double2 v, float2 yv) { u.st((uint32_t)q, refresh_res(yv, v)); }, ArithF64{});
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
@@ -2644,36 +2712,21 @@ __global__ __launch_bounds__(kBlock, OTFS_REF_MIN_WAVES) void k_refresh_c(const 
     return;
   }
   const FrameVecs V = frame_vecs(F, B);
-  const int64_t E = (int64_t)F.M * F.N;
-  const double lam = (double)F.lam;
-  const CVec cv = cvec(F.c, E), xv = cvec(V.x, E);
   double acc = 0.0;
-  const SrcBuf us{buf_rsrc(F.u, E * 8)};
-  auto cval = [&](double2 v, float2 x) {
-    return make_float2((float)(v.x - lam * (double)x.x), (float)(v.y - lam * (double)x.y));
-  };
-  auto nrm = [&](float2 cf) {
-    acc = fma((double)cf.x, (double)cf.x, acc);
-    acc = fma((double)cf.y, (double)cf.y, acc);
-  };
   if (ref_lds_ok(F, wi, lds_bytes)) {
-    struct X2 {
-      float2 a, b;
-    };
-    lds_apply_pairs<true, ArithF64>(
-        F, wi.l_begin, wi.l_end, us, ref_lds,
-        [&](uint32_t q) {
-          X2 r;
-          xv.ld2(q, r.a, r.b);
-          return r;
-        },
-        [&](uint32_t q, double2 v0, double2 v1, const X2& x) {
-          const float2 c0 = cval(v0, x.a), c1 = cval(v1, x.b);
-          cv.st2(q, c0, c1);
-          nrm(c0);
-          nrm(c1);
-        });
+    acc = refresh_c_window(F, wi, V, ref_lds);
   } else {
+    const int64_t E = (int64_t)F.M * F.N;
+    const double lam = (double)F.lam;
+    const CVec cv = cvec(F.c, E), xv = cvec(V.x, E);
+    const SrcBuf us{buf_rsrc(F.u, E * 8)};
+    auto cval = [&](double2 v, float2 x) {
+      return make_float2((float)(v.x - lam * (double)x.x), (float)(v.y - lam * (double)x.y));
+    };
+    auto nrm = [&](float2 cf) {
+      acc = fma((double)cf.x, (double)cf.x, acc);
+      acc = fma((double)cf.y, (double)cf.y, acc);
+    };
     band_apply<kRefRows, kRefPaths, true, kDNone>(
         F, wi.l_begin, wi.l_end, us, [&](uint32_t q) { return xv.ld(q); },
         [&](int q, double2 v, float2 x) {
