@@ -256,7 +256,8 @@ def solve_block(otfs, O, np, torch, name, frames, ys, refs, steps, warmup, refre
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": load_traffic(name, refresh),
-                     "kernel": kname + (" + k_refresh_u + k_refresh_c" if refresh else ""),
+                     "kernel": (kname[:-1] + ", FP64 refresh inside the launch)" if lds and refresh
+                                else kname + (" + k_refresh_u + k_refresh_c" if refresh else "")),
                      "kernel_ms": kavg,
                      "algorithmic_bytes_per_launch": lb,
                      "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},

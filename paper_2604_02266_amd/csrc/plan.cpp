@@ -865,6 +865,7 @@ extern "C" otfs_status otfs_plan_bind(otfs_plan_t* plan, void* ws, size_t ws_byt
   // the host arrays above must outlive the copies
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize (bind)");
   plan->bound = true;
+  plan->device_paths = false;   // the tables just uploaded are the host's
   return OTFS_OK;
 }
 
@@ -928,7 +929,12 @@ static hipError_t enqueue_fused(otfs_plan_t* plan, const Bases& B, hipStream_t s
                               plan->d_qhead, kKinds * kMaxGroups, s);
   if (e != hipSuccess) return e;
   if (timed && (e = hipEventRecord(plan->ev_begin, s)) != hipSuccess) return e;
-  const int nseg = fused_segments(plan->opts);
+  // Frames of the windowed-pairs kind refresh inside the fused launch when their windows
+  // fit; with the host's path tables (for which the plan sized the windows) and every frame
+  // of that kind, one launch runs the whole solve.
+  bool inline_refresh = !plan->device_paths && !plan->launches.empty();
+  for (const KindLaunch& L : plan->launches) inline_refresh = inline_refresh && L.kind == kKindLds;
+  const int nseg = inline_refresh ? 1 : fused_segments(plan->opts);
   for (int seg = 0; seg < nseg; ++seg) {
     for (const KindLaunch& L : plan->launches) {
       e = launch_cg_fused(L.kind, stored_mode(plan->opts.flags), plan->d_frames, plan->d_items,
@@ -1146,6 +1152,7 @@ extern "C" otfs_status otfs_plan_paths_from_pilot(otfs_plan_t* plan, const void*
   hipError_t e = launch_pilot_paths(plan->d_frames, (int)plan->frames.size(),
                                     static_cast<const float2*>(ypilot), theta, npaths, s);
   if (e != hipSuccess) return hip_fail(e, "pilot path estimation");
+  plan->device_paths = true;
   const int sd = stored_mode(plan->opts.flags);
   if (sd != kDNone &&
       (e = launch_build_d(sd, plan->d_frames, plan->d_items, (int)plan->items.size(), s)) != hipSuccess)

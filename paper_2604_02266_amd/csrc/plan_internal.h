@@ -127,6 +127,7 @@ struct otfs_plan {
   int stage_bytes = otfs::kDefaultStageBytes;   // LDS budget for staged windows, 0 = off
   int64_t wait_us = -1;   // bound of the kernels' waits (-1: the default 20 s)
   int ref_xcds = 1;       // XCDs of round-robin dispatch (block order of the refresh)
+  bool device_paths = false;   // the path tables were made on the device (from a pilot)
   int win_w_req = 0, win_rc_req = 0;   // windowed form (0: off)
   std::vector<int> winw;               // per frame: strip width of the windowed form, or 0
   // tiling (host) and schedule (chosen at bind)
