@@ -100,3 +100,73 @@ def test_lds_gather_same_bits_as_direct(otfs, case):
         assert nm <= NMSE_TOL, nm
         o += f.E
     say(f"case {case}: bit-identical to the direct gathers; worst NMSE vs oracle {worst:.2e}")
+
+
+@pytest.mark.parametrize("cover", [False, True])
+def test_lds_gather_device_paths_with_refresh(otfs, cover):
+    """Path tables made on the device from a pilot (Eqs. heff_hadamard, heff_thres) with the
+    FP64 refresh every 3 iterations.  With placeholder paths whose ranges cover the estimated
+    ones the windows fit and those frames refresh inside the fused launch: the same bits as
+    the direct gathers.  With all-zero placeholders the estimated ranges outgrow the planned
+    windows, so the gathers read memory one element per lane (their partial sums then add
+    in another order than the direct kind's pairs) and the frames refresh in the refresh
+    launches.  Either way every frame finishes its fixed iteration count and the oracle's
+    solve with the device's path table agrees (NMSE <= 1e-5)."""
+    import torch
+    M, N, P, cap, theta = 256, 32, 6, 8, 0.08
+    rng = np.random.default_rng(9300 + int(cover))
+    frames = _frames(rng, M, N, P, (0, 12), (-4, 4), 4)
+    for f in frames:   # gains well above the threshold
+        f.h = 0.5 * np.exp(2j * np.pi * rng.random(P))
+    ops, ys = _received(rng, frames)
+    yp = []
+    for f, op in zip(frames, ops):
+        w = 1e-3 * (rng.standard_normal(f.E) + 1j * rng.standard_normal(f.E))
+        yp.append((op.apply(O.pilot_frame(M, N)) + w).astype(np.complex64))
+    if cover:
+        tau_ph = [0, 12] + [0] * (cap - 2)
+        nu_ph = [-4, 4] + [0] * (cap - 2)
+    else:
+        tau_ph, nu_ph = [0] * cap, [0] * cap
+    ph = [SpecLike(M, N, tau_ph, nu_ph, [0.1] * cap, lam=f.lam, qam=f.qam) for f in frames]
+    y = to_dev(np.concatenate(ys))
+    ypd = to_dev(np.concatenate(yp))
+    say("lds gather, device paths, cover", cover)
+    res = {}
+    for name, fl in (("direct", otfs.SPLIT_DIRECTION), ("lds", otfs.LDS_GATHER)):
+        plan = otfs.Plan(ph, max_iters=20, rel_tol=0.0, refresh_every=3, flags=fl,
+                         tile_elems=2048, tune=False)
+        n = plan.paths_from_pilot(ypd, theta).cpu().numpy()
+        assert np.all(n == P), n
+        st = plan.new_stats()
+        sym = torch.zeros(y.numel(), dtype=torch.uint8, device="cuda")
+        x = plan.lmmse_cg(y, sym=sym, stats=st)
+        torch.cuda.synchronize()
+        paths = [plan.get_paths(i) for i in range(len(frames))]
+        res[name] = (x.cpu().numpy(), sym.cpu().numpy(), otfs.stats_numpy(st), paths)
+        del plan
+    xd, sd, std, pd = res["direct"]
+    xl, sl, stl, pl = res["lds"]
+    for a, b in zip(pd, pl):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+    if cover:
+        assert np.array_equal(xd.view(np.uint32), xl.view(np.uint32))
+        assert np.array_equal(sd, sl)
+        assert np.array_equal(std, stl)
+    else:
+        assert O.nmse(xl, xd.astype(np.complex128)) <= 1e-9
+    for st in (std, stl):
+        assert np.all(st["status"] == otfs.FRAME_CAPPED), st["status"]
+        assert np.all(st["iters"] == 20)
+    o = 0
+    worst = 0.0
+    for i, (f, yy) in enumerate(zip(frames, ys)):
+        t, v, g = pl[i]
+        op = O.TwistedConvChannel(M, N, g.astype(np.complex128), t, v)
+        xr, _, _ = O.cg_lmmse(yy.astype(np.complex128), op, f.lam, 20, 0.0)
+        nm = O.nmse(xl[o:o + f.E], xr)
+        worst = max(worst, nm)
+        assert nm <= NMSE_TOL, nm
+        o += f.E
+    say(f"device paths (cover={cover}): worst NMSE vs oracle {worst:.2e}")
