@@ -1138,13 +1138,17 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
   const void* wt = A::wtab(F);
   const __amdgpu_buffer_rsrc_t rtab = buf_rsrc(A::rtab(F), (int64_t)P * M * A::kTabBytes);
   const lptr<u64> win = (lptr<u64>)lds_gen;
+  // A wave's window chunks are kWaves * 128 elements apart: its lane's (row, column) in the
+  // window advances by (dr, dc) from one chunk to the next, so the walk needs no division.
+  const int dr = (kWaves << 7) / WC, dc = (kWaves << 7) - dr * WC;   // dc < WC
+  const int e_lane = (wave << 7) + 2 * lane;
+  const int r_lane = e_lane / WC, c_lane = e_lane - r_lane * WC;
   for (int k0 = 0; k0 < M; k0 += KC) {
     const int col0 = full_cols ? 0 : ((ADJ ? k0 + F.tau_lo : k0 - F.tau_hi) & ~1);
     __syncthreads();   // the previous strip's window is no longer read
+    int e = e_lane, r = r_lane, cc = c_lane;
     for (int c = wave; c < nchunk; c += kWaves) {
-      const int e = (c << 7) + 2 * lane;
       if (e < total) {
-        const int r = e / WC, cc = e - r * WC;
         int sr = row0 + r;
         sr += sr < 0 ? N : 0;
         sr -= sr >= N ? N : 0;
@@ -1153,6 +1157,13 @@ __device__ __forceinline__ void lds_apply_pairs(const FrameDev& F, int lb, int l
         sc -= sc >= M ? M : 0;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(src.r, (lptr<void>)(win + (c << 7)), 16,
                                                  (uint32_t)(sr * M + sc) * 8u, 0, 0, 0);
+      }
+      e += kWaves << 7;
+      r += dr;
+      cc += dc;
+      if (cc >= WC) {
+        cc -= WC;
+        ++r;
       }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
