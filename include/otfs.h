@@ -225,7 +225,10 @@ otfs_status otfs_apply_HH(const otfs_plan_t* plan, const void* y_dev, void* x_de
  * frames are split into row tiles, the workgroups of one frame meet at per-frame barriers,
  * and each frame stops on its own.  With refresh_every = k the loop is cut after every k-th
  * iteration into segments, and two launches between segments form the FP64 true residual
- * c = H^H (y - H x) - lam x.  The fused launches expect the GPU to themselves: a frame's
+ * c = H^H (y - H x) - lam x; frames of the windowed-pairs kind (OTFS_LDS_GATHER) whose LDS
+ * windows fit form it inside the fused launch instead, and when every frame is of that kind
+ * and the path tables are the host's, a solve is one launch.  The fused launches expect the
+ * GPU to themselves: a frame's
  * tiles must all be resident at once, and work from other streams that keeps some of them
  * waiting makes the frame report OTFS_FRAME_TIMEOUT after the wait bound.  y_dev: total_elems complex64 (bf16 pairs with OTFS_Y_BF16);
  * xhat_dev: total_elems complex64 output; sym_dev: total_elems uint8 hard decisions
@@ -331,7 +334,7 @@ otfs_status otfs_plan_get_paths(const otfs_plan_t* plan, int32_t frame, int32_t 
 otfs_status otfs_plan_set_wait_limit(otfs_plan_t* plan, int64_t wait_us);
 
 /* Duration in milliseconds of the launch sequence of the last otfs_lmmse_cg call that ran
- * with OTFS_TIME_KERNEL (its fused launches and, with the refresh, the refresh launches
+ * with OTFS_TIME_KERNEL (its fused launches and, with the refresh, any refresh launches
  * between them; waits for its end event). */
 otfs_status otfs_plan_kernel_ms(otfs_plan_t* plan, float* ms);
 
