@@ -1923,6 +1923,21 @@ __device__ __forceinline__ bool frame_windows_fit(const FrameDev& F) {
          lds_window_fits(F, 0, (F.N + F.T - 1) / F.T);
 }
 
+// A frame's state as every lane holds it: read through the vector path (other workgroups
+// write it), then taken from the first lane, so that what is derived from it (which
+// direction buffer is current, and the buffer descriptors built on that) stays in scalar
+// registers instead of every buffer access being repeated per distinct descriptor.
+__device__ __forceinline__ FrameState uniform_state(const FrameState* p) {
+  FrameState s = *p;
+  s.iter = __builtin_amdgcn_readfirstlane(s.iter);
+  s.status = __builtin_amdgcn_readfirstlane(s.status);
+  s.pbuf = __builtin_amdgcn_readfirstlane(s.pbuf);
+  s.pending = __builtin_amdgcn_readfirstlane(s.pending);
+  s.init = __builtin_amdgcn_readfirstlane(s.init);
+  s.refresh = __builtin_amdgcn_readfirstlane(s.refresh);
+  return s;
+}
+
 // GM: where the gathers read from (kGmDirect, kGmStaged, kGmLds).  FDIR: the H pass forms
 // p' = c + beta p inside its gathers (direct-fd kind).
 template <int SD, int GM, bool FDIR = false>
@@ -1934,7 +1949,7 @@ __device__ __forceinline__ void cg_item(const FrameDev& F, const WorkItem& wi, i
   // registers for more)
   constexpr int ECK = GM == kGmLds ? kElemChunkLds : kElemChunk;
   const FrameVecs V = frame_vecs(F, B);
-  FrameState s = *F.st;
+  FrameState s = uniform_state(F.st);
   if (s.status != OTFS_FRAME_RUNNING) return;
   const int M = F.M, T = F.T;
   const int lb = wi.l_begin, le = wi.l_end;
@@ -2252,7 +2267,7 @@ struct OwnCPX {      // own elements the H pass needs besides the window
 __device__ void cg_item_win(const FrameDev& F, const WorkItem& wi, int budget, const Bases& B,
                             const LaunchCtx& L, float* red, int* sflag, float2* lds) {
   const FrameVecs V = frame_vecs(F, B);
-  FrameState s = *F.st;
+  FrameState s = uniform_state(F.st);
   if (s.status != OTFS_FRAME_RUNNING) return;
   const int M = F.M, N = F.N, T = F.T, W = F.win_w;
   const int k0 = wi.k_begin;
@@ -2433,7 +2448,7 @@ __device__ void cg_item_win(const FrameDev& F, const WorkItem& wi, int budget, c
 __device__ void cg_item_resident(const FrameDev& F, int budget, const Bases& B, float* red,
                                  float2* lds) {
   const FrameVecs V = frame_vecs(F, B);
-  FrameState s = *F.st;
+  FrameState s = uniform_state(F.st);
   if (s.status != OTFS_FRAME_RUNNING) return;
   const int N = F.N;
   const int E = F.M * F.N;
